@@ -1,0 +1,169 @@
+/*
+ * sim.h -- C ABI of the MI355X event simulator (libevsim.so).
+ *
+ * The library turns camera frames into the events an event camera would have produced between
+ * them, following Ziegler et al., "Real-time event simulation with frame-based cameras"
+ * (arXiv 2209.04634):
+ *   - inputs are consecutive grayscale camera frames taken at t_{i-1} and t_i (Sec. III-A,
+ *     Fig. 1 caption), plus, for the interpolating methods, a dense optical-flow field per frame
+ *     interval (Sec. III-A, III-B; here supplied by the caller instead of estimated);
+ *   - parameters are the contrast thresholds C_pos / C_neg and the number of interpolated frames
+ *     (Sec. IV-A, Table I);
+ *   - outputs are events <x, y, t, p> (Sec. III-A, Fig. 1 caption).
+ * Three methods: BASIC (difference of consecutive frames, Sec. III and IV-A reference bar),
+ * DENSE (dense flow interpolation, Sec. III-A) and SPARSE (interpolation only at pixels whose
+ * frame-to-frame change reaches a threshold, Sec. III-B).
+ *
+ * Arithmetic (identical on every entry point; fp32, one rounding per operation, no contraction):
+ *   L = T[I] with T the 256-entry transform table (LOG: ln(v/255 + eps) rounded once from double;
+ *   LINEAR: v).  Per pixel and interval, with S = n_interp + 1 sub-intervals (BASIC: S = 1),
+ *   samples V_0 = L0, V_S = L1 and, for 0 < k < S, tau = k/S, w = 1 - tau, (u, v) = flow at the
+ *   pixel: V_k = w * bil(L0, x - tau u, y - tau v) + tau * bil(L1, x + w u, y + w v) with
+ *   clamp-to-edge bilinear sampling.  A per-pixel reference level R (device resident, initialised
+ *   from the first frame) fires a positive event while V_{k+1} - R >= C_pos (R += C_pos) and a
+ *   negative one while V_{k+1} - R <= -C_neg (R -= C_neg); the event time is
+ *   t_{i-1} + floor(((k + theta) / S) * (t_i - t_{i-1})) with theta the crossing fraction inside
+ *   the sub-interval (0 when the level was already passed at its start).  SPARSE skips pixels
+ *   with |L1 - L0| < mask_threshold entirely (no events, R unchanged).
+ *
+ * Event order: within each frame interval events are sorted by (t, y, x, p) with p = -1 before
+ * p = +1; intervals follow in push order.
+ *
+ * Packed key (sim_drain_keys): ((t - epoch) << 25) | (y << 13) | (x << 1) | (p > 0), where
+ * epoch is the timestamp of the first frame pushed (sim_epoch).
+ *
+ * Conventions for every call: the return value is SIM_OK (0) or a negative status.  No C++
+ * exception crosses the ABI.  SIM_E_INVAL, SIM_E_ORDER, SIM_E_RANGE and SIM_E_NOMEM leave the
+ * stream exactly as it was before the call, with one exception: when the device event buffer
+ * has to grow in the middle of a push and that allocation fails, part of the image has already
+ * advanced, so the push returns SIM_E_NOMEM and poisons the handle.  SIM_E_HIP poisons the
+ * handle: every later call except sim_destroy, sim_get_stats and sim_strerror returns
+ * SIM_E_POISONED.  A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef EVSIM_SIM_H
+#define EVSIM_SIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_E_INVAL (-1)     /* bad argument or configuration                                   */
+#define SIM_E_ORDER (-2)     /* frame timestamp not strictly increasing                         */
+#define SIM_E_NOMEM (-3)     /* device or host allocation failed                                */
+#define SIM_E_RANGE (-4)     /* timestamp or key field out of range (see sim_push_frames)       */
+#define SIM_E_HIP (-5)       /* HIP runtime error; the handle is now poisoned                   */
+#define SIM_E_POISONED (-6)  /* handle poisoned by an earlier SIM_E_HIP                         */
+#define SIM_E_BUSY (-7)      /* server: no slot or memory for the request (nothing changed)     */
+#define SIM_E_EMPTY (-8)     /* server: nothing to return yet                                   */
+
+enum { SIM_BASIC = 0, SIM_DENSE = 1, SIM_SPARSE = 2 };
+enum { SIM_LOG = 0, SIM_LINEAR = 1 };
+enum { SIM_MEM_HOST = 0, SIM_MEM_DEVICE = 1 };
+
+typedef struct sim_config {
+    int32_t width, height;      /* 1..4096 each (12-bit x and y fields of the packed key)          */
+    int32_t method;             /* SIM_BASIC | SIM_DENSE | SIM_SPARSE                               */
+    int32_t transform;          /* SIM_LOG (default) | SIM_LINEAR (the paper's linear difference)  */
+    float c_pos, c_neg;         /* threshold magnitudes > 0; the paper writes C_neg as negative     */
+    float log_eps;              /* SIM_LOG offset inside the logarithm, > 0 (default 1e-3)          */
+    int32_t n_interp;           /* N >= 0 interpolated frames per interval, S = N + 1 (<= 255);     */
+                                /* ignored by SIM_BASIC (S = 1)                                     */
+    float mask_threshold;       /* SIM_SPARSE selection m: < 0 -> min(c_pos, c_neg); 0 -> all px   */
+    uint64_t event_capacity;    /* initial device event buffer (events); grows on demand; 0 = auto */
+    void* hip_stream;           /* hipStream_t to order all work on; NULL -> library-owned stream   */
+} sim_config;
+
+/* One event as drained to the host (16 bytes). */
+typedef struct sim_event {
+    int64_t t_us;               /* absolute timestamp, microseconds                                 */
+    uint16_t x, y;              /* pixel                                                            */
+    int8_t p;                   /* +1 or -1                                                         */
+    uint8_t pad[3];
+} sim_event;
+
+typedef struct sim_stats {
+    uint64_t frames;            /* frames pushed (including the first)                              */
+    uint64_t intervals;         /* frame intervals simulated                                        */
+    uint64_t events;            /* events produced                                                  */
+    uint64_t selected;          /* SIM_SPARSE: pixel-intervals selected for interpolation           */
+    uint64_t retries;           /* event-buffer growths that re-ran part of a window                */
+    uint64_t event_capacity;    /* current device event buffer (events)                             */
+} sim_stats;
+
+typedef struct sim_stream sim_stream;
+
+/* Fills cfg with defaults: 0x0 image, SIM_BASIC, SIM_LOG, C = 0.2, eps = 1e-3, N = 10, m = -1,
+ * automatic capacity, library-owned stream.  Width and height must be set before sim_create. */
+void sim_config_init(sim_config* cfg);
+
+/* Creates a stream (device state: reference levels, previous frame, table, event buffers).
+ * cfg is copied.  On success *out owns the handle until sim_destroy.  Errors: SIM_E_INVAL
+ * (dimension out of 1..4096, method/transform unknown, thresholds not > 0 or so small that
+ * R + C == R for some reachable R, n_interp outside 0..255, log_eps not > 0), SIM_E_NOMEM. */
+int sim_create(const sim_config* cfg, sim_stream** out);
+
+/* Releases every resource of the handle after the work queued on its stream completes. */
+int sim_destroy(sim_stream* s);
+
+/* Forgets all frames and pending events; the next push is a first frame again. */
+int sim_reset(sim_stream* s);
+
+/* Pushes one frame taken at t_us (frame interval semantics of Sec. III-A: the pair of frames
+ * (previous, this one) defines one interval).  frame: uint8 [height][width], row-major, no
+ * padding.  flow: float32 [height][width][2] (dx, dy in pixels per interval, motion from the
+ * previous frame to this one); required for SIM_DENSE / SIM_SPARSE except on the first frame,
+ * ignored otherwise (may be NULL).  mem_kind tells whether frame and flow are host or device
+ * pointers; host inputs are copied before the call returns, device inputs must stay valid until
+ * the work queued on the stream has completed.  The first push only initialises the reference
+ * levels (no events).  n_new_events (may be NULL) receives the number of events this push
+ * produced.  Errors: SIM_E_INVAL (NULL frame, missing flow), SIM_E_ORDER (t_us not greater than
+ * the previous frame's), SIM_E_RANGE (t_us - epoch >= 2^39 or interval longer than 2^31 us). */
+int sim_push_frame(sim_stream* s, const uint8_t* frame, const float* flow, int64_t t_us,
+                   int32_t mem_kind, uint64_t* n_new_events);
+
+/* Pushes n_frames frames at once: the same result as n_frames calls of sim_push_frame, computed
+ * by one persistent launch that carries the reference levels across the frame intervals.
+ * frames: uint8 [n_frames][height][width]; t_us: host array of n_frames timestamps; flows:
+ * float32 [n_intervals][height][width][2] with n_intervals = n_frames - 1 when the stream has no
+ * frame yet (the first frame only initialises) and n_frames otherwise; flows[j] belongs to the
+ * j-th interval produced by this call.  Same memory, error and ordering rules as
+ * sim_push_frame; every timestamp is validated before any work is queued. */
+int sim_push_frames(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
+                    const int64_t* t_us, int32_t mem_kind, uint64_t* n_new_events);
+
+/* Number of events produced and not yet drained. */
+int sim_pending_events(sim_stream* s, uint64_t* n);
+
+/* Copies up to max_events of the oldest pending events, in canonical order, into dst (host
+ * memory owned by the caller) and removes them from the stream.  *n_written receives the count.
+ * Partial drains are allowed; the next drain continues where this one stopped. */
+int sim_drain_events(sim_stream* s, sim_event* dst, uint64_t max_events, uint64_t* n_written);
+
+/* As sim_drain_events, but writes packed 64-bit keys (format above) to dst, which is host
+ * memory (SIM_MEM_HOST) or device memory (SIM_MEM_DEVICE, copied on the stream). */
+int sim_drain_keys(sim_stream* s, uint64_t* dst, uint64_t max_events, int32_t mem_kind,
+                   uint64_t* n_written);
+
+/* Timestamp of the first frame (the epoch of packed keys).  SIM_E_INVAL before the first push. */
+int sim_epoch(sim_stream* s, int64_t* epoch);
+
+/* Copies the per-pixel reference levels, float32 [height][width], to host or device memory. */
+int sim_get_reference(sim_stream* s, float* dst, int32_t mem_kind);
+
+/* Waits until all work queued by this stream has completed. */
+int sim_sync(sim_stream* s);
+
+/* Counters since creation (or the last sim_reset). */
+int sim_get_stats(sim_stream* s, sim_stats* out);
+
+/* Static text for a status code. */
+const char* sim_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVSIM_SIM_H */

@@ -1,0 +1,564 @@
+// Host runtime of the event simulator: the C ABI declared in include/sim.h.
+//
+// Per stream the device holds the 256-entry transform table, the per-pixel reference levels
+// (updated in place), two previous-frame buffers (ping-pong), an unsorted event arena with its
+// sort scratch, and a FIFO of sorted packed keys awaiting drain.  A push of K frames is one
+// simulation launch over all tiles, a read of four counters, an optional re-run of the tiles that
+// ran out of arena space (after growing it), and one sort whose last pass appends to the FIFO.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/sim.h"
+#include "evsim_internal.h"
+
+using namespace evsim;
+
+namespace {
+
+constexpr int kMaxWindow = 256;            // frame intervals per simulation launch (8-bit index)
+constexpr uint64_t kMaxInterval = 1ull << 31;
+constexpr int64_t kMaxEpochSpan = (int64_t)1 << 39;
+
+int bits_for(uint64_t v) {  // number of bits to represent values 0..v (at least 1)
+    int b = 1;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+template <class T>
+hipError_t dev_alloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    return hipMalloc((void**)p, n * sizeof(T));
+}
+
+}  // namespace
+
+struct sim_stream {
+    sim_config cfg;
+    int S = 1;
+    float m = 0.0f;
+    float lut_host[256];
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+
+    int64_t npix = 0;
+    int ntiles = 0;
+    float* d_lut = nullptr;
+    float* d_lref = nullptr;
+    uint8_t* d_prev[2] = {nullptr, nullptr};
+    int cur = 0;
+
+    bool started = false;
+    int64_t epoch = 0, t_prev = 0;
+
+    // window scratch
+    uint64_t* d_arena = nullptr;
+    uint64_t arena_cap = 0;
+    uint64_t* d_alt = nullptr;
+    uint64_t alt_cap = 0;
+    uint32_t* d_hist = nullptr;
+    size_t hist_cap = 0;
+    uint32_t* d_totals = nullptr;
+    unsigned long long* d_counters = nullptr;
+    unsigned long long* h_counters = nullptr;   // pinned
+    unsigned int* d_icount = nullptr;
+    float* d_delta = nullptr;
+    int64_t* d_tbase = nullptr;
+    int* d_resume = nullptr;
+    float* h_delta = nullptr;                    // pinned
+    int64_t* h_tbase = nullptr;                  // pinned
+
+    // staging for host inputs
+    uint8_t* d_stage_frames = nullptr;
+    size_t stage_frames_cap = 0;
+    float* d_stage_flows = nullptr;
+    size_t stage_flows_cap = 0;
+
+    // FIFO of sorted packed keys
+    uint64_t* d_fifo = nullptr;
+    uint64_t fifo_cap = 0, fifo_head = 0, fifo_tail = 0;
+
+    sim_stats stats;
+};
+
+namespace {
+
+int hip_fail(sim_stream* s) {
+    s->poisoned = true;
+    return SIM_E_HIP;
+}
+
+#define HIP_TRY(s, expr)                               \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(s);      \
+    } while (0)
+
+void free_stream(sim_stream* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    dfree(s->d_lut);
+    dfree(s->d_lref);
+    dfree(s->d_prev[0]);
+    dfree(s->d_prev[1]);
+    dfree(s->d_arena);
+    dfree(s->d_alt);
+    dfree(s->d_hist);
+    dfree(s->d_totals);
+    dfree(s->d_counters);
+    dfree(s->d_icount);
+    dfree(s->d_delta);
+    dfree(s->d_tbase);
+    dfree(s->d_resume);
+    dfree(s->d_stage_frames);
+    dfree(s->d_stage_flows);
+    dfree(s->d_fifo);
+    if (s->h_counters) (void)hipHostFree(s->h_counters);
+    if (s->h_delta) (void)hipHostFree(s->h_delta);
+    if (s->h_tbase) (void)hipHostFree(s->h_tbase);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+// Grows a device buffer to at least n elements, keeping the first `keep` elements.
+template <class T>
+int grow(sim_stream* s, T** buf, uint64_t* cap, uint64_t n, uint64_t keep) {
+    if (n <= *cap) return SIM_OK;
+    T* nb = nullptr;
+    if (hipMalloc((void**)&nb, n * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIM_E_NOMEM;
+    }
+    if (keep) {
+        if (hipMemcpyAsync(nb, *buf, keep * sizeof(T), hipMemcpyDeviceToDevice, s->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(s->stream) != hipSuccess) {
+            dfree(nb);
+            return hip_fail(s);
+        }
+    } else if (*buf) {
+        if (hipStreamSynchronize(s->stream) != hipSuccess) {
+            dfree(nb);
+            return hip_fail(s);
+        }
+    }
+    dfree(*buf);
+    *buf = nb;
+    *cap = n;
+    return SIM_OK;
+}
+
+int ensure_sort_scratch(sim_stream* s, uint64_t n) {
+    int rc = grow(s, &s->d_alt, &s->alt_cap, n, 0);
+    if (rc) return rc;
+    uint64_t hc = s->hist_cap;
+    rc = grow(s, &s->d_hist, &hc, sort_hist_entries(n), 0);
+    s->hist_cap = (size_t)hc;
+    return rc;
+}
+
+void build_lut(sim_stream* s) {
+    for (int v = 0; v < 256; ++v) {
+        if (s->cfg.transform == SIM_LOG)
+            s->lut_host[v] = (float)log((double)v / 255.0 + (double)s->cfg.log_eps);
+        else
+            s->lut_host[v] = (float)v;
+    }
+}
+
+int check_mem_kind(int32_t k) { return (k == SIM_MEM_HOST || k == SIM_MEM_DEVICE) ? SIM_OK : SIM_E_INVAL; }
+
+// Runs one window of K intervals whose frames/flows are already on the device.
+int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
+               int K, uint64_t* n_new) {
+    const int W = s->cfg.width, H = s->cfg.height;
+    uint64_t max_delta = 0;
+    for (int i = 0; i < K; ++i) {
+        const int64_t t0 = i == 0 ? s->t_prev : t_us[i - 1];
+        const int64_t d = t_us[i] - t0;
+        s->h_delta[i] = (float)d;
+        s->h_tbase[i] = t0 - s->epoch;
+        const uint64_t dr = (uint64_t)ceil((double)s->h_delta[i]);
+        max_delta = std::max(max_delta, dr);
+    }
+    KeyLayout lay;
+    lay.xb = bits_for((uint64_t)(W - 1));
+    lay.yb = bits_for((uint64_t)(H - 1));
+    lay.tb = bits_for(max_delta);
+    lay.ib = K > 1 ? bits_for((uint64_t)(K - 1)) : 0;
+    const int nbits = lay.total_bits() + 1;   // + sentinel bit
+    if (nbits > 64) return SIM_E_RANGE;
+
+    HIP_TRY(s, hipMemcpyAsync(s->d_delta, s->h_delta, K * sizeof(float), hipMemcpyHostToDevice,
+                              s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->d_tbase, s->h_tbase, K * sizeof(int64_t), hipMemcpyHostToDevice,
+                              s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->d_resume, 0, s->ntiles * sizeof(int), s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, 4 * sizeof(unsigned long long), s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->d_icount, 0, K * sizeof(unsigned int), s->stream));
+
+    SimArgs a;
+    a.prev = s->d_prev[s->cur];
+    a.frames = frames;
+    a.fstride = s->npix;
+    a.flows = flows;
+    a.flstride = 2 * s->npix;
+    a.lut = s->d_lut;
+    a.delta = s->d_delta;
+    a.lref = s->d_lref;
+    a.prev_out = s->d_prev[1 - s->cur];
+    a.counters = s->d_counters;
+    a.icount = s->d_icount;
+    a.resume = s->d_resume;
+    a.W = W;
+    a.H = H;
+    a.S = s->S;
+    a.K = K;
+    a.method = s->cfg.method;
+    a.ntiles = s->ntiles;
+    a.cpos = s->cfg.c_pos;
+    a.cneg = s->cfg.c_neg;
+    a.m = s->m;
+    a.lay = lay;
+
+    for (;;) {
+        a.arena = s->d_arena;
+        a.cap = s->arena_cap;
+        HIP_TRY(s, launch_simulate(a, s->stream));
+        HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 4 * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        if (s->h_counters[2] == 0) break;
+        // Some tiles ran out of arena space: grow it (keeping what was written, including the
+        // sentinels of abandoned reservations) and re-run only the unfinished tiles.
+        const uint64_t old = s->arena_cap;
+        const uint64_t want = std::max<uint64_t>(2 * old, s->h_counters[0] + s->h_counters[0] / 2);
+        int rc = grow(s, &s->d_arena, &s->arena_cap, want, old);
+        if (rc) {
+            // Finished tiles have already advanced their reference levels: the stream can no
+            // longer be rolled back, so an allocation failure here poisons the handle.
+            s->poisoned = true;
+            return rc;
+        }
+        s->h_counters[0] = old;
+        s->h_counters[2] = 0;
+        HIP_TRY(s, hipMemcpyAsync(s->d_counters, s->h_counters, 3 * sizeof(unsigned long long),
+                                  hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        s->stats.retries++;
+    }
+    const uint64_t n_total = std::min<uint64_t>(s->h_counters[0], s->arena_cap);
+    const uint64_t n_valid = s->h_counters[1];
+    s->stats.selected += s->h_counters[3];
+
+    if (n_valid > 0) {
+        int rc = ensure_sort_scratch(s, n_total);
+        if (rc) return rc;
+        rc = grow(s, &s->d_fifo, &s->fifo_cap, s->fifo_tail + n_valid, s->fifo_tail);
+        if (rc) return rc;
+        ConvertArgs cv;
+        cv.enabled = 1;
+        cv.n_valid = n_valid;
+        cv.tbase = s->d_tbase;
+        cv.lay = lay;
+        HIP_TRY(s, launch_sort(s->d_arena, s->d_alt, n_total, nbits, s->d_hist, s->d_totals,
+                               s->d_fifo + s->fifo_tail, cv, s->stream));
+        s->fifo_tail += n_valid;
+    }
+    s->cur = 1 - s->cur;
+    s->t_prev = t_us[K - 1];
+    s->stats.intervals += (uint64_t)K;
+    s->stats.frames += (uint64_t)K;
+    s->stats.events += n_valid;
+    if (n_new) *n_new += n_valid;
+    return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sim_config_init(sim_config* cfg) {
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->method = SIM_BASIC;
+    cfg->transform = SIM_LOG;
+    cfg->c_pos = 0.2f;
+    cfg->c_neg = 0.2f;
+    cfg->log_eps = 1e-3f;
+    cfg->n_interp = 10;
+    cfg->mask_threshold = -1.0f;
+    cfg->event_capacity = 0;
+    cfg->hip_stream = nullptr;
+}
+
+const char* sim_strerror(int status) {
+    switch (status) {
+        case SIM_OK: return "ok";
+        case SIM_E_INVAL: return "invalid argument";
+        case SIM_E_ORDER: return "frame timestamps must strictly increase";
+        case SIM_E_NOMEM: return "out of memory";
+        case SIM_E_RANGE: return "value out of range";
+        case SIM_E_HIP: return "HIP runtime error (handle poisoned)";
+        case SIM_E_POISONED: return "handle poisoned by an earlier HIP error";
+        case SIM_E_BUSY: return "no capacity for the request";
+        case SIM_E_EMPTY: return "nothing available";
+        default: return "unknown status";
+    }
+}
+
+int sim_create(const sim_config* cfg, sim_stream** out) {
+    if (!cfg || !out) return SIM_E_INVAL;
+    *out = nullptr;
+    if (cfg->width < 1 || cfg->height < 1 || cfg->width > 4096 || cfg->height > 4096)
+        return SIM_E_INVAL;
+    if (cfg->method < SIM_BASIC || cfg->method > SIM_SPARSE) return SIM_E_INVAL;
+    if (cfg->transform != SIM_LOG && cfg->transform != SIM_LINEAR) return SIM_E_INVAL;
+    if (!(cfg->c_pos > 0.0f) || !(cfg->c_neg > 0.0f) || !isfinite(cfg->c_pos) ||
+        !isfinite(cfg->c_neg))
+        return SIM_E_INVAL;
+    if (cfg->transform == SIM_LOG && !(cfg->log_eps > 0.0f && isfinite(cfg->log_eps)))
+        return SIM_E_INVAL;
+    if (cfg->n_interp < 0 || cfg->n_interp > 255) return SIM_E_INVAL;
+    if (isnan(cfg->mask_threshold)) return SIM_E_INVAL;
+
+    sim_stream* s = new (std::nothrow) sim_stream();
+    if (!s) return SIM_E_NOMEM;
+    s->cfg = *cfg;
+    build_lut(s);
+    // The crossing loop advances R by C each step; C must be large enough that R + C != R for
+    // every level the loop can reach (|R| <= max|T| + C).
+    float maxabs = 0.0f;
+    for (int v = 0; v < 256; ++v) maxabs = std::max(maxabs, fabsf(s->lut_host[v]));
+    const float cmin = (maxabs + 1.0f) * ldexpf(1.0f, -20);
+    if (cfg->c_pos < cmin || cfg->c_neg < cmin) {
+        delete s;
+        return SIM_E_INVAL;
+    }
+    s->S = cfg->method == SIM_BASIC ? 1 : cfg->n_interp + 1;
+    s->m = cfg->mask_threshold < 0.0f ? std::min(cfg->c_pos, cfg->c_neg) : cfg->mask_threshold;
+    s->npix = (int64_t)cfg->width * cfg->height;
+    s->ntiles = (int)((s->npix + kSimThreads - 1) / kSimThreads);
+    memset(&s->stats, 0, sizeof(s->stats));
+
+    bool ok = true;
+    if (cfg->hip_stream) {
+        s->stream = (hipStream_t)cfg->hip_stream;
+    } else {
+        ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+        s->own_stream = ok;
+    }
+    uint64_t cap0 = cfg->event_capacity ? cfg->event_capacity : (uint64_t)s->npix;
+    ok = ok && dev_alloc(&s->d_lut, 256) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_lref, s->npix) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_prev[0], s->npix) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_prev[1], s->npix) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_arena, cap0) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_totals, 256) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_counters, 4) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_icount, kMaxWindow) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_delta, kMaxWindow) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_tbase, kMaxWindow) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_resume, s->ntiles) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->h_counters, 4 * sizeof(unsigned long long), 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->h_delta, kMaxWindow * sizeof(float), 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->h_tbase, kMaxWindow * sizeof(int64_t), 0) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_stream(s);
+        return SIM_E_NOMEM;
+    }
+    s->arena_cap = cap0;
+    if (hipMemcpyAsync(s->d_lut, s->lut_host, sizeof(s->lut_host), hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+        free_stream(s);
+        return SIM_E_HIP;
+    }
+    s->stats.event_capacity = cap0;
+    *out = s;
+    return SIM_OK;
+}
+
+int sim_destroy(sim_stream* s) {
+    if (!s) return SIM_E_INVAL;
+    free_stream(s);
+    return SIM_OK;
+}
+
+int sim_reset(sim_stream* s) {
+    if (!s) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->started = false;
+    s->fifo_head = s->fifo_tail = 0;
+    const uint64_t cap = s->arena_cap;
+    memset(&s->stats, 0, sizeof(s->stats));
+    s->stats.event_capacity = cap;
+    return SIM_OK;
+}
+
+int sim_push_frames(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
+                    const int64_t* t_us, int32_t mem_kind, uint64_t* n_new_events) {
+    if (!s) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    if (n_new_events) *n_new_events = 0;
+    if (n_frames < 1 || !frames || !t_us || check_mem_kind(mem_kind)) return SIM_E_INVAL;
+    const int first = s->started ? 0 : 1;     // frames consumed by initialisation
+    const int n_int = n_frames - first;
+    if (n_int > 0 && s->S > 1 && !flows) return SIM_E_INVAL;
+    // validate every timestamp before queueing any work
+    int64_t prev = s->started ? s->t_prev : t_us[0];
+    const int64_t epoch = s->started ? s->epoch : t_us[0];
+    for (int j = first; j < n_frames; ++j) {
+        if (t_us[j] <= prev) return SIM_E_ORDER;
+        if ((uint64_t)(t_us[j] - prev) >= kMaxInterval) return SIM_E_RANGE;
+        if (t_us[j] - epoch >= kMaxEpochSpan) return SIM_E_RANGE;
+        prev = t_us[j];
+    }
+    const size_t fbytes = (size_t)s->npix;
+    const size_t flfloats = (size_t)s->npix * 2;
+
+    // stage host inputs on the device
+    const uint8_t* dframes = frames;
+    const float* dflows = flows;
+    if (mem_kind == SIM_MEM_HOST) {
+        uint64_t cap = s->stage_frames_cap;
+        int rc = grow(s, &s->d_stage_frames, &cap, (uint64_t)n_frames * fbytes, 0);
+        s->stage_frames_cap = (size_t)cap;
+        if (rc) return rc;
+        HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, frames, (size_t)n_frames * fbytes,
+                                  hipMemcpyHostToDevice, s->stream));
+        dframes = s->d_stage_frames;
+        if (n_int > 0 && s->S > 1) {
+            cap = s->stage_flows_cap;
+            rc = grow(s, &s->d_stage_flows, &cap, (uint64_t)n_int * flfloats, 0);
+            s->stage_flows_cap = (size_t)cap;
+            if (rc) return rc;
+            HIP_TRY(s, hipMemcpyAsync(s->d_stage_flows, flows, (size_t)n_int * flfloats * 4,
+                                      hipMemcpyHostToDevice, s->stream));
+            dflows = s->d_stage_flows;
+        }
+    }
+
+    if (!s->started) {
+        HIP_TRY(s, launch_init(dframes, s->d_lut, s->d_lref, s->d_prev[s->cur], s->npix,
+                               s->stream));
+        s->started = true;
+        s->epoch = t_us[0];
+        s->t_prev = t_us[0];
+        s->stats.frames += 1;
+    }
+    uint64_t total = 0;
+    for (int j = 0; j < n_int; j += kMaxWindow) {
+        const int K = std::min(kMaxWindow, n_int - j);
+        const uint8_t* wf = dframes + (size_t)(first + j) * fbytes;
+        const float* wfl = (s->S > 1) ? dflows + (size_t)j * flfloats : nullptr;
+        uint64_t nn = 0;
+        int rc = run_window(s, wf, wfl, t_us + first + j, K, &nn);
+        if (rc) return rc;
+        total += nn;
+    }
+    s->stats.event_capacity = s->arena_cap;
+    if (n_new_events) *n_new_events = total;
+    return SIM_OK;
+}
+
+int sim_push_frame(sim_stream* s, const uint8_t* frame, const float* flow, int64_t t_us,
+                   int32_t mem_kind, uint64_t* n_new_events) {
+    return sim_push_frames(s, 1, frame, flow, &t_us, mem_kind, n_new_events);
+}
+
+int sim_pending_events(sim_stream* s, uint64_t* n) {
+    if (!s || !n) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    *n = s->fifo_tail - s->fifo_head;
+    return SIM_OK;
+}
+
+int sim_drain_keys(sim_stream* s, uint64_t* dst, uint64_t max_events, int32_t mem_kind,
+                   uint64_t* n_written) {
+    if (!s || (!dst && max_events) || check_mem_kind(mem_kind)) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    const uint64_t n = std::min(max_events, s->fifo_tail - s->fifo_head);
+    if (n) {
+        HIP_TRY(s, hipMemcpyAsync(dst, s->d_fifo + s->fifo_head, n * sizeof(uint64_t),
+                                  mem_kind == SIM_MEM_HOST ? hipMemcpyDeviceToHost
+                                                           : hipMemcpyDeviceToDevice,
+                                  s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+    }
+    s->fifo_head += n;
+    if (s->fifo_head == s->fifo_tail) s->fifo_head = s->fifo_tail = 0;
+    if (n_written) *n_written = n;
+    return SIM_OK;
+}
+
+int sim_drain_events(sim_stream* s, sim_event* dst, uint64_t max_events, uint64_t* n_written) {
+    if (!s || (!dst && max_events)) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    const uint64_t n = std::min(max_events, s->fifo_tail - s->fifo_head);
+    std::vector<uint64_t> keys;
+    try {
+        keys.resize(n);
+    } catch (...) {
+        return SIM_E_NOMEM;
+    }
+    uint64_t got = 0;
+    int rc = sim_drain_keys(s, keys.data(), n, SIM_MEM_HOST, &got);
+    if (rc) return rc;
+    for (uint64_t j = 0; j < got; ++j) {
+        const uint64_t k = keys[j];
+        sim_event& e = dst[j];
+        e.t_us = s->epoch + (int64_t)(k >> 25);
+        e.y = (uint16_t)((k >> 13) & 0xFFF);
+        e.x = (uint16_t)((k >> 1) & 0xFFF);
+        e.p = (k & 1) ? 1 : -1;
+        e.pad[0] = e.pad[1] = e.pad[2] = 0;
+    }
+    if (n_written) *n_written = got;
+    return SIM_OK;
+}
+
+int sim_epoch(sim_stream* s, int64_t* epoch) {
+    if (!s || !epoch || !s->started) return SIM_E_INVAL;
+    *epoch = s->epoch;
+    return SIM_OK;
+}
+
+int sim_get_reference(sim_stream* s, float* dst, int32_t mem_kind) {
+    if (!s || !dst || check_mem_kind(mem_kind)) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    HIP_TRY(s, hipMemcpyAsync(dst, s->d_lref, (size_t)s->npix * sizeof(float),
+                              mem_kind == SIM_MEM_HOST ? hipMemcpyDeviceToHost
+                                                       : hipMemcpyDeviceToDevice,
+                              s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return SIM_OK;
+}
+
+int sim_sync(sim_stream* s) {
+    if (!s) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return SIM_OK;
+}
+
+int sim_get_stats(sim_stream* s, sim_stats* out) {
+    if (!s || !out) return SIM_E_INVAL;
+    *out = s->stats;
+    return SIM_OK;
+}
+
+}  // extern "C"

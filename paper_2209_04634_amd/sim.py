@@ -1,0 +1,277 @@
+"""ctypes binding of libevsim.so (include/sim.h): argument marshalling only.
+
+Every step of the simulation runs in the HIP library.  numpy arrays are passed as host memory,
+torch tensors on a GPU as device memory.  There is no fallback: if the library is missing the
+import fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Union
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libevsim.so")
+
+BASIC, DENSE, SPARSE = 0, 1, 2
+LOG, LINEAR = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+METHODS = {"basic": BASIC, "dense": DENSE, "sparse": SPARSE}
+TRANSFORMS = {"log": LOG, "linear": LINEAR}
+
+OK, E_INVAL, E_ORDER, E_NOMEM, E_RANGE, E_HIP, E_POISONED, E_BUSY, E_EMPTY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+
+
+class SimConfig(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("transform", ctypes.c_int32),
+                ("c_pos", ctypes.c_float), ("c_neg", ctypes.c_float),
+                ("log_eps", ctypes.c_float), ("n_interp", ctypes.c_int32),
+                ("mask_threshold", ctypes.c_float), ("event_capacity", ctypes.c_uint64),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class SimEvent(ctypes.Structure):
+    _fields_ = [("t_us", ctypes.c_int64), ("x", ctypes.c_uint16), ("y", ctypes.c_uint16),
+                ("p", ctypes.c_int8), ("pad", ctypes.c_uint8 * 3)]
+
+
+class SimStats(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_uint64), ("intervals", ctypes.c_uint64),
+                ("events", ctypes.c_uint64), ("selected", ctypes.c_uint64),
+                ("retries", ctypes.c_uint64), ("event_capacity", ctypes.c_uint64)]
+
+
+EVENT_DTYPE = np.dtype([("t", "<i8"), ("x", "<u2"), ("y", "<u2"), ("p", "i1"), ("pad", "u1", 3)])
+assert EVENT_DTYPE.itemsize == ctypes.sizeof(SimEvent) == 16
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2209_04634_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).  Loading torch
+    # first makes the library bind to that runtime, so the process has one HIP runtime and
+    # torch tensors, streams and this library share devices and memory.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    PU64 = ctypes.POINTER(ctypes.c_uint64)
+    sigs = {
+        "sim_config_init": (None, [ctypes.POINTER(SimConfig)]),
+        "sim_create": (ctypes.c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(P)]),
+        "sim_destroy": (ctypes.c_int, [P]),
+        "sim_reset": (ctypes.c_int, [P]),
+        "sim_push_frame": (ctypes.c_int, [P, P, P, I64, I32, PU64]),
+        "sim_push_frames": (ctypes.c_int, [P, I32, P, P, P, I32, PU64]),
+        "sim_pending_events": (ctypes.c_int, [P, PU64]),
+        "sim_drain_events": (ctypes.c_int, [P, P, U64, PU64]),
+        "sim_drain_keys": (ctypes.c_int, [P, P, U64, I32, PU64]),
+        "sim_epoch": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64)]),
+        "sim_get_reference": (ctypes.c_int, [P, P, I32]),
+        "sim_sync": (ctypes.c_int, [P]),
+        "sim_get_stats": (ctypes.c_int, [P, ctypes.POINTER(SimStats)]),
+        "sim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SimError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = load().sim_strerror(status).decode()
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise SimError(rc, where)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _buffer(x, dtype, shape=None):
+    """(pointer, mem_kind, keepalive) of a numpy array or a torch tensor."""
+    if x is None:
+        return None, None, None
+    if _is_torch(x):
+        import torch
+        want = {np.uint8: torch.uint8, np.float32: torch.float32, np.int64: torch.int64}[dtype]
+        if x.dtype != want:
+            raise TypeError(f"expected {want}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if shape is not None and tuple(x.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(x.shape)}")
+        kind = MEM_DEVICE if x.is_cuda else MEM_HOST
+        return ctypes.c_void_p(x.data_ptr()), kind, x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a.ctypes.data_as(ctypes.c_void_p), MEM_HOST, a
+
+
+class Stream:
+    """One simulated event camera (a sim_stream handle)."""
+
+    def __init__(self, width: int, height: int, method: Union[str, int] = "basic",
+                 transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
+                 log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
+                 event_capacity: int = 0, hip_stream=None):
+        lib = load()
+        cfg = SimConfig()
+        lib.sim_config_init(ctypes.byref(cfg))
+        cfg.width, cfg.height = int(width), int(height)
+        cfg.method = METHODS[method] if isinstance(method, str) else int(method)
+        cfg.transform = TRANSFORMS[transform] if isinstance(transform, str) else int(transform)
+        cfg.c_pos, cfg.c_neg, cfg.log_eps = float(c_pos), float(c_neg), float(log_eps)
+        cfg.n_interp, cfg.mask_threshold = int(n_interp), float(mask_threshold)
+        cfg.event_capacity = int(event_capacity)
+        if hip_stream == "torch":
+            import torch
+            hip_stream = torch.cuda.current_stream().cuda_stream
+        elif hip_stream is not None and hasattr(hip_stream, "cuda_stream"):
+            hip_stream = hip_stream.cuda_stream
+        cfg.hip_stream = ctypes.c_void_p(int(hip_stream)) if hip_stream else None
+        h = ctypes.c_void_p()
+        _check(lib.sim_create(ctypes.byref(cfg), ctypes.byref(h)), "sim_create")
+        self._h = h
+        self._lib = lib
+        self.width, self.height = int(width), int(height)
+        self.method = cfg.method
+
+    # -- frames ---------------------------------------------------------------------------
+    def push(self, frame, flow=None, t_us: int = 0) -> int:
+        """Pushes one frame (uint8 [H, W]) with its interval's flow (float32 [H, W, 2])."""
+        H, W = self.height, self.width
+        fp, fk, fa = _buffer(frame, np.uint8, (H, W))
+        lp, lk, la = _buffer(flow, np.float32, (H, W, 2))
+        if lk is not None and lk != fk:
+            raise ValueError("frame and flow must both be host or both be device memory")
+        n = ctypes.c_uint64()
+        _check(self._lib.sim_push_frame(self._h, fp, lp, int(t_us), fk, ctypes.byref(n)),
+               "sim_push_frame")
+        return n.value
+
+    def push_frames(self, frames, flows, t_us: Sequence[int]) -> int:
+        """Pushes frames uint8 [n, H, W]; flows float32 [n_intervals, H, W, 2] (see sim.h)."""
+        H, W = self.height, self.width
+        n = int(frames.shape[0])
+        fp, fk, fa = _buffer(frames, np.uint8, (n, H, W))
+        lp, lk, la = _buffer(flows, np.float32, None)
+        if lk is not None and lk != fk:
+            raise ValueError("frames and flows must both be host or both be device memory")
+        t = np.ascontiguousarray(np.asarray(t_us, dtype=np.int64))
+        if t.shape != (n,):
+            raise ValueError("need one timestamp per frame")
+        out = ctypes.c_uint64()
+        _check(self._lib.sim_push_frames(self._h, n, fp, lp, t.ctypes.data_as(ctypes.c_void_p),
+                                         fk, ctypes.byref(out)), "sim_push_frames")
+        return out.value
+
+    # -- events ---------------------------------------------------------------------------
+    def pending(self) -> int:
+        n = ctypes.c_uint64()
+        _check(self._lib.sim_pending_events(self._h, ctypes.byref(n)), "sim_pending_events")
+        return n.value
+
+    def drain_events(self, max_events: Optional[int] = None) -> np.ndarray:
+        """Oldest pending events as a structured array (t, x, y, p, pad)."""
+        n = self.pending() if max_events is None else int(max_events)
+        out = np.zeros(n, dtype=EVENT_DTYPE)
+        got = ctypes.c_uint64()
+        _check(self._lib.sim_drain_events(self._h, out.ctypes.data_as(ctypes.c_void_p), n,
+                                          ctypes.byref(got)), "sim_drain_events")
+        return out[:got.value]
+
+    def drain_keys(self, max_events: Optional[int] = None, out=None):
+        """Oldest pending events as packed uint64 keys: numpy (host) or into a torch int64
+        device tensor `out` (returns the number written)."""
+        if out is not None:
+            ptr, kind, keep = _buffer(out, np.int64, None)
+            n = int(out.numel()) if max_events is None else int(max_events)
+            got = ctypes.c_uint64()
+            _check(self._lib.sim_drain_keys(self._h, ptr, n, kind, ctypes.byref(got)),
+                   "sim_drain_keys")
+            return got.value
+        n = self.pending() if max_events is None else int(max_events)
+        arr = np.zeros(n, dtype=np.uint64)
+        got = ctypes.c_uint64()
+        _check(self._lib.sim_drain_keys(self._h, arr.ctypes.data_as(ctypes.c_void_p), n,
+                                        MEM_HOST, ctypes.byref(got)), "sim_drain_keys")
+        return arr[:got.value]
+
+    # -- state ----------------------------------------------------------------------------
+    @property
+    def epoch(self) -> int:
+        e = ctypes.c_int64()
+        _check(self._lib.sim_epoch(self._h, ctypes.byref(e)), "sim_epoch")
+        return e.value
+
+    def reference(self, out=None):
+        """Per-pixel reference levels float32 [H, W] (numpy, or into a torch device tensor)."""
+        if out is not None:
+            ptr, kind, keep = _buffer(out, np.float32, (self.height, self.width))
+            _check(self._lib.sim_get_reference(self._h, ptr, kind), "sim_get_reference")
+            return out
+        arr = np.zeros((self.height, self.width), dtype=np.float32)
+        _check(self._lib.sim_get_reference(self._h, arr.ctypes.data_as(ctypes.c_void_p),
+                                           MEM_HOST), "sim_get_reference")
+        return arr
+
+    def stats(self) -> dict:
+        st = SimStats()
+        _check(self._lib.sim_get_stats(self._h, ctypes.byref(st)), "sim_get_stats")
+        return {k: getattr(st, k) for k, _ in SimStats._fields_}
+
+    def sync(self) -> None:
+        _check(self._lib.sim_sync(self._h), "sim_sync")
+
+    def reset(self) -> None:
+        _check(self._lib.sim_reset(self._h), "sim_reset")
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.sim_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def decode_keys(keys: np.ndarray, epoch: int = 0):
+    """Unpacks packed keys into (t, x, y, p) int64 arrays."""
+    keys = np.asarray(keys).view(np.uint64) if np.asarray(keys).dtype == np.int64 else np.asarray(keys, dtype=np.uint64)
+    t = (keys >> np.uint64(25)).astype(np.int64) + epoch
+    y = ((keys >> np.uint64(13)) & np.uint64(0xFFF)).astype(np.int64)
+    x = ((keys >> np.uint64(1)) & np.uint64(0xFFF)).astype(np.int64)
+    p = np.where((keys & np.uint64(1)) == 1, 1, -1).astype(np.int64)
+    return t, x, y, p

@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path (through the C ABI) equals the CPU oracle bit for bit.
+
+Compared element by element: the full ordered packed-key sequence of every interval and the final
+per-pixel reference levels.  Integer work (counts, order, timestamps, coordinates) must match
+exactly; the fp32 arithmetic is performed in the same order with the same roundings on both sides,
+so the reference levels must match bit for bit too (tolerance zero).
+"""
+import numpy as np
+import pytest
+
+import golden_io
+from oracle.oracle import OracleSim
+from paper_2209_04634_amd import sim, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_keys(frames, flows, t, **cfg):
+    T, H, W = frames.shape
+    o = OracleSim(W, H, **cfg)
+    out = []
+    for k in range(T):
+        ev = o.push(frames[k], None if (flows is None or k == 0) else flows[k - 1], int(t[k]))
+        if k:
+            out.append(ev)
+    return (np.concatenate(out) if out else np.zeros(0, np.uint64)), o.lref()
+
+
+def hip_keys(frames, flows, t, mode="window", **cfg):
+    T, H, W = frames.shape
+    s = sim.Stream(W, H, **cfg)
+    if mode == "window":
+        s.push_frames(frames, flows if T > 1 else None, t)
+    elif mode == "single":
+        for k in range(T):
+            s.push(frames[k], None if (flows is None or k == 0) else flows[k - 1], int(t[k]))
+    elif mode == "chunks":          # first frame alone, then windows of 3 frames
+        s.push(frames[0], None, int(t[0]))
+        for a in range(1, T, 3):
+            b = min(T, a + 3)
+            s.push_frames(frames[a:b], None if flows is None else flows[a - 1:b - 1], t[a:b])
+    elif mode == "device":
+        import torch
+        torch.cuda.synchronize()
+        fr = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+        fl = None if flows is None else torch.from_numpy(np.ascontiguousarray(flows)).cuda()
+        torch.cuda.synchronize()
+        s.push_frames(fr, fl, t)
+        s.sync()
+    else:
+        raise ValueError(mode)
+    keys = s.drain_keys()
+    ref = s.reference()
+    st = s.stats()
+    s.close()
+    return keys, ref, st
+
+
+def assert_parity(frames, flows, t, modes=("window",), **cfg):
+    ok, oref = oracle_keys(frames, flows, t, **cfg)
+    for mode in modes:
+        hk, href, _ = hip_keys(frames, flows, t, mode=mode, **cfg)
+        assert hk.shape == ok.shape, (mode, hk.shape, ok.shape)
+        np.testing.assert_array_equal(hk, ok, err_msg=mode)
+        np.testing.assert_array_equal(href.view(np.uint32), oref.view(np.uint32), err_msg=mode)
+    return len(ok)
+
+
+@pytest.mark.parametrize("path", golden_io.all_fixtures(), ids=lambda p: p.rsplit("/", 1)[-1])
+def test_hand_worked_fixtures(path):
+    g = golden_io.load(path)
+    for mode in ("window", "single"):
+        keys, ref, _ = hip_keys(g.frames, g.flows, g.t_us, mode=mode, **g.cfg)
+        s_epoch = g.t_us[0]
+        t, x, y, p = sim.decode_keys(keys, s_epoch)
+        got = list(zip(t.tolist(), x.tolist(), y.tolist(), p.tolist()))
+        assert got == [e for iv in g.events for e in iv], mode
+        np.testing.assert_array_equal(ref, g.lref)
+
+
+def test_basic_240x180():
+    v = synth.blob_video(synth.basic_240x180())
+    n = assert_parity(v.frames, None, v.t_us, modes=("window", "single", "device"),
+                      method=sim.BASIC, c_pos=0.2, c_neg=0.2)
+    assert n > 1000
+
+
+def test_dense_346x260_full_sequence():
+    v = synth.blob_video(synth.dense_346x260())
+    n = assert_parity(v.frames, v.flows, v.t_us, modes=("window", "device"), method=sim.DENSE,
+                      c_pos=0.15, c_neg=0.15, n_interp=10)
+    assert n > 100000
+
+
+def test_dense_346x260_per_frame_pushes():
+    v = synth.blob_video(synth.dense_346x260(n_frames=8))
+    assert_parity(v.frames, v.flows, v.t_us, modes=("single", "chunks"), method=sim.DENSE,
+                  c_pos=0.15, c_neg=0.15, n_interp=10)
+
+
+def test_sparse_1280x720_full_sequence():
+    v = synth.blob_video(synth.sparse_1280x720())
+    n = assert_parity(v.frames, v.flows, v.t_us, modes=("window",), method=sim.SPARSE,
+                      c_pos=0.2, c_neg=0.2, n_interp=10)
+    assert n > 1000000
+
+
+@pytest.mark.parametrize("S", [1, 2, 3, 21, 32, 33, 256])
+@pytest.mark.parametrize("method", [sim.DENSE, sim.SPARSE])
+def test_subinterval_counts_ragged_image(S, method):
+    """37x23 = 851 pixels: several tiles and a ragged tail; S beyond the LDS stash too."""
+    rng = np.random.default_rng(S * 7 + method)
+    frames, flows = synth.random_frames(rng, 4, 23, 37, flow_scale=3.0)
+    t = np.array([0, 33333, 50000, 83333])
+    assert_parity(frames, flows, t, modes=("window", "single"), method=method, c_pos=0.2,
+                  c_neg=0.25, n_interp=S - 1)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (2, 129), (17, 256)])
+def test_degenerate_shapes(shape):
+    H, W = shape
+    rng = np.random.default_rng(H * 1000 + W)
+    frames, flows = synth.random_frames(rng, 3, H, W, flow_scale=2.0)
+    t = np.array([5, 1005, 3000])
+    for method in (sim.BASIC, sim.DENSE, sim.SPARSE):
+        assert_parity(frames, flows, t, method=method, n_interp=4)
+
+
+def test_linear_transform_table_i_thresholds():
+    """The paper's linear intensities with Table I's dense/sparse thresholds (2 and 10)."""
+    v = synth.blob_video(synth.dense_346x260(n_frames=5))
+    assert_parity(v.frames, v.flows, v.t_us, method=sim.DENSE, transform=sim.LINEAR, c_pos=2.0,
+                  c_neg=2.0, n_interp=10)
+    assert_parity(v.frames, v.flows, v.t_us, method=sim.SPARSE, transform=sim.LINEAR,
+                  c_pos=10.0, c_neg=10.0, n_interp=10)
+
+
+def test_max_image_size_basic():
+    rng = np.random.default_rng(4096)
+    frames = rng.integers(0, 256, (2, 4096, 4096), dtype=np.uint8)
+    n = assert_parity(frames, None, np.array([0, 33333]), method=sim.BASIC, c_pos=0.3,
+                      c_neg=0.3)
+    assert n > 10_000_000
+
+
+def test_arena_overflow_reruns_give_identical_events():
+    v = synth.blob_video(synth.dense_346x260(n_frames=6))
+    ok, oref = oracle_keys(v.frames, v.flows, v.t_us, method=sim.DENSE, c_pos=0.15,
+                           c_neg=0.15)
+    for cap in (1, 1000, 50000):
+        hk, href, st = hip_keys(v.frames, v.flows, v.t_us, method=sim.DENSE, c_pos=0.15,
+                                c_neg=0.15, event_capacity=cap)
+        np.testing.assert_array_equal(hk, ok)
+        np.testing.assert_array_equal(href, oref)
+        assert st["retries"] > 0
+
+
+def test_constant_and_static_inputs_emit_nothing():
+    H, W = 64, 300
+    const = np.full((5, H, W), 123, dtype=np.uint8)
+    flows = np.random.default_rng(0).standard_normal((4, H, W, 2)).astype(np.float32) * 5
+    for method in (sim.BASIC, sim.DENSE, sim.SPARSE):
+        keys, _, _ = hip_keys(const, flows, [0, 1, 2, 3, 4], method=method)
+        assert len(keys) == 0
+
+
+def test_non_finite_flow_clamps_to_border_like_the_oracle():
+    rng = np.random.default_rng(3)
+    frames, flows = synth.random_frames(rng, 3, 19, 41, flow_scale=4.0)
+    flows[0, 3, 5] = [np.nan, 1.0]
+    flows[0, 7, 8] = [np.inf, -np.inf]
+    flows[1, 2, 2] = [-np.inf, np.nan]
+    for method in (sim.DENSE, sim.SPARSE):
+        assert_parity(frames, flows, [0, 100, 200], method=method, n_interp=5)
+
+
+def test_partial_drains_and_event_records():
+    v = synth.blob_video(synth.basic_240x180())
+    s = sim.Stream(240, 180, method="basic")
+    s.push(v.frames[0], None, int(v.t_us[0]))
+    n = s.push(v.frames[1], None, int(v.t_us[1]))
+    ok, _ = oracle_keys(v.frames, None, v.t_us, method=sim.BASIC)
+    assert n == len(ok) == s.pending()
+    first = s.drain_events(100)
+    rest = s.drain_keys()
+    assert s.pending() == 0
+    t, x, y, p = sim.decode_keys(ok[:100], int(v.t_us[0]))
+    assert (first["t"] == t).all() and (first["x"] == x).all() and (first["y"] == y).all()
+    assert (first["p"] == p).all()
+    np.testing.assert_array_equal(rest, ok[100:])
+
+
+def test_device_drain_into_torch_tensor():
+    import torch
+    v = synth.blob_video(synth.basic_240x180())
+    s = sim.Stream(240, 180, method="basic", hip_stream="torch")
+    fr = torch.from_numpy(v.frames).cuda()
+    s.push_frames(fr, None, v.t_us)
+    out = torch.empty(s.pending(), dtype=torch.int64, device="cuda")
+    n = s.drain_keys(out=out)
+    ok, _ = oracle_keys(v.frames, None, v.t_us, method=sim.BASIC)
+    assert n == len(ok)
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint64), ok)
+
+
+def test_errors_leave_state_untouched():
+    rng = np.random.default_rng(1)
+    frames, flows = synth.random_frames(rng, 3, 20, 30)
+    s = sim.Stream(30, 20, method="dense", n_interp=3)
+    s.push(frames[0], None, 100)
+    with pytest.raises(sim.SimError) as e:
+        s.push(frames[1], flows[0], 100)
+    assert e.value.status == sim.E_ORDER
+    with pytest.raises(sim.SimError) as e:
+        s.push(frames[1], None, 200)               # dense needs a flow
+    assert e.value.status == sim.E_INVAL
+    with pytest.raises(sim.SimError) as e:
+        s.push(frames[1], flows[0], 100 + (1 << 39))
+    assert e.value.status == sim.E_RANGE
+    with pytest.raises(sim.SimError) as e:        # one bad timestamp rejects the whole batch
+        s.push_frames(frames[1:3], flows[0:2], [200, 150])
+    assert e.value.status == sim.E_ORDER
+    s.push(frames[1], flows[0], 200)
+    s.push(frames[2], flows[1], 300)
+    ok, oref = oracle_keys(frames, flows, [100, 200, 300], method=sim.DENSE, n_interp=3)
+    np.testing.assert_array_equal(s.drain_keys(), ok)
+    np.testing.assert_array_equal(s.reference(), oref)
+
+
+def test_reset_and_determinism():
+    v = synth.blob_video(synth.dense_346x260(n_frames=10))
+    s = sim.Stream(346, 260, method="dense", c_pos=0.15, c_neg=0.15)
+    runs = []
+    for _ in range(5):
+        s.reset()
+        s.push_frames(v.frames, v.flows, v.t_us)
+        runs.append(s.drain_keys())
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r, runs[0])
+    ok, _ = oracle_keys(v.frames, v.flows, v.t_us, method=sim.DENSE, c_pos=0.15, c_neg=0.15)
+    np.testing.assert_array_equal(runs[0], ok)
