@@ -91,6 +91,14 @@ typedef struct sim_stats {
     uint64_t selected;          /* SIM_SPARSE: pixel-intervals selected for interpolation           */
     uint64_t retries;           /* event-buffer growths that re-ran part of a window                */
     uint64_t event_capacity;    /* current device event buffer (events)                             */
+    /* Filled only while kernel timing is on (sim_set_kernel_timing): HIP-event durations on the  */
+    /* stream of the launches, summed over launches.                                               */
+    uint64_t select_launches;   /* selection passes (SIM_SPARSE) or frame saves (others), 1/window */
+    double select_ms;           /* their summed duration                                            */
+    uint64_t simulate_launches; /* per-pixel chain kernel launches (one per window, plus re-runs)   */
+    double simulate_ms;         /* their summed duration                                            */
+    uint64_t sort_launches;     /* ordering passes (each: histogram, scan, scatter kernels)         */
+    double sort_ms;             /* their summed duration                                            */
 } sim_stats;
 
 typedef struct sim_stream sim_stream;
@@ -158,6 +166,12 @@ int sim_sync(sim_stream* s);
 
 /* Counters since creation (or the last sim_reset). */
 int sim_get_stats(sim_stream* s, sim_stats* out);
+
+/* Turns per-kernel timing on (enable != 0) or off.  While on, every simulation launch and every
+ * ordering sort is bracketed by HIP events recorded on the stream's own queue, and each push
+ * waits for its sort to finish before returning so the durations can be read.  The durations
+ * accumulate in sim_stats until sim_reset. */
+int sim_set_kernel_timing(sim_stream* s, int32_t enable);
 
 /* Static text for a status code. */
 const char* sim_strerror(int status);

@@ -13,6 +13,15 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // keys per sort block
 constexpr uint64_t kSentinel = ~0ull;
+constexpr int kMaskWords = 4;        // selected-interval bitmask words per pixel
+constexpr int kMaxWindow = 32 * kMaskWords;   // frame intervals per launch
+// Device-scope atomics on one address serialise (about 12 ns each on MI355X), so every counter
+// that many waves hit is striped: each stripe lives on its own 256-byte line.
+constexpr int kCounterStride = 32;   // u64 / u32 elements between stripe counters
+constexpr int kArenaStripes = 256;   // event sub-arenas, one reservation counter each
+constexpr int kActStripes = 8;       // active-pixel sub-lists (one per group of select blocks)
+constexpr int kStatStripes = 64;     // statistics counters
+constexpr int kSelectPx = 1024;      // pixels per selection block (4 per thread)
 
 enum Method { kBasic = 0, kDense = 1, kSparse = 2 };
 
@@ -26,23 +35,45 @@ struct KeyLayout {
     __host__ __device__ int total_bits() const { return ib + tb + xb + yb + 1; }
 };
 
-struct SimArgs {
+// Selection pass (sparse method): streams every frame of the window once, writes the per-pixel
+// bitmask of selected intervals, compacts the pixels selected at least once into an active list.
+struct SelectArgs {
     const uint8_t* prev;        // frame before the window, uint8 [H][W]
     const uint8_t* frames;      // window frames; frame j at frames + j * fstride
     int64_t fstride;
+    const float* lut;           // 256-entry transform table
+    uint8_t* prev_out;          // receives the window's last frame
+    uint32_t* mask;             // [kMaskWords][npix] selected-interval bits
+    uint32_t* act_px;           // kActStripes sub-lists of act_cap slots each
+    int* resume;                // per slot (same indexing as act_px): set to 0 here
+    unsigned int* n_active;     // kActStripes counters (stride kCounterStride)
+    unsigned long long* stats;  // kStatStripes counters: += selected pixel-intervals
+    int npix, K, act_cap;
+    float m;
+};
+
+// Chain pass: one lane per active pixel (sparse) or per pixel (dense, basic) walks its selected
+// intervals in order, carrying the reference level in a register.
+struct ChainArgs {
+    const uint8_t* prev;
+    const uint8_t* frames;
+    int64_t fstride;
     const float* flows;         // flow of interval j at flows + j * flstride (null for basic)
     int64_t flstride;
-    const float* lut;           // 256-entry transform table
+    const float* lut;
     const float* delta;         // per interval: (float)(t_j - t_{j-1})
     float* lref;                // per-pixel reference level, updated in place
-    uint8_t* prev_out;          // receives the window's last frame (may be null)
-    uint64_t* arena;            // unsorted sort keys
-    uint64_t cap;               // arena capacity (keys)
-    unsigned long long* counters;  // [0] reserved, [1] committed, [2] failed tiles, [3] selected
-    unsigned int* icount;       // committed events per interval of the window
-    int* resume;                // per tile: first interval to run; on exit the first not run
-    int W, H, S, K, method, ntiles;
-    float cpos, cneg, m;
+    const uint32_t* mask;       // sparse: [kMaskWords][npix]; null: every interval selected
+    const uint32_t* act_px;     // sparse: active sub-lists; null: slot = pixel
+    const unsigned int* n_active;  // sparse: sub-list lengths; null: npix slots
+    int act_cap;                // sparse: slots per sub-list
+    int* resume;                // per slot: first interval still to run (updated on exit)
+    uint64_t* arena;            // kArenaStripes sub-arenas of stripe_cap keys
+    uint64_t stripe_cap;
+    unsigned long long* reserve;   // kArenaStripes reservation counters (stride kCounterStride)
+    unsigned long long* fails;     // [0] failed reservations, [1] sentinel slots written
+    int W, H, S, K, npix;
+    float cpos, cneg;
     KeyLayout lay;
 };
 
@@ -56,7 +87,15 @@ struct ConvertArgs {
 // Launchers (all asynchronous on `stream`).
 hipError_t launch_init(const uint8_t* frame, const float* lut, float* lref, uint8_t* prev,
                        int64_t npix, hipStream_t stream);
-hipError_t launch_simulate(const SimArgs& a, hipStream_t stream);
+hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
+hipError_t launch_chain(const ChainArgs& a, int max_slots, hipStream_t stream);
+// Concatenates the used part of every sub-arena into `out`; writes the total to *n_total.
+hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
+                         const unsigned long long* reserve, uint64_t* out,
+                         unsigned long long* n_total, hipStream_t stream);
+// reserve[s] = min(reserve[s], cap) for every stripe (before re-running failed chains).
+hipError_t launch_clamp(unsigned long long* reserve, uint64_t cap, hipStream_t stream);
+hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream_t stream);
 // Sorts keys[0, n) on bits [0, nbits) (stable LSD radix, 8-bit digits); the last pass writes
 // into `out` converted by `cv`.  `alt` holds n keys; `hist` holds 256 * ceil(n / kSortTile)
 // counters and `totals` 256.

@@ -8,6 +8,8 @@
 // here; the file is compiled with -ffp-contract=off so no multiply-add is fused.
 #include "evsim_internal.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace evsim {
@@ -15,14 +17,6 @@ namespace evsim {
 // ------------------------------------------------------------------------------------------
 // Helpers
 // ------------------------------------------------------------------------------------------
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
-// tiles so that neighbouring tiles (which gather the same texels) share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int g) {
-    const int q = g >> 3, r = g & 7;
-    const int xcd = b & 7, idx = b >> 3;
-    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
 
 // Exclusive scan over a 256-thread block; returns this thread's prefix and the block total.
 // `wsum` is 4 ints of LDS; the caller must synchronise before `wsum` is reused.
@@ -150,113 +144,288 @@ __global__ __launch_bounds__(256) void k_init(const uint8_t* __restrict__ frame,
 }
 
 // ------------------------------------------------------------------------------------------
-// Simulation of a window of K frame intervals.  One workgroup owns a tile of 256 consecutive
-// pixels (row-major) for the whole window and carries their reference levels in registers from
-// interval to interval (the only temporal dependency is per pixel).  Per interval:
-//   1. transform, sparse selection, interior samples into LDS, count the events;
-//   2. block scan of the counts, one arena reservation per workgroup;
-//   3. if it fits, write the events; otherwise fill the reserved slots with sentinels, keep the
-//      levels of the last completed interval and record where to resume (the host grows the
-//      arena and relaunches only the unfinished tiles).
+// Wave-level helpers (wave64)
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kSimThreads) void k_simulate(SimArgs a) {
-    extern __shared__ float smem[];
-    __shared__ int s_wsum[4];
-    __shared__ int s_wsel[4];
-    __shared__ unsigned long long s_base;
-    __shared__ int s_fail;
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
 
-    float* lut = smem;
+__device__ __forceinline__ uint32_t pick4(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3,
+                                          int w) {
+    return w == 0 ? m0 : (w == 1 ? m1 : (w == 2 ? m2 : m3));
+}
+
+// First selected interval >= i (K when none is left).
+__device__ __forceinline__ int next_selected(bool all, uint32_t m0, uint32_t m1, uint32_t m2,
+                                             uint32_t m3, int i, int K) {
+    if (all) return min(i, K);
+    while (i < K) {
+        const int w = i >> 5;
+        const uint32_t bits = pick4(m0, m1, m2, m3, w) >> (i & 31);
+        if (bits) return min(i + __ffs(bits) - 1, K);
+        i = (w + 1) << 5;
+    }
+    return K;
+}
+
+// ------------------------------------------------------------------------------------------
+// Selection pass of the sparse method (Sec. III-B): a pixel-interval is interpolated only if the
+// transformed frame-to-frame change reaches m.  Each thread streams 4 consecutive pixels through
+// every frame of the window once, builds their selected-interval bitmasks, saves the window's
+// last frame for the next window, and appends the pixels selected at least once to the active
+// list (wave-aggregated reservation).
+// ------------------------------------------------------------------------------------------
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_select(SelectArgs a) {
+    __shared__ float lut[256];
     const int tid = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     lut[tid] = a.lut[tid];
-    const int start = a.resume[tile];
     __syncthreads();
-    if (start >= a.K) return;
+    const int lane = tid & 63;
+    const int base = (blockIdx.x * 256 + tid) * 4;
+    const int cnt = max(0, min(4, a.npix - base));
+
+    uint32_t last = 0;
+    float A0[4];
+    if (VEC && cnt == 4) {
+        last = *(const uint32_t*)(a.prev + base);
+    } else {
+        for (int q = 0; q < cnt; ++q) last |= (uint32_t)a.prev[base + q] << (8 * q);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) A0[q] = lut[(last >> (8 * q)) & 255u];
+
+    uint32_t any[4] = {0u, 0u, 0u, 0u};
+    int nsel = 0;
+    for (int w = 0; w < kMaskWords && w * 32 < a.K; ++w) {
+        uint32_t mw[4] = {0u, 0u, 0u, 0u};
+        const int jend = min(32, a.K - w * 32);
+#pragma unroll 8
+        for (int jj = 0; jj < jend; ++jj) {
+            const uint8_t* F = a.frames + (int64_t)(w * 32 + jj) * a.fstride + base;
+            uint32_t v = 0;
+            if (VEC && cnt == 4) {
+                v = *(const uint32_t*)F;
+            } else {
+                for (int q = 0; q < cnt; ++q) v |= (uint32_t)F[q] << (8 * q);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float A1 = lut[(v >> (8 * q)) & 255u];
+                mw[q] |= (uint32_t)(fabsf(A1 - A0[q]) >= a.m) << jj;
+                A0[q] = A1;
+            }
+            last = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < cnt) {
+                a.mask[(int64_t)w * a.npix + base + q] = mw[q];
+                any[q] |= mw[q];
+                nsel += __popc(mw[q]);
+            }
+        }
+    }
+    if (VEC && cnt == 4) {
+        *(uint32_t*)(a.prev_out + base) = last;
+    } else {
+        for (int q = 0; q < cnt; ++q) a.prev_out[base + q] = (uint8_t)(last >> (8 * q));
+    }
+
+    __shared__ int s_wsum[4];
+    __shared__ unsigned int s_slot0;
+    int na = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) na += (q < cnt && any[q] != 0u) ? 1 : 0;
+    int total;
+    const int off = block_scan_256(na, s_wsum, &total);
+    __syncthreads();
+    int sel_total;
+    block_scan_256(nsel, s_wsum, &sel_total);
+    const int stripe = blockIdx.x % kActStripes;
+    if (tid == 0) {
+        s_slot0 = total > 0 ? atomicAdd(a.n_active + stripe * kCounterStride, (unsigned int)total)
+                            : 0u;
+        if (sel_total > 0)
+            atomicAdd(a.stats + (blockIdx.x % kStatStripes) * kCounterStride,
+                      (unsigned long long)sel_total);
+    }
+    __syncthreads();
+    unsigned int slot = (unsigned int)stripe * (unsigned int)a.act_cap + s_slot0 + (unsigned int)off;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < cnt && any[q] != 0u) {
+            a.act_px[slot] = (uint32_t)(base + q);
+            a.resume[slot] = 0;
+            ++slot;
+        }
+    }
+    (void)lane;
+}
+
+// ------------------------------------------------------------------------------------------
+// Chain pass.  One lane per pixel (per active pixel for the sparse method) walks that pixel's
+// selected intervals in order, carrying its reference level in a register: the only temporal
+// dependency of the method is per pixel, so no lane ever waits for another.  Per step, each
+// active lane computes its interior samples into LDS, counts its crossings, the wave reserves
+// arena space with one atomic (no block barrier), and the lanes write their events.  If the
+// arena is full the wave fills its reservation with sentinels, stores each lane's current
+// interval as its resume point and stops; the host grows the arena and launches again.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
+    extern __shared__ float smem[];
+    float* lut = smem;
+    const int tid = threadIdx.x, lane = tid & 63;
+    lut[tid] = a.lut[tid];
+    __syncthreads();
+
+    const int slot = blockIdx.x * kSimThreads + tid;
+    bool valid;
+    if (a.act_px) {
+        const int stripe = slot / a.act_cap;
+        valid = stripe < kActStripes &&
+                (slot - stripe * a.act_cap) < (int)a.n_active[stripe * kCounterStride];
+    } else {
+        valid = slot < a.npix;
+    }
+    if (!__any(valid)) return;
+
+    const int p = valid ? (a.act_px ? (int)a.act_px[slot] : slot) : 0;
+    const int astripe = (slot >> 6) % kArenaStripes;   // this wave's sub-arena
+    uint64_t* arena = a.arena + (uint64_t)astripe * a.stripe_cap;
+    const int y = p / a.W;
+    const int x = p - y * a.W;
+    const bool all = a.mask == nullptr;
+    uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+    if (valid && !all) {
+        m0 = a.mask[p];
+        if (a.K > 32) m1 = a.mask[(int64_t)a.npix + p];
+        if (a.K > 64) m2 = a.mask[2 * (int64_t)a.npix + p];
+        if (a.K > 96) m3 = a.mask[3 * (int64_t)a.npix + p];
+    }
+    int i = valid ? next_selected(all, m0, m1, m2, m3, a.resume[slot], a.K) : a.K;
+    float R = valid ? a.lref[p] : 0.0f;
 
     const int stash_n = (a.S - 1 <= kMaxStash) ? (a.S - 1) : 0;
     float* stash = smem + 256 + tid;
-
-    const int64_t npix = (int64_t)a.W * a.H;
-    const int64_t p = (int64_t)tile * kSimThreads + tid;
-    const bool inb = p < npix;
-    const int y = inb ? (int)(p / a.W) : 0;
-    const int x = inb ? (int)(p - (int64_t)y * a.W) : 0;
     const int pbits = a.lay.pix_bits();
     const int ishift = a.lay.tb + pbits;
     const uint64_t pixkey = ((uint64_t)y << (a.lay.xb + 1)) | ((uint64_t)x << 1);
+    bool failed = false;
 
-    float R = inb ? a.lref[p] : 0.0f;
-    const uint8_t* Fs = start == 0 ? a.prev : a.frames + (int64_t)(start - 1) * a.fstride;
-    float A0 = inb ? lut[Fs[p]] : 0.0f;
-
-    int i = start;
-    for (; i < a.K; ++i) {
-        const uint8_t* F0 = i == 0 ? a.prev : a.frames + (int64_t)(i - 1) * a.fstride;
-        const uint8_t* F1 = a.frames + (int64_t)i * a.fstride;
-        const float A1 = inb ? lut[F1[p]] : 0.0f;
-        const float delta = a.delta[i];
-        const bool sel = inb && (a.method != kSparse || fabsf(A1 - A0) >= a.m);
-
-        PixelCtx c;
-        c.F0 = F0; c.F1 = F1; c.lut = lut; c.W = a.W; c.H = a.H; c.x = x; c.y = y; c.S = a.S;
-        c.u = 0.0f; c.v = 0.0f; c.stash = nullptr;
-        float Rn = R;
+    for (;;) {
+        const bool have = i < a.K;
+        if (!__any(have)) break;
         int n = 0;
-        if (sel) {
+        float Rn = R, A0 = 0.0f, A1 = 0.0f, delta = 0.0f;
+        PixelCtx c;
+        c.W = a.W; c.H = a.H; c.x = x; c.y = y; c.S = a.S; c.lut = lut;
+        c.u = 0.0f; c.v = 0.0f; c.stash = nullptr;
+        c.F0 = i == 0 ? a.prev : a.frames + (int64_t)(i - 1) * a.fstride;
+        c.F1 = a.frames + (int64_t)i * a.fstride;
+        if (have) {
+            A0 = lut[c.F0[p]];
+            A1 = lut[c.F1[p]];
+            delta = a.delta[i];
             if (a.S > 1) {
-                const float* fl = a.flows + (int64_t)i * a.flstride + 2 * p;
+                const float* fl = a.flows + (int64_t)i * a.flstride + 2 * (int64_t)p;
                 c.u = fl[0];
                 c.v = fl[1];
                 for (int k = 1; k <= stash_n; ++k)
                     stash[(k - 1) * kSimThreads] =
-                        interp_sample(F0, F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
+                        interp_sample(c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
                 if (stash_n) c.stash = stash;
             }
             n = crossings<false>(c, R, A0, A1, a.cpos, a.cneg, delta, 0, pbits, 0, nullptr, &Rn);
         }
-        const uint64_t wsel = __ballot(sel);
-        if ((tid & 63) == 0) s_wsel[tid >> 6] = __popcll(wsel);
-        int total;
-        const int off = block_scan_256(n, s_wsum, &total);
-        if (tid == 0) {
-            int fail = 0;
-            unsigned long long base = 0;
-            if (total > 0) {
-                base = atomicAdd(&a.counters[0], (unsigned long long)total);
-                if (base + (unsigned long long)total > a.cap) {
-                    fail = 1;
-                    atomicAdd(&a.counters[2], 1ull);
-                } else {
-                    atomicAdd(&a.counters[1], (unsigned long long)total);
-                    atomicAdd(&a.icount[i], (unsigned int)total);
-                }
+        const int inc = wave_incl_scan(n);
+        const int total = __shfl(inc, 63, 64);
+        unsigned long long base = 0;
+        int fail = 0;
+        if (lane == 0 && total > 0) {
+            base = atomicAdd(a.reserve + astripe * kCounterStride, (unsigned long long)total);
+            if (base + (unsigned long long)total > a.stripe_cap) {
+                fail = 1;
+                atomicAdd(&a.fails[0], 1ull);
+                if (base < a.stripe_cap) atomicAdd(&a.fails[1], a.stripe_cap - base);
             }
-            if (!fail) {
-                const int nsel = s_wsel[0] + s_wsel[1] + s_wsel[2] + s_wsel[3];
-                if (nsel) atomicAdd(&a.counters[3], (unsigned long long)nsel);
-            }
-            s_base = base;
-            s_fail = fail;
         }
-        __syncthreads();
-        if (s_fail) {
-            const unsigned long long b = s_base;
-            const unsigned long long e = min(b + (unsigned long long)total, (unsigned long long)a.cap);
-            for (unsigned long long j = b + tid; j < e; j += kSimThreads) a.arena[j] = kSentinel;
+        base = __shfl(base, 0, 64);
+        fail = __shfl(fail, 0, 64);
+        if (fail) {
+            const unsigned long long e =
+                min(base + (unsigned long long)total, (unsigned long long)a.stripe_cap);
+            for (unsigned long long j = base + lane; j < e; j += 64) arena[j] = kSentinel;
+            failed = true;
             break;
         }
-        if (n > 0) {
-            const uint64_t keyhi = (uint64_t)i << ishift;
-            crossings<true>(c, R, A0, A1, a.cpos, a.cneg, delta, keyhi, pbits, pixkey,
-                            a.arena + s_base + off, &Rn);
+        if (have) {
+            if (n > 0) {
+                const uint64_t keyhi = (uint64_t)i << ishift;
+                crossings<true>(c, R, A0, A1, a.cpos, a.cneg, delta, keyhi, pbits, pixkey,
+                                arena + base + (inc - n), &Rn);
+            }
+            R = Rn;
+            i = next_selected(all, m0, m1, m2, m3, i + 1, a.K);
         }
-        if (sel) R = Rn;
-        A0 = A1;
     }
-    if (inb) a.lref[p] = R;
-    if (tid == 0) a.resume[tile] = i;
-    if (i == a.K && a.prev_out && inb) a.prev_out[p] = a.frames[(int64_t)(a.K - 1) * a.fstride + p];
+    if (valid) {
+        a.lref[p] = R;
+        a.resume[slot] = failed ? i : a.K;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_u8(const uint8_t* __restrict__ src,
+                                                 uint8_t* __restrict__ dst, int64_t n) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        dst[j] = src[j];
+}
+
+// Concatenation of the sub-arenas.  Block b copies chunk b / kArenaStripes of stripe
+// b % kArenaStripes; its destination offset is the exclusive prefix of the stripe lengths.
+__global__ __launch_bounds__(kArenaStripes) void k_gather(const uint64_t* __restrict__ arena,
+                                                          uint64_t stripe_cap,
+                                                          const unsigned long long* reserve,
+                                                          uint64_t* __restrict__ out,
+                                                          unsigned long long* n_total) {
+    static_assert(kArenaStripes == 256, "one thread per stripe");
+    __shared__ int s_wsum[4];
+    __shared__ unsigned long long s_len[kArenaStripes];
+    const int tid = threadIdx.x;
+    const unsigned long long len = min(reserve[tid * kCounterStride], (unsigned long long)stripe_cap);
+    s_len[tid] = len;
+    // 64-bit exclusive prefix via two 32-bit scans would be overkill: stripe lengths and their
+    // sum stay below 2^31 (the arena holds fewer than 2^31 keys).
+    int tot;
+    const int ex = block_scan_256((int)len, s_wsum, &tot);
+    __shared__ unsigned long long s_off[kArenaStripes];
+    s_off[tid] = (unsigned long long)ex;
+    __syncthreads();
+    const int stripe = blockIdx.x % kArenaStripes;
+    const uint64_t chunk = blockIdx.x / kArenaStripes;
+    if (blockIdx.x == 0 && tid == 0) *n_total = (unsigned long long)tot;
+    const uint64_t n = s_len[stripe];
+    const uint64_t b0 = chunk * kSortTile;
+    if (b0 >= n) return;
+    const uint64_t* src = arena + (uint64_t)stripe * stripe_cap;
+    uint64_t* dst = out + s_off[stripe];
+    const uint64_t e = min(b0 + (uint64_t)kSortTile, n);
+    for (uint64_t j = b0 + tid; j < e; j += kArenaStripes) dst[j] = src[j];
+}
+
+__global__ void k_clamp(unsigned long long* reserve, uint64_t cap) {
+    const int s = threadIdx.x;
+    if (s < kArenaStripes) {
+        unsigned long long* r = reserve + s * kCounterStride;
+        if (*r > cap) *r = cap;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -369,10 +538,44 @@ hipError_t launch_init(const uint8_t* frame, const float* lut, float* lref, uint
     return hipGetLastError();
 }
 
-hipError_t launch_simulate(const SimArgs& a, hipStream_t stream) {
+hipError_t launch_select(const SelectArgs& a, hipStream_t stream) {
+    const int blocks = (a.npix + kSelectPx - 1) / kSelectPx;
+    const bool vec = (a.fstride % 4) == 0 && ((uintptr_t)a.frames % 4) == 0 &&
+                     ((uintptr_t)a.prev % 4) == 0 && ((uintptr_t)a.prev_out % 4) == 0;
+    if (vec)
+        hipLaunchKernelGGL(k_select<true>, dim3(blocks), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_select<false>, dim3(blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain(const ChainArgs& a, int max_slots, hipStream_t stream) {
     const int stash_n = (a.S - 1 <= kMaxStash) ? (a.S - 1) : 0;
     const size_t shmem = (size_t)(256 + stash_n * kSimThreads) * sizeof(float);
-    hipLaunchKernelGGL(k_simulate, dim3((unsigned)a.ntiles), dim3(kSimThreads), shmem, stream, a);
+    const int blocks = (max_slots + kSimThreads - 1) / kSimThreads;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chain, dim3(blocks), dim3(kSimThreads), shmem, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
+                         const unsigned long long* reserve, uint64_t* out,
+                         unsigned long long* n_total, hipStream_t stream) {
+    const uint64_t chunks = (stripe_cap + kSortTile - 1) / kSortTile;
+    const uint64_t blocks = std::max<uint64_t>(1, chunks) * kArenaStripes;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(kArenaStripes), 0, stream, arena,
+                       stripe_cap, reserve, out, n_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_clamp(unsigned long long* reserve, uint64_t cap, hipStream_t stream) {
+    hipLaunchKernelGGL(k_clamp, dim3(1), dim3(kArenaStripes), 0, stream, reserve, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream_t stream) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_copy_u8, dim3((unsigned)blocks), dim3(256), 0, stream, src, dst, n);
     return hipGetLastError();
 }
 

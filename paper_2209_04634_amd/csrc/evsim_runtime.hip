@@ -20,7 +20,6 @@ using namespace evsim;
 
 namespace {
 
-constexpr int kMaxWindow = 256;            // frame intervals per simulation launch (8-bit index)
 constexpr uint64_t kMaxInterval = 1ull << 31;
 constexpr int64_t kMaxEpochSpan = (int64_t)1 << 39;
 
@@ -63,8 +62,11 @@ struct sim_stream {
     int64_t epoch = 0, t_prev = 0;
 
     // window scratch
-    uint64_t* d_arena = nullptr;
-    uint64_t arena_cap = 0;
+    uint64_t* d_arena = nullptr;                 // kArenaStripes sub-arenas of stripe_cap keys
+    uint64_t stripe_cap = 0;
+    unsigned long long* d_reserve = nullptr;     // per sub-arena reservation counters
+    unsigned long long* d_stats = nullptr;       // striped selection statistics
+    int act_cap = 0;                             // sparse: slots per active sub-list
     uint64_t* d_alt = nullptr;
     uint64_t alt_cap = 0;
     uint32_t* d_hist = nullptr;
@@ -72,10 +74,12 @@ struct sim_stream {
     uint32_t* d_totals = nullptr;
     unsigned long long* d_counters = nullptr;
     unsigned long long* h_counters = nullptr;   // pinned
-    unsigned int* d_icount = nullptr;
     float* d_delta = nullptr;
     int64_t* d_tbase = nullptr;
-    int* d_resume = nullptr;
+    int* d_resume = nullptr;                     // per chain slot
+    uint32_t* d_mask = nullptr;                  // sparse: [kMaskWords][npix]
+    uint32_t* d_act = nullptr;                   // sparse: active pixel list
+    unsigned int* d_nact = nullptr;              // sparse: its length
     float* h_delta = nullptr;                    // pinned
     int64_t* h_tbase = nullptr;                  // pinned
 
@@ -90,6 +94,10 @@ struct sim_stream {
     uint64_t fifo_cap = 0, fifo_head = 0, fifo_tail = 0;
 
     sim_stats stats;
+
+    // kernel timing (sim_set_kernel_timing)
+    bool timing = false;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -113,11 +121,15 @@ void free_stream(sim_stream* s) {
     dfree(s->d_prev[0]);
     dfree(s->d_prev[1]);
     dfree(s->d_arena);
+    dfree(s->d_reserve);
+    dfree(s->d_stats);
     dfree(s->d_alt);
     dfree(s->d_hist);
     dfree(s->d_totals);
     dfree(s->d_counters);
-    dfree(s->d_icount);
+    dfree(s->d_mask);
+    dfree(s->d_act);
+    dfree(s->d_nact);
     dfree(s->d_delta);
     dfree(s->d_tbase);
     dfree(s->d_resume);
@@ -127,6 +139,8 @@ void free_stream(sim_stream* s) {
     if (s->h_counters) (void)hipHostFree(s->h_counters);
     if (s->h_delta) (void)hipHostFree(s->h_delta);
     if (s->h_tbase) (void)hipHostFree(s->h_tbase);
+    for (hipEvent_t& e : s->ev)
+        if (e) (void)hipEventDestroy(e);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -159,13 +173,36 @@ int grow(sim_stream* s, T** buf, uint64_t* cap, uint64_t n, uint64_t keep) {
     return SIM_OK;
 }
 
+int ensure_alt(sim_stream* s, uint64_t n) { return grow(s, &s->d_alt, &s->alt_cap, n, 0); }
+
 int ensure_sort_scratch(sim_stream* s, uint64_t n) {
-    int rc = grow(s, &s->d_alt, &s->alt_cap, n, 0);
-    if (rc) return rc;
     uint64_t hc = s->hist_cap;
-    rc = grow(s, &s->d_hist, &hc, sort_hist_entries(n), 0);
+    int rc = grow(s, &s->d_hist, &hc, sort_hist_entries(n), 0);
     s->hist_cap = (size_t)hc;
     return rc;
+}
+
+// Grows every sub-arena to new_stripe_cap keys, keeping the first stripe_cap keys of each.
+int grow_arena(sim_stream* s, uint64_t new_stripe_cap) {
+    if (new_stripe_cap <= s->stripe_cap) return SIM_OK;
+    if (new_stripe_cap * kArenaStripes >= (1ull << 31)) return SIM_E_NOMEM;
+    uint64_t* nb = nullptr;
+    if (hipMalloc((void**)&nb, new_stripe_cap * kArenaStripes * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIM_E_NOMEM;
+    }
+    if (hipMemcpy2DAsync(nb, new_stripe_cap * sizeof(uint64_t), s->d_arena,
+                         s->stripe_cap * sizeof(uint64_t), s->stripe_cap * sizeof(uint64_t),
+                         kArenaStripes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+        dfree(nb);
+        return hip_fail(s);
+    }
+    dfree(s->d_arena);
+    s->d_arena = nb;
+    s->stripe_cap = new_stripe_cap;
+    s->stats.event_capacity = new_stripe_cap * kArenaStripes;
+    return SIM_OK;
 }
 
 void build_lut(sim_stream* s) {
@@ -204,11 +241,42 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
                               s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->d_tbase, s->h_tbase, K * sizeof(int64_t), hipMemcpyHostToDevice,
                               s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->d_resume, 0, s->ntiles * sizeof(int), s->stream));
     HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, 4 * sizeof(unsigned long long), s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->d_icount, 0, K * sizeof(unsigned int), s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->d_reserve, 0,
+                              (size_t)kArenaStripes * kCounterStride * sizeof(unsigned long long),
+                              s->stream));
 
-    SimArgs a;
+    const bool sparse = s->cfg.method == SIM_SPARSE;
+    uint8_t* prev_out = s->d_prev[1 - s->cur];
+    if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[0], s->stream));
+    if (sparse) {
+        HIP_TRY(s, hipMemsetAsync(s->d_nact, 0,
+                                  (size_t)kActStripes * kCounterStride * sizeof(unsigned int),
+                                  s->stream));
+        SelectArgs sa;
+        sa.prev = s->d_prev[s->cur];
+        sa.frames = frames;
+        sa.fstride = s->npix;
+        sa.lut = s->d_lut;
+        sa.prev_out = prev_out;
+        sa.mask = s->d_mask;
+        sa.act_px = s->d_act;
+        sa.resume = s->d_resume;
+        sa.n_active = s->d_nact;
+        sa.stats = s->d_stats;
+        sa.npix = (int)s->npix;
+        sa.K = K;
+        sa.act_cap = s->act_cap;
+        sa.m = s->m;
+        HIP_TRY(s, launch_select(sa, s->stream));
+    } else {
+        HIP_TRY(s, hipMemsetAsync(s->d_resume, 0, (size_t)s->npix * sizeof(int), s->stream));
+        HIP_TRY(s, launch_copy_u8(frames + (size_t)(K - 1) * s->npix, prev_out, s->npix,
+                                  s->stream));
+    }
+    if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
+
+    ChainArgs a;
     a.prev = s->d_prev[s->cur];
     a.frames = frames;
     a.fstride = s->npix;
@@ -217,50 +285,73 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
     a.lut = s->d_lut;
     a.delta = s->d_delta;
     a.lref = s->d_lref;
-    a.prev_out = s->d_prev[1 - s->cur];
-    a.counters = s->d_counters;
-    a.icount = s->d_icount;
+    a.mask = sparse ? s->d_mask : nullptr;
+    a.act_px = sparse ? s->d_act : nullptr;
+    a.n_active = sparse ? s->d_nact : nullptr;
+    a.act_cap = s->act_cap;
     a.resume = s->d_resume;
+    a.reserve = s->d_reserve;
+    a.fails = s->d_counters;          // [0] failed reservations, [1] sentinels, [2] gathered
     a.W = W;
     a.H = H;
     a.S = s->S;
     a.K = K;
-    a.method = s->cfg.method;
-    a.ntiles = s->ntiles;
+    a.npix = (int)s->npix;
     a.cpos = s->cfg.c_pos;
     a.cneg = s->cfg.c_neg;
-    a.m = s->m;
     a.lay = lay;
+    const int max_slots = sparse ? kActStripes * s->act_cap : (int)s->npix;
 
+    bool first = true;
     for (;;) {
         a.arena = s->d_arena;
-        a.cap = s->arena_cap;
-        HIP_TRY(s, launch_simulate(a, s->stream));
-        HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 4 * sizeof(unsigned long long),
+        a.stripe_cap = s->stripe_cap;
+        if (s->timing && !first) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
+        HIP_TRY(s, launch_chain(a, max_slots, s->stream));
+        if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
+        HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(s, hipStreamSynchronize(s->stream));
-        if (s->h_counters[2] == 0) break;
-        // Some tiles ran out of arena space: grow it (keeping what was written, including the
-        // sentinels of abandoned reservations) and re-run only the unfinished tiles.
-        const uint64_t old = s->arena_cap;
-        const uint64_t want = std::max<uint64_t>(2 * old, s->h_counters[0] + s->h_counters[0] / 2);
-        int rc = grow(s, &s->d_arena, &s->arena_cap, want, old);
+        if (s->timing) {
+            float ms = 0.0f;
+            if (first) {
+                HIP_TRY(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
+                s->stats.select_ms += ms;
+                s->stats.select_launches++;
+            }
+            HIP_TRY(s, hipEventElapsedTime(&ms, s->ev[1], s->ev[2]));
+            s->stats.simulate_ms += ms;
+            s->stats.simulate_launches++;
+        }
+        first = false;
+        if (s->h_counters[0] == 0) break;
+        // Some waves ran out of sub-arena space: grow every sub-arena (keeping what was
+        // written, including the sentinels of abandoned reservations) and re-run only the
+        // unfinished pixel chains.
+        const uint64_t old = s->stripe_cap;
+        int rc = grow_arena(s, 2 * old);
         if (rc) {
-            // Finished tiles have already advanced their reference levels: the stream can no
+            // Finished chains have already advanced their reference levels: the stream can no
             // longer be rolled back, so an allocation failure here poisons the handle.
             s->poisoned = true;
             return rc;
         }
-        s->h_counters[0] = old;
-        s->h_counters[2] = 0;
-        HIP_TRY(s, hipMemcpyAsync(s->d_counters, s->h_counters, 3 * sizeof(unsigned long long),
-                                  hipMemcpyHostToDevice, s->stream));
-        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        HIP_TRY(s, launch_clamp(s->d_reserve, old, s->stream));
+        HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, sizeof(unsigned long long), s->stream));
         s->stats.retries++;
     }
-    const uint64_t n_total = std::min<uint64_t>(s->h_counters[0], s->arena_cap);
-    const uint64_t n_valid = s->h_counters[1];
-    s->stats.selected += s->h_counters[3];
+    // concatenate the sub-arenas (into the sort's scratch buffer)
+    {
+        int rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
+        if (rc) return rc;
+    }
+    HIP_TRY(s, launch_gather(s->d_arena, s->stripe_cap, s->d_reserve, s->d_alt,
+                             s->d_counters + 2, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 3 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const uint64_t n_total = s->h_counters[2];
+    const uint64_t n_valid = n_total - s->h_counters[1];
 
     if (n_valid > 0) {
         int rc = ensure_sort_scratch(s, n_total);
@@ -272,8 +363,17 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
         cv.n_valid = n_valid;
         cv.tbase = s->d_tbase;
         cv.lay = lay;
-        HIP_TRY(s, launch_sort(s->d_arena, s->d_alt, n_total, nbits, s->d_hist, s->d_totals,
+        if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[3], s->stream));
+        HIP_TRY(s, launch_sort(s->d_alt, s->d_arena, n_total, nbits, s->d_hist, s->d_totals,
                                s->d_fifo + s->fifo_tail, cv, s->stream));
+        if (s->timing) {
+            HIP_TRY(s, hipEventRecord(s->ev[4], s->stream));
+            HIP_TRY(s, hipEventSynchronize(s->ev[4]));
+            float ms = 0.0f;
+            HIP_TRY(s, hipEventElapsedTime(&ms, s->ev[3], s->ev[4]));
+            s->stats.sort_ms += ms;
+            s->stats.sort_launches++;
+        }
         s->fifo_tail += n_valid;
     }
     s->cur = 1 - s->cur;
@@ -359,18 +459,32 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
         ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
         s->own_stream = ok;
     }
-    uint64_t cap0 = cfg->event_capacity ? cfg->event_capacity : (uint64_t)s->npix;
+    uint64_t cap0 = cfg->event_capacity ? cfg->event_capacity : 2 * (uint64_t)s->npix;
+    s->stripe_cap = std::max<uint64_t>(1, (cap0 + kArenaStripes - 1) / kArenaStripes);
+    if (s->stripe_cap * kArenaStripes >= (1ull << 31)) {
+        delete s;
+        return SIM_E_INVAL;
+    }
+    const int sel_blocks = (int)((s->npix + kSelectPx - 1) / kSelectPx);
+    s->act_cap = ((sel_blocks + kActStripes - 1) / kActStripes) * kSelectPx;
+    const size_t slots = std::max<size_t>((size_t)s->npix, (size_t)kActStripes * s->act_cap);
     ok = ok && dev_alloc(&s->d_lut, 256) == hipSuccess;
     ok = ok && dev_alloc(&s->d_lref, s->npix) == hipSuccess;
     ok = ok && dev_alloc(&s->d_prev[0], s->npix) == hipSuccess;
     ok = ok && dev_alloc(&s->d_prev[1], s->npix) == hipSuccess;
-    ok = ok && dev_alloc(&s->d_arena, cap0) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_arena, s->stripe_cap * kArenaStripes) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_reserve, (size_t)kArenaStripes * kCounterStride) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_stats, (size_t)kStatStripes * kCounterStride) == hipSuccess;
     ok = ok && dev_alloc(&s->d_totals, 256) == hipSuccess;
     ok = ok && dev_alloc(&s->d_counters, 4) == hipSuccess;
-    ok = ok && dev_alloc(&s->d_icount, kMaxWindow) == hipSuccess;
+    if (cfg->method == SIM_SPARSE) {
+        ok = ok && dev_alloc(&s->d_mask, (size_t)kMaskWords * s->npix) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_act, (size_t)kActStripes * s->act_cap) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_nact, (size_t)kActStripes * kCounterStride) == hipSuccess;
+    }
     ok = ok && dev_alloc(&s->d_delta, kMaxWindow) == hipSuccess;
     ok = ok && dev_alloc(&s->d_tbase, kMaxWindow) == hipSuccess;
-    ok = ok && dev_alloc(&s->d_resume, s->ntiles) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_resume, slots) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->h_counters, 4 * sizeof(unsigned long long), 0) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->h_delta, kMaxWindow * sizeof(float), 0) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->h_tbase, kMaxWindow * sizeof(int64_t), 0) == hipSuccess;
@@ -379,14 +493,16 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
         free_stream(s);
         return SIM_E_NOMEM;
     }
-    s->arena_cap = cap0;
     if (hipMemcpyAsync(s->d_lut, s->lut_host, sizeof(s->lut_host), hipMemcpyHostToDevice,
+                       s->stream) != hipSuccess ||
+        hipMemsetAsync(s->d_stats, 0,
+                       (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
                        s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess) {
         free_stream(s);
         return SIM_E_HIP;
     }
-    s->stats.event_capacity = cap0;
+    s->stats.event_capacity = s->stripe_cap * kArenaStripes;
     *out = s;
     return SIM_OK;
 }
@@ -400,12 +516,14 @@ int sim_destroy(sim_stream* s) {
 int sim_reset(sim_stream* s) {
     if (!s) return SIM_E_INVAL;
     if (s->poisoned) return SIM_E_POISONED;
+    HIP_TRY(s, hipMemsetAsync(s->d_stats, 0,
+                              (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
+                              s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     s->started = false;
     s->fifo_head = s->fifo_tail = 0;
-    const uint64_t cap = s->arena_cap;
     memset(&s->stats, 0, sizeof(s->stats));
-    s->stats.event_capacity = cap;
+    s->stats.event_capacity = s->stripe_cap * kArenaStripes;
     return SIM_OK;
 }
 
@@ -470,7 +588,6 @@ int sim_push_frames(sim_stream* s, int32_t n_frames, const uint8_t* frames, cons
         if (rc) return rc;
         total += nn;
     }
-    s->stats.event_capacity = s->arena_cap;
     if (n_new_events) *n_new_events = total;
     return SIM_OK;
 }
@@ -558,6 +675,27 @@ int sim_sync(sim_stream* s) {
 int sim_get_stats(sim_stream* s, sim_stats* out) {
     if (!s || !out) return SIM_E_INVAL;
     *out = s->stats;
+    if (!s->poisoned && s->cfg.method == SIM_SPARSE) {
+        unsigned long long sel[kStatStripes];
+        HIP_TRY(s, hipMemcpy2DAsync(sel, sizeof(unsigned long long), s->d_stats,
+                                    kCounterStride * sizeof(unsigned long long),
+                                    sizeof(unsigned long long), kStatStripes,
+                                    hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        uint64_t tot = 0;
+        for (int i = 0; i < kStatStripes; ++i) tot += sel[i];
+        out->selected = tot;
+    }
+    return SIM_OK;
+}
+
+int sim_set_kernel_timing(sim_stream* s, int32_t enable) {
+    if (!s) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    if (enable && !s->ev[0]) {
+        for (hipEvent_t& e : s->ev) HIP_TRY(s, hipEventCreate(&e));
+    }
+    s->timing = enable != 0;
     return SIM_OK;
 }
 

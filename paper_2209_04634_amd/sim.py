@@ -41,7 +41,10 @@ class SimEvent(ctypes.Structure):
 class SimStats(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_uint64), ("intervals", ctypes.c_uint64),
                 ("events", ctypes.c_uint64), ("selected", ctypes.c_uint64),
-                ("retries", ctypes.c_uint64), ("event_capacity", ctypes.c_uint64)]
+                ("retries", ctypes.c_uint64), ("event_capacity", ctypes.c_uint64),
+                ("select_launches", ctypes.c_uint64), ("select_ms", ctypes.c_double),
+                ("simulate_launches", ctypes.c_uint64), ("simulate_ms", ctypes.c_double),
+                ("sort_launches", ctypes.c_uint64), ("sort_ms", ctypes.c_double)]
 
 
 EVENT_DTYPE = np.dtype([("t", "<i8"), ("x", "<u2"), ("y", "<u2"), ("p", "i1"), ("pad", "u1", 3)])
@@ -83,6 +86,7 @@ def load() -> ctypes.CDLL:
         "sim_sync": (ctypes.c_int, [P]),
         "sim_get_stats": (ctypes.c_int, [P, ctypes.POINTER(SimStats)]),
         "sim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "sim_set_kernel_timing": (ctypes.c_int, [P, I32]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -241,6 +245,10 @@ class Stream:
         st = SimStats()
         _check(self._lib.sim_get_stats(self._h, ctypes.byref(st)), "sim_get_stats")
         return {k: getattr(st, k) for k, _ in SimStats._fields_}
+
+    def set_kernel_timing(self, enable: bool = True) -> None:
+        _check(self._lib.sim_set_kernel_timing(self._h, 1 if enable else 0),
+               "sim_set_kernel_timing")
 
     def sync(self) -> None:
         _check(self._lib.sim_sync(self._h), "sim_sync")
