@@ -48,14 +48,20 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(npix: int, K: int, selected: int, events: int, method: str) -> int:
-    """Minimum HBM bytes of one simulation launch over a window of K intervals: each of the K
-    window frames and the frame before it read once (1 B/px), the last frame saved for the next
-    window (1 B/px), the reference levels read and written once (8 B/px), the flow read at every
-    interpolated pixel-interval (8 B; all of them for dense, the selected ones for sparse, none for
-    basic), and every event written once (8 B)."""
-    flow = 0 if method == "basic" else 8 * selected
-    return npix * (K + 1) + npix + 8 * npix + flow + 8 * events
+def chain_bytes(npix: int, K: int, active: int, selected: int, events: int, method: str) -> int:
+    """Minimum HBM bytes of one chain-kernel launch (the dominant kernel) over a window of K
+    intervals.  Per chain (an active pixel for sparse, every pixel otherwise): its list slot and
+    selected-interval bitmask (sparse: 4 + 16 B), its reference level read and written (8 B).
+    Per interpolated pixel-interval: the two endpoint bytes and the flow vector (2 + 8 B; basic
+    reads no flow).  Per event: one 8-byte key written."""
+    if method == "sparse":
+        per_chain = 4 + 16 + 8
+        chains = active
+    else:
+        per_chain, chains = 8, npix
+        selected = npix * K
+    per_sel = 2 + (0 if method == "basic" else 8)
+    return chains * per_chain + selected * per_sel + 8 * events
 
 
 def main():
@@ -95,40 +101,39 @@ def main():
             raise RuntimeError("output buffer too small")
         got = s.drain_keys(out=out, max_events=n)
         assert got == n
-        return n, s.stats()
+        return n
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    sim_ms = sort_ms = 0.0
-    sim_launches = sort_launches = 0
-    events = selected = 0
+    s.clear_stats()
+    events = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        n, st = step()
-        events += n
-        selected += st["selected"]
-        sim_ms += st["simulate_ms"]
-        sim_launches += st["simulate_launches"]
-        sort_ms += st["sort_ms"]
-        sort_launches += st["sort_launches"]
+        events += step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    st = s.stats()
+    selected = st["selected"]
+    sim_ms, sim_launches = st["simulate_ms"], st["simulate_launches"]
+    sel_ms = st["select_ms"]
+    sort_ms, sort_launches = st["sort_ms"], st["sort_launches"]
     ms_per_step = 1e3 * elapsed / args.steps
     value = npix * K * args.steps / elapsed / 1e6
     ev_per_step = events // args.steps
     sel_per_step = (selected // args.steps) if wl["method"] == "sparse" else npix * K
 
-    # dominant kernel: the simulation launch (one per step: the window holds every interval)
+    # dominant kernel: the per-pixel chain launch (one per step: the window holds every interval)
     launch_ms = sim_ms / max(1, sim_launches)
     launches_per_step = sim_launches / args.steps
-    alg = algorithmic_bytes(npix, K, sel_per_step, ev_per_step, wl["method"])
+    act_per_step = st["active"] // args.steps
+    alg = chain_bytes(npix, K, act_per_step, sel_per_step, ev_per_step, wl["method"])
     alg_per_launch = alg / launches_per_step
     achieved = alg_per_launch / (launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_simulate", "launch_ms": round(launch_ms, 4),
+                "kernel": "k_chain", "launch_ms": round(launch_ms, 4),
                 "algorithmic_bytes_per_launch": int(alg_per_launch)}
 
     # plain path: one push per frame, latency of each push until its events are ordered
@@ -196,6 +201,8 @@ def main():
         "events_per_s": round(ev_per_step * args.steps / elapsed, 1),
         "events_per_step": ev_per_step,
         "selected_fraction": round(sel_per_step / (npix * K), 5),
+        "active_pixels_per_step": act_per_step,
+        "select_ms_per_step": round(sel_ms / args.steps, 4),
         "simulate_ms_per_step": round(sim_ms / args.steps, 4),
         "sort_ms_per_step": round(sort_ms / args.steps, 4),
         "plain_one_frame_pushes": plain,

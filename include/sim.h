@@ -89,6 +89,7 @@ typedef struct sim_stats {
     uint64_t intervals;         /* frame intervals simulated                                        */
     uint64_t events;            /* events produced                                                  */
     uint64_t selected;          /* SIM_SPARSE: pixel-intervals selected for interpolation           */
+    uint64_t active;            /* SIM_SPARSE: pixels selected at least once, summed over windows  */
     uint64_t retries;           /* event-buffer growths that re-ran part of a window                */
     uint64_t event_capacity;    /* current device event buffer (events)                             */
     /* Filled only while kernel timing is on (sim_set_kernel_timing): HIP-event durations on the  */
@@ -116,7 +117,8 @@ int sim_create(const sim_config* cfg, sim_stream** out);
 /* Releases every resource of the handle after the work queued on its stream completes. */
 int sim_destroy(sim_stream* s);
 
-/* Forgets all frames and pending events; the next push is a first frame again. */
+/* Forgets all frames and pending events; the next push is a first frame again.  Device
+ * buffers keep their (grown) sizes and sim_stats keeps counting. */
 int sim_reset(sim_stream* s);
 
 /* Pushes one frame taken at t_us (frame interval semantics of Sec. III-A: the pair of frames
@@ -164,17 +166,24 @@ int sim_get_reference(sim_stream* s, float* dst, int32_t mem_kind);
 /* Waits until all work queued by this stream has completed. */
 int sim_sync(sim_stream* s);
 
-/* Counters since creation (or the last sim_reset). */
+/* Counters since creation or the last sim_clear_stats. */
 int sim_get_stats(sim_stream* s, sim_stats* out);
+
+/* Zeroes the counters of sim_stats (event_capacity excepted). */
+int sim_clear_stats(sim_stream* s);
 
 /* Turns per-kernel timing on (enable != 0) or off.  While on, every simulation launch and every
  * ordering sort is bracketed by HIP events recorded on the stream's own queue, and each push
  * waits for its sort to finish before returning so the durations can be read.  The durations
- * accumulate in sim_stats until sim_reset. */
+ * accumulate in sim_stats until sim_clear_stats. */
 int sim_set_kernel_timing(sim_stream* s, int32_t enable);
 
 /* Static text for a status code. */
 const char* sim_strerror(int status);
+
+/* Text describing the HIP failure that poisoned the handle (call, source line, HIP's message);
+ * empty when there was none.  Valid until the next call on the handle. */
+const char* sim_last_error(sim_stream* s);
 
 #ifdef __cplusplus
 }

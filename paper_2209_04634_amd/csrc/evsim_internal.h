@@ -47,7 +47,7 @@ struct SelectArgs {
     uint32_t* act_px;           // kActStripes sub-lists of act_cap slots each
     int* resume;                // per slot (same indexing as act_px): set to 0 here
     unsigned int* n_active;     // kActStripes counters (stride kCounterStride)
-    unsigned long long* stats;  // kStatStripes counters: += selected pixel-intervals
+    unsigned long long* stats;  // kStatStripes counter pairs: += selected pixel-intervals, active px
     int npix, K, act_cap;
     float m;
 };
@@ -79,8 +79,9 @@ struct ChainArgs {
 
 struct ConvertArgs {
     int enabled;                // final pass: write packed ABI keys instead of sort keys
-    uint64_t n_valid;           // keys below this position are real events
+    const unsigned long long* n_sentinel;  // keys below n - *n_sentinel are real events
     const int64_t* tbase;       // per interval: t_{j-1} - epoch
+    int K;                      // intervals in the window (bound of the interval field)
     KeyLayout lay;
 };
 
@@ -96,11 +97,12 @@ hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
 // reserve[s] = min(reserve[s], cap) for every stripe (before re-running failed chains).
 hipError_t launch_clamp(unsigned long long* reserve, uint64_t cap, hipStream_t stream);
 hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream_t stream);
-// Sorts keys[0, n) on bits [0, nbits) (stable LSD radix, 8-bit digits); the last pass writes
-// into `out` converted by `cv`.  `alt` holds n keys; `hist` holds 256 * ceil(n / kSortTile)
-// counters and `totals` 256.
-hipError_t launch_sort(uint64_t* keys, uint64_t* alt, uint64_t n, int nbits, uint32_t* hist,
-                       uint32_t* totals, uint64_t* out, const ConvertArgs& cv, hipStream_t stream);
-size_t sort_hist_entries(uint64_t n);
+// Sorts keys[0, *n) on bits [0, nbits) (stable LSD radix, 8-bit digits); the last pass writes
+// into `out` converted by `cv`.  The count is read on the device; grids are sized for n_max.
+// `alt` holds n_max keys; `hist` holds sort_hist_entries(n_max) counters and `totals` 256.
+hipError_t launch_sort(uint64_t* keys, uint64_t* alt, const unsigned long long* n,
+                       uint64_t n_max, int nbits, uint32_t* hist, uint32_t* totals,
+                       uint64_t* out, const ConvertArgs& cv, hipStream_t stream);
+size_t sort_hist_entries(uint64_t n_max);
 
 }  // namespace evsim

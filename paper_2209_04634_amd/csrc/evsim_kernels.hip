@@ -252,9 +252,9 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     if (tid == 0) {
         s_slot0 = total > 0 ? atomicAdd(a.n_active + stripe * kCounterStride, (unsigned int)total)
                             : 0u;
-        if (sel_total > 0)
-            atomicAdd(a.stats + (blockIdx.x % kStatStripes) * kCounterStride,
-                      (unsigned long long)sel_total);
+        unsigned long long* st = a.stats + (blockIdx.x % kStatStripes) * kCounterStride;
+        if (sel_total > 0) atomicAdd(st, (unsigned long long)sel_total);
+        if (total > 0) atomicAdd(st + 1, (unsigned long long)total);
     }
     __syncthreads();
     unsigned int slot = (unsigned int)stripe * (unsigned int)a.act_cap + s_slot0 + (unsigned int)off;
@@ -432,11 +432,13 @@ __global__ void k_clamp(unsigned long long* reserve, uint64_t cap) {
 // Stable LSD radix sort, 8-bit digits, three kernels per pass.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
-                                                             uint64_t n, int shift,
+                                                             const unsigned long long* n_dev,
+                                                             int shift,
                                                              uint32_t* __restrict__ hist,
                                                              int nblocks) {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
+    const uint64_t n = *n_dev;
     h[tid] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
@@ -474,6 +476,7 @@ __device__ __forceinline__ uint64_t convert_key(uint64_t k, const ConvertArgs& c
     const uint64_t pix = k & ((1ull << pb) - 1);
     const uint64_t trel = (k >> pb) & ((1ull << L.tb) - 1);
     const uint64_t iv = k >> (pb + L.tb);
+    if (iv >= (uint64_t)cv.K) return kSentinel;   // never for a real key; keeps reads in bounds
     const uint64_t x = (pix >> 1) & ((1ull << L.xb) - 1);
     const uint64_t y = (pix >> (L.xb + 1)) & ((1ull << L.yb) - 1);
     const uint64_t t = (uint64_t)cv.tbase[iv] + trel;
@@ -481,13 +484,16 @@ __device__ __forceinline__ uint64_t convert_key(uint64_t k, const ConvertArgs& c
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n, int shift,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ totals, int nblocks,
-    ConvertArgs cv) {
+    const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+    const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv) {
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_wcnt[4][256];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint64_t n = *n_dev;
+    if ((uint64_t)blockIdx.x * kSortTile >= n) return;
+    const uint64_t n_valid = cv.enabled ? n - *cv.n_sentinel : n;
     int tot;
     const int dex = block_scan_256((int)totals[tid], s_wsum, &tot);
     s_base[tid] = (uint32_t)dex + hist[(size_t)tid * nblocks + blockIdx.x];
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             const uint64_t pos = (uint64_t)s_base[d] + pre + rank;
             if (!cv.enabled) {
                 out[pos] = key;
-            } else if (pos < cv.n_valid) {
+            } else if (pos < n_valid) {
                 out[pos] = convert_key(key, cv);
             }
         }
@@ -579,16 +585,15 @@ hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream
     return hipGetLastError();
 }
 
-size_t sort_hist_entries(uint64_t n) {
-    const uint64_t nb = (n + kSortTile - 1) / kSortTile;
+size_t sort_hist_entries(uint64_t n_max) {
+    const uint64_t nb = (n_max + kSortTile - 1) / kSortTile;
     return (size_t)(nb ? nb : 1) * 256;
 }
 
-hipError_t launch_sort(uint64_t* keys, uint64_t* alt, uint64_t n, int nbits, uint32_t* hist,
-                       uint32_t* totals, uint64_t* out, const ConvertArgs& cv,
-                       hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+hipError_t launch_sort(uint64_t* keys, uint64_t* alt, const unsigned long long* n,
+                       uint64_t n_max, int nbits, uint32_t* hist, uint32_t* totals,
+                       uint64_t* out, const ConvertArgs& cv, hipStream_t stream) {
+    const int nblocks = (int)std::max<uint64_t>(1, (n_max + kSortTile - 1) / kSortTile);
     const int passes = (nbits + 7) / 8;
     uint64_t* src = keys;
     uint64_t* dst = alt;

@@ -6,6 +6,7 @@
 // simulation launch over all tiles, a read of four counters, an optional re-run of the tiles that
 // ran out of arena space (after growing it), and one sort whose last pass appends to the FIFO.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -67,8 +68,10 @@ struct sim_stream {
     unsigned long long* d_reserve = nullptr;     // per sub-arena reservation counters
     unsigned long long* d_stats = nullptr;       // striped selection statistics
     int act_cap = 0;                             // sparse: slots per active sub-list
-    uint64_t* d_alt = nullptr;
+    uint64_t* d_alt = nullptr;                   // gathered keys (sort input)
     uint64_t alt_cap = 0;
+    uint64_t* d_alt2 = nullptr;                  // sort ping-pong buffer; never the arena, which
+    uint64_t alt2_cap = 0;                       // must survive until the overflow check
     uint32_t* d_hist = nullptr;
     size_t hist_cap = 0;
     uint32_t* d_totals = nullptr;
@@ -94,6 +97,7 @@ struct sim_stream {
     uint64_t fifo_cap = 0, fifo_head = 0, fifo_tail = 0;
 
     sim_stats stats;
+    char last_error[256] = {0};
 
     // kernel timing (sim_set_kernel_timing)
     bool timing = false;
@@ -102,15 +106,20 @@ struct sim_stream {
 
 namespace {
 
-int hip_fail(sim_stream* s) {
+int hip_fail_at(sim_stream* s, hipError_t e, const char* what, int line) {
     s->poisoned = true;
+    snprintf(s->last_error, sizeof(s->last_error), "%s (line %d): %s", what, line,
+             hipGetErrorString(e));
+    (void)hipGetLastError();
     return SIM_E_HIP;
 }
 
-#define HIP_TRY(s, expr)                               \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return hip_fail(s);      \
+int hip_fail(sim_stream* s) { return hip_fail_at(s, hipGetLastError(), "HIP call", 0); }
+
+#define HIP_TRY(s, expr)                                                 \
+    do {                                                                 \
+        hipError_t e_ = (expr);                                          \
+        if (e_ != hipSuccess) return hip_fail_at(s, e_, #expr, __LINE__); \
     } while (0)
 
 void free_stream(sim_stream* s) {
@@ -124,6 +133,7 @@ void free_stream(sim_stream* s) {
     dfree(s->d_reserve);
     dfree(s->d_stats);
     dfree(s->d_alt);
+    dfree(s->d_alt2);
     dfree(s->d_hist);
     dfree(s->d_totals);
     dfree(s->d_counters);
@@ -173,7 +183,11 @@ int grow(sim_stream* s, T** buf, uint64_t* cap, uint64_t n, uint64_t keep) {
     return SIM_OK;
 }
 
-int ensure_alt(sim_stream* s, uint64_t n) { return grow(s, &s->d_alt, &s->alt_cap, n, 0); }
+int ensure_alt(sim_stream* s, uint64_t n) {
+    int rc = grow(s, &s->d_alt, &s->alt_cap, n, 0);
+    if (!rc) rc = grow(s, &s->d_alt2, &s->alt2_cap, n, 0);
+    return rc;
+}
 
 int ensure_sort_scratch(sim_stream* s, uint64_t n) {
     uint64_t hc = s->hist_cap;
@@ -327,7 +341,7 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
         if (s->h_counters[0] == 0) break;
         // Some waves ran out of sub-arena space: grow every sub-arena (keeping what was
         // written, including the sentinels of abandoned reservations) and re-run only the
-        // unfinished pixel chains.
+        // unfinished pixel chains.  Nothing else reads or writes the arena in between.
         const uint64_t old = s->stripe_cap;
         int rc = grow_arena(s, 2 * old);
         if (rc) {
@@ -340,7 +354,7 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
         HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, sizeof(unsigned long long), s->stream));
         s->stats.retries++;
     }
-    // concatenate the sub-arenas (into the sort's scratch buffer)
+    // every chain has finished: concatenate the sub-arenas, then order the events
     {
         int rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
         if (rc) return rc;
@@ -352,20 +366,22 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const uint64_t n_total = s->h_counters[2];
     const uint64_t n_valid = n_total - s->h_counters[1];
-
     if (n_valid > 0) {
         int rc = ensure_sort_scratch(s, n_total);
-        if (rc) return rc;
-        rc = grow(s, &s->d_fifo, &s->fifo_cap, s->fifo_tail + n_valid, s->fifo_tail);
+        if (!rc && s->fifo_tail + n_valid > s->fifo_cap)
+            rc = grow(s, &s->d_fifo, &s->fifo_cap,
+                      std::max<uint64_t>(s->fifo_tail + n_valid, 2 * s->fifo_cap),
+                      s->fifo_tail);
         if (rc) return rc;
         ConvertArgs cv;
         cv.enabled = 1;
-        cv.n_valid = n_valid;
+        cv.n_sentinel = s->d_counters + 1;
         cv.tbase = s->d_tbase;
+        cv.K = K;
         cv.lay = lay;
         if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[3], s->stream));
-        HIP_TRY(s, launch_sort(s->d_alt, s->d_arena, n_total, nbits, s->d_hist, s->d_totals,
-                               s->d_fifo + s->fifo_tail, cv, s->stream));
+        HIP_TRY(s, launch_sort(s->d_alt, s->d_alt2, s->d_counters + 2, n_total, nbits,
+                               s->d_hist, s->d_totals, s->d_fifo + s->fifo_tail, cv, s->stream));
         if (s->timing) {
             HIP_TRY(s, hipEventRecord(s->ev[4], s->stream));
             HIP_TRY(s, hipEventSynchronize(s->ev[4]));
@@ -374,8 +390,8 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
             s->stats.sort_ms += ms;
             s->stats.sort_launches++;
         }
-        s->fifo_tail += n_valid;
     }
+    s->fifo_tail += n_valid;
     s->cur = 1 - s->cur;
     s->t_prev = t_us[K - 1];
     s->stats.intervals += (uint64_t)K;
@@ -516,12 +532,19 @@ int sim_destroy(sim_stream* s) {
 int sim_reset(sim_stream* s) {
     if (!s) return SIM_E_INVAL;
     if (s->poisoned) return SIM_E_POISONED;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    s->started = false;
+    s->fifo_head = s->fifo_tail = 0;
+    return SIM_OK;
+}
+
+int sim_clear_stats(sim_stream* s) {
+    if (!s) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
     HIP_TRY(s, hipMemsetAsync(s->d_stats, 0,
                               (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
                               s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
-    s->started = false;
-    s->fifo_head = s->fifo_tail = 0;
     memset(&s->stats, 0, sizeof(s->stats));
     s->stats.event_capacity = s->stripe_cap * kArenaStripes;
     return SIM_OK;
@@ -672,19 +695,28 @@ int sim_sync(sim_stream* s) {
     return SIM_OK;
 }
 
+const char* sim_last_error(sim_stream* s) {
+    if (!s) return "";
+    return s->last_error;
+}
+
 int sim_get_stats(sim_stream* s, sim_stats* out) {
     if (!s || !out) return SIM_E_INVAL;
     *out = s->stats;
     if (!s->poisoned && s->cfg.method == SIM_SPARSE) {
-        unsigned long long sel[kStatStripes];
-        HIP_TRY(s, hipMemcpy2DAsync(sel, sizeof(unsigned long long), s->d_stats,
+        unsigned long long sel[2 * kStatStripes];
+        HIP_TRY(s, hipMemcpy2DAsync(sel, 2 * sizeof(unsigned long long), s->d_stats,
                                     kCounterStride * sizeof(unsigned long long),
-                                    sizeof(unsigned long long), kStatStripes,
+                                    2 * sizeof(unsigned long long), kStatStripes,
                                     hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(s, hipStreamSynchronize(s->stream));
-        uint64_t tot = 0;
-        for (int i = 0; i < kStatStripes; ++i) tot += sel[i];
+        uint64_t tot = 0, act = 0;
+        for (int i = 0; i < kStatStripes; ++i) {
+            tot += sel[2 * i];
+            act += sel[2 * i + 1];
+        }
         out->selected = tot;
+        out->active = act;
     }
     return SIM_OK;
 }

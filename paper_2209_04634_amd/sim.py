@@ -41,6 +41,7 @@ class SimEvent(ctypes.Structure):
 class SimStats(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_uint64), ("intervals", ctypes.c_uint64),
                 ("events", ctypes.c_uint64), ("selected", ctypes.c_uint64),
+                ("active", ctypes.c_uint64),
                 ("retries", ctypes.c_uint64), ("event_capacity", ctypes.c_uint64),
                 ("select_launches", ctypes.c_uint64), ("select_ms", ctypes.c_double),
                 ("simulate_launches", ctypes.c_uint64), ("simulate_ms", ctypes.c_double),
@@ -87,6 +88,8 @@ def load() -> ctypes.CDLL:
         "sim_get_stats": (ctypes.c_int, [P, ctypes.POINTER(SimStats)]),
         "sim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "sim_set_kernel_timing": (ctypes.c_int, [P, I32]),
+        "sim_clear_stats": (ctypes.c_int, [P]),
+        "sim_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -103,8 +106,12 @@ class SimError(RuntimeError):
         super().__init__(f"{where}: {msg} ({status})")
 
 
-def _check(rc: int, where: str) -> None:
+def _check(rc: int, where: str, handle=None) -> None:
     if rc != OK:
+        if handle is not None and rc in (E_HIP, E_POISONED):
+            detail = load().sim_last_error(handle).decode()
+            if detail:
+                where = f"{where} [{detail}]"
         raise SimError(rc, where)
 
 
@@ -172,7 +179,7 @@ class Stream:
             raise ValueError("frame and flow must both be host or both be device memory")
         n = ctypes.c_uint64()
         _check(self._lib.sim_push_frame(self._h, fp, lp, int(t_us), fk, ctypes.byref(n)),
-               "sim_push_frame")
+               "sim_push_frame", self._h)
         return n.value
 
     def push_frames(self, frames, flows, t_us: Sequence[int]) -> int:
@@ -188,13 +195,13 @@ class Stream:
             raise ValueError("need one timestamp per frame")
         out = ctypes.c_uint64()
         _check(self._lib.sim_push_frames(self._h, n, fp, lp, t.ctypes.data_as(ctypes.c_void_p),
-                                         fk, ctypes.byref(out)), "sim_push_frames")
+                                         fk, ctypes.byref(out)), "sim_push_frames", self._h)
         return out.value
 
     # -- events ---------------------------------------------------------------------------
     def pending(self) -> int:
         n = ctypes.c_uint64()
-        _check(self._lib.sim_pending_events(self._h, ctypes.byref(n)), "sim_pending_events")
+        _check(self._lib.sim_pending_events(self._h, ctypes.byref(n)), "sim_pending_events", self._h)
         return n.value
 
     def drain_events(self, max_events: Optional[int] = None) -> np.ndarray:
@@ -203,7 +210,7 @@ class Stream:
         out = np.zeros(n, dtype=EVENT_DTYPE)
         got = ctypes.c_uint64()
         _check(self._lib.sim_drain_events(self._h, out.ctypes.data_as(ctypes.c_void_p), n,
-                                          ctypes.byref(got)), "sim_drain_events")
+                                          ctypes.byref(got)), "sim_drain_events", self._h)
         return out[:got.value]
 
     def drain_keys(self, max_events: Optional[int] = None, out=None):
@@ -214,47 +221,50 @@ class Stream:
             n = int(out.numel()) if max_events is None else int(max_events)
             got = ctypes.c_uint64()
             _check(self._lib.sim_drain_keys(self._h, ptr, n, kind, ctypes.byref(got)),
-                   "sim_drain_keys")
+                   "sim_drain_keys", self._h)
             return got.value
         n = self.pending() if max_events is None else int(max_events)
         arr = np.zeros(n, dtype=np.uint64)
         got = ctypes.c_uint64()
         _check(self._lib.sim_drain_keys(self._h, arr.ctypes.data_as(ctypes.c_void_p), n,
-                                        MEM_HOST, ctypes.byref(got)), "sim_drain_keys")
+                                        MEM_HOST, ctypes.byref(got)), "sim_drain_keys", self._h)
         return arr[:got.value]
 
     # -- state ----------------------------------------------------------------------------
     @property
     def epoch(self) -> int:
         e = ctypes.c_int64()
-        _check(self._lib.sim_epoch(self._h, ctypes.byref(e)), "sim_epoch")
+        _check(self._lib.sim_epoch(self._h, ctypes.byref(e)), "sim_epoch", self._h)
         return e.value
 
     def reference(self, out=None):
         """Per-pixel reference levels float32 [H, W] (numpy, or into a torch device tensor)."""
         if out is not None:
             ptr, kind, keep = _buffer(out, np.float32, (self.height, self.width))
-            _check(self._lib.sim_get_reference(self._h, ptr, kind), "sim_get_reference")
+            _check(self._lib.sim_get_reference(self._h, ptr, kind), "sim_get_reference", self._h)
             return out
         arr = np.zeros((self.height, self.width), dtype=np.float32)
         _check(self._lib.sim_get_reference(self._h, arr.ctypes.data_as(ctypes.c_void_p),
-                                           MEM_HOST), "sim_get_reference")
+                                           MEM_HOST), "sim_get_reference", self._h)
         return arr
 
     def stats(self) -> dict:
         st = SimStats()
-        _check(self._lib.sim_get_stats(self._h, ctypes.byref(st)), "sim_get_stats")
+        _check(self._lib.sim_get_stats(self._h, ctypes.byref(st)), "sim_get_stats", self._h)
         return {k: getattr(st, k) for k, _ in SimStats._fields_}
+
+    def clear_stats(self) -> None:
+        _check(self._lib.sim_clear_stats(self._h), "sim_clear_stats", self._h)
 
     def set_kernel_timing(self, enable: bool = True) -> None:
         _check(self._lib.sim_set_kernel_timing(self._h, 1 if enable else 0),
-               "sim_set_kernel_timing")
+               "sim_set_kernel_timing", self._h)
 
     def sync(self) -> None:
-        _check(self._lib.sim_sync(self._h), "sim_sync")
+        _check(self._lib.sim_sync(self._h), "sim_sync", self._h)
 
     def reset(self) -> None:
-        _check(self._lib.sim_reset(self._h), "sim_reset")
+        _check(self._lib.sim_reset(self._h), "sim_reset", self._h)
 
     def close(self) -> None:
         h = getattr(self, "_h", None)
