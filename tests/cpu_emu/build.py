@@ -1,0 +1,41 @@
+"""Builds the CPU emulation of libevsim (TEST INFRASTRUCTURE): the unmodified HIP sources of
+paper_2209_04634_amd/csrc compiled as host C++ against tests/cpu_emu/hip/hip_runtime.h."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2209_04634_amd", "csrc")
+SOURCES = [os.path.join(CSRC, "evsim_kernels.hip"), os.path.join(CSRC, "evsim_runtime.hip")]
+
+
+def lib_path(asan: bool = False) -> str:
+    return os.path.join(HERE, "libevsim_cpu_asan.so" if asan else "libevsim_cpu.so")
+
+
+def build(asan: bool = False, force: bool = False) -> str:
+    out = lib_path(asan)
+    deps = SOURCES + [os.path.join(CSRC, "evsim_internal.h"), os.path.join(HERE, "emu.cpp"),
+                      os.path.join(HERE, "hip", "hip_runtime.h"),
+                      os.path.join(ROOT, "include", "sim.h")]
+    if (not force and os.path.exists(out)
+            and os.path.getmtime(out) >= max(os.path.getmtime(d) for d in deps)):
+        return out
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-Wno-unknown-pragmas", "-Wno-unused-result",
+             "-I", HERE, "-I", os.path.join(ROOT, "include"), "-Wl,-Bsymbolic"]
+    if asan:
+        flags += ["-fsanitize=address", "-fno-omit-frame-pointer"]
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["g++", *flags, "-x", "c++", *SOURCES, "-x", "none", os.path.join(HERE, "emu.cpp"),
+           "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(force=True))
+    print(build(asan=True, force=True))

@@ -1,0 +1,369 @@
+// CPU emulation of HIP kernel execution and runtime calls (TEST INFRASTRUCTURE).
+//
+// One fiber per GPU thread, scheduled cooperatively on the calling OS thread.  A wave
+// intrinsic is a two-phase rendezvous of the live lanes of a wave (deposit, then read); a
+// __syncthreads() waits for every live thread of the block.  Any lane reaching a different
+// intrinsic (by source line) than its wave-mates is reported as divergent use, and a round in
+// which no fiber can make progress is reported as a deadlock; both abort the process.
+#include "hip/hip_runtime.h"
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#if defined(__SANITIZE_ADDRESS__)
+#define EMU_ASAN 1
+#elif defined(__has_feature)
+#if __has_feature(address_sanitizer)
+#define EMU_ASAN 1
+#endif
+#endif
+#ifdef EMU_ASAN
+#include <sanitizer/asan_interface.h>
+#include <sanitizer/common_interface_defs.h>
+#endif
+
+namespace evsim {
+// dynamic shared memory ("extern __shared__ float smem[]") of the block that is running
+thread_local float smem[1 << 16];
+}
+
+// Minimal x86-64 (System V) stack switch: saves the callee-saved registers and the SSE/x87
+// control words on the current stack, stores the stack pointer to *save, loads `next` and pops
+// the same frame from it.  No signal-mask system call (unlike swapcontext).
+extern "C" void emu_ctx_switch(void** save, void* next);
+asm(R"(
+    .text
+    .globl emu_ctx_switch
+    .type emu_ctx_switch, @function
+emu_ctx_switch:
+    pushq %rbp
+    pushq %rbx
+    pushq %r12
+    pushq %r13
+    pushq %r14
+    pushq %r15
+    subq $8, %rsp
+    stmxcsr (%rsp)
+    fnstcw 4(%rsp)
+    movq %rsp, (%rdi)
+    movq %rsi, %rsp
+    ldmxcsr (%rsp)
+    fldcw 4(%rsp)
+    addq $8, %rsp
+    popq %r15
+    popq %r14
+    popq %r13
+    popq %r12
+    popq %rbx
+    popq %rbp
+    ret
+    .size emu_ctx_switch, .-emu_ctx_switch
+)");
+
+namespace {
+
+constexpr size_t kStack = 512 * 1024;
+
+struct Fiber {
+    void* sp;          // saved stack pointer while switched out
+    emu_uint3 tid;
+    int wave;
+    bool done;
+};
+
+struct Wave {
+    int state;        // 0 collecting, 1 draining
+    int arrived, departed;
+    int op, line;
+    uint64_t gen;
+    uint64_t vals[64];
+    int args[64];
+    bool present[64];
+    int live;
+};
+
+struct Block {
+    std::vector<Fiber> fibers;
+    std::vector<Wave> waves;
+    int live = 0;
+    int bar_arrived = 0;
+    int bar_line = -1;
+    uint64_t bar_gen = 0;
+    void* sched_sp = nullptr;
+    int cur = -1;
+    const std::function<void()>* body = nullptr;
+    uint64_t progress = 0;
+    const char* name = "";
+};
+
+Block B;
+const void* g_main_bottom = nullptr;   // the scheduler's (process) stack, for the sanitizer
+size_t g_main_size = 0;
+emu_uint3 g_block{0, 0, 0};
+dim3 g_bdim, g_gdim;
+std::vector<char*> g_stacks;
+hipError_t g_last = hipSuccess;
+
+[[noreturn]] void die(const char* what) {
+    fprintf(stderr, "[cpu-emu] %s in kernel %s, block (%u,%u,%u)\n", what, B.name, g_block.x,
+            g_block.y, g_block.z);
+    fflush(stderr);
+    abort();
+}
+
+void switch_to(void** save, void* next, const void* stack_bottom, size_t size) {
+#ifdef EMU_ASAN
+    void* fake = nullptr;
+    __sanitizer_start_switch_fiber(&fake, stack_bottom, size);
+    emu_ctx_switch(save, next);
+    __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#else
+    (void)stack_bottom;
+    (void)size;
+    emu_ctx_switch(save, next);
+#endif
+}
+
+void yield_fiber() {
+    Fiber& f = B.fibers[B.cur];
+    // back to the scheduler, which runs on the process stack
+    switch_to(&f.sp, B.sched_sp, g_main_bottom, g_main_size);
+}
+
+void wave_try_complete(Wave& w) {
+    if (w.state == 0 && w.arrived > 0 && w.arrived == w.live) {
+        w.state = 1;
+        w.departed = 0;
+        w.gen++;
+        B.progress++;
+    }
+}
+
+void barrier_try_release() {
+    if (B.bar_arrived > 0 && B.bar_arrived == B.live) {
+        B.bar_arrived = 0;
+        B.bar_line = -1;
+        B.bar_gen++;
+        B.progress++;
+    }
+}
+
+[[noreturn]] void trampoline() {
+#ifdef EMU_ASAN
+    __sanitizer_finish_switch_fiber(nullptr, &g_main_bottom, &g_main_size);
+#endif
+    (*B.body)();
+    Fiber& f = B.fibers[B.cur];
+    f.done = true;
+    B.live--;
+    Wave& w = B.waves[f.wave];
+    w.live--;
+    B.progress++;
+    wave_try_complete(w);
+    barrier_try_release();
+#ifdef EMU_ASAN
+    __sanitizer_start_switch_fiber(nullptr, g_main_bottom, g_main_size);
+#endif
+    void* dead = nullptr;
+    emu_ctx_switch(&dead, B.sched_sp);   // never resumed
+    abort();
+}
+
+// Initial frame of a fiber: what emu_ctx_switch pops, then the entry address as return address
+// and a fake return address of the entry function (so rsp is 8 mod 16 at its first instruction).
+void* initial_sp(char* stack) {
+#ifdef EMU_ASAN
+    // the stack is reused across blocks: drop the frame poisoning of the previous fiber
+    __asan_unpoison_memory_region(stack, kStack);
+#endif
+    uint64_t top = ((uint64_t)(stack + kStack)) & ~(uint64_t)15;
+    uint64_t* sp = (uint64_t*)top;
+    *--sp = 0;                          // fake return address of trampoline
+    *--sp = (uint64_t)&trampoline;      // popped by ret
+    for (int r = 0; r < 6; ++r) *--sp = 0;   // rbp rbx r12 r13 r14 r15
+    // default x86-64 SysV control words: MXCSR 0x1F80 (round to nearest, all exceptions
+    // masked, no flush-to-zero), x87 control word 0x037F
+    *--sp = (uint64_t)0x1F80u | ((uint64_t)0x037Fu << 32);
+    return sp;
+}
+
+void run_block(int n, const std::function<void()>& body, const char* name) {
+    B.fibers.assign(n, Fiber());
+    B.waves.assign((n + 63) / 64, Wave());
+    for (auto& w : B.waves) memset(&w, 0, sizeof(Wave));
+    B.live = n;
+    B.bar_arrived = 0;
+    B.bar_line = -1;
+    B.bar_gen = 0;
+    B.body = &body;
+    B.name = name;
+    while ((int)g_stacks.size() < n) g_stacks.push_back((char*)malloc(kStack));
+    for (int i = 0; i < n; ++i) {
+        Fiber& f = B.fibers[i];
+        f.tid = emu_uint3{(unsigned)i, 0u, 0u};
+        f.wave = i / 64;
+        f.done = false;
+        B.waves[f.wave].live++;
+        f.sp = initial_sp(g_stacks[i]);
+    }
+    while (B.live > 0) {
+        const uint64_t before = B.progress;
+        for (int i = 0; i < n; ++i) {
+            if (B.fibers[i].done) continue;
+            B.cur = i;
+            switch_to(&B.sched_sp, B.fibers[i].sp, g_stacks[i], kStack);
+        }
+        if (B.live > 0 && B.progress == before) die("deadlock (no fiber can progress)");
+    }
+    B.cur = -1;
+}
+
+}  // namespace
+
+const emu_uint3& emu_thread_idx() { return B.fibers[B.cur].tid; }
+const emu_uint3& emu_block_idx() { return g_block; }
+const dim3& emu_block_dim() { return g_bdim; }
+const dim3& emu_grid_dim() { return g_gdim; }
+
+void emu_syncthreads(int line) {
+    if (B.bar_arrived == 0) B.bar_line = line;
+    else if (B.bar_line != line) die("__syncthreads reached from different lines");
+    const uint64_t gen = B.bar_gen;
+    B.bar_arrived++;
+    B.progress++;
+    barrier_try_release();
+    while (B.bar_gen == gen) yield_fiber();
+}
+
+uint64_t emu_wave_exchange(int op, uint64_t value, int arg, int line) {
+    Fiber& f = B.fibers[B.cur];
+    Wave& w = B.waves[f.wave];
+    const int lane = (int)(f.tid.x & 63u);
+    while (w.state == 1) yield_fiber();
+    if (w.arrived == 0) {
+        w.op = op;
+        w.line = line;
+    } else if (w.op != op || w.line != line) {
+        die("divergent wave intrinsic (lanes at different calls)");
+    }
+    w.vals[lane] = value;
+    w.args[lane] = arg;
+    w.present[lane] = true;
+    w.arrived++;
+    B.progress++;
+    const uint64_t gen = w.gen;
+    wave_try_complete(w);
+    while (w.gen == gen) yield_fiber();
+    uint64_t r = 0;
+    if (op == EMU_SHFL) {
+        const int src = arg & 63;
+        r = w.present[src] ? w.vals[src] : value;
+    } else if (op == EMU_SHFL_UP) {
+        const int src = lane - arg;
+        r = (src >= 0 && w.present[src]) ? w.vals[src] : value;
+    } else {
+        for (int l = 0; l < 64; ++l)
+            if (w.present[l] && w.vals[l]) r |= 1ull << l;
+    }
+    w.departed++;
+    B.progress++;
+    if (w.departed == w.arrived) {
+        w.state = 0;
+        w.arrived = 0;
+        memset(w.present, 0, sizeof(w.present));
+    }
+    return r;
+}
+
+void emu_run_grid(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body,
+                  const char* name) {
+    if (shmem > sizeof(evsim::smem)) die("dynamic shared memory request too large");
+    if (block.y != 1 || block.z != 1 || block.x == 0 || block.x > 1024) die("unsupported block");
+    g_gdim = grid;
+    g_bdim = block;
+    for (unsigned bz = 0; bz < grid.z; ++bz)
+        for (unsigned by = 0; by < grid.y; ++by)
+            for (unsigned bx = 0; bx < grid.x; ++bx) {
+                g_block = emu_uint3{bx, by, bz};
+                run_block((int)block.x, body, name);
+            }
+}
+
+// ---- runtime API ------------------------------------------------------------------------------
+struct emu_stream_t {
+    int dummy;
+};
+struct emu_event_t {
+    std::chrono::steady_clock::time_point t;
+};
+
+hipError_t emu_hipMalloc(void** p, size_t n) {
+    *p = malloc(n ? n : 1);
+    if (!*p) return hipErrorOutOfMemory;
+    memset(*p, 0xA5, n);   // device memory starts as garbage
+    return hipSuccess;
+}
+hipError_t emu_hipFree(void* p) {
+    free(p);
+    return hipSuccess;
+}
+hipError_t emu_hipHostMalloc(void** p, size_t n, unsigned) {
+    *p = malloc(n ? n : 1);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+hipError_t emu_hipHostFree(void* p) {
+    free(p);
+    return hipSuccess;
+}
+hipError_t emu_hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) {
+    if (n) memmove(dst, src, n);
+    return hipSuccess;
+}
+hipError_t emu_hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind k, hipStream_t) {
+    return emu_hipMemcpy(dst, src, n, k);
+}
+hipError_t emu_hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch,
+                                size_t width, size_t height, hipMemcpyKind, hipStream_t) {
+    if (width > dpitch || width > spitch) return hipErrorInvalidValue;
+    for (size_t r = 0; r < height; ++r)
+        memmove((char*)dst + r * dpitch, (const char*)src + r * spitch, width);
+    return hipSuccess;
+}
+hipError_t emu_hipMemsetAsync(void* p, int v, size_t n, hipStream_t) {
+    memset(p, v, n);
+    return hipSuccess;
+}
+hipError_t emu_hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+    *s = new emu_stream_t();
+    return hipSuccess;
+}
+hipError_t emu_hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t emu_hipStreamDestroy(hipStream_t s) {
+    delete s;
+    return hipSuccess;
+}
+hipError_t emu_hipEventCreate(hipEvent_t* e) {
+    *e = new emu_event_t();
+    return hipSuccess;
+}
+hipError_t emu_hipEventRecord(hipEvent_t e, hipStream_t) {
+    e->t = std::chrono::steady_clock::now();
+    return hipSuccess;
+}
+hipError_t emu_hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t emu_hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+    *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();
+    return hipSuccess;
+}
+hipError_t emu_hipEventDestroy(hipEvent_t e) {
+    delete e;
+    return hipSuccess;
+}
+hipError_t emu_hipGetLastError() {
+    hipError_t e = g_last;
+    g_last = hipSuccess;
+    return e;
+}
+const char* emu_hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "error"; }
