@@ -144,6 +144,28 @@ int sim_push_frame(sim_stream* s, const uint8_t* frame, const float* flow, int64
 int sim_push_frames(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
                     const int64_t* t_us, int32_t mem_kind, uint64_t* n_new_events);
 
+/* One entry of a batched push: the arguments of sim_push_frames for one stream (inputs), plus
+ * the per-stream results (outputs). */
+typedef struct sim_frames {
+    int32_t n_frames;
+    int32_t mem_kind;           /* SIM_MEM_HOST or SIM_MEM_DEVICE for frames and flows            */
+    const uint8_t* frames;      /* uint8 [n_frames][height][width]                                 */
+    const float* flows;         /* float32 [n_intervals][height][width][2] (see sim_push_frames)   */
+    const int64_t* t_us;        /* host array of n_frames timestamps                               */
+    uint64_t n_new_events;      /* out: events produced for this stream                            */
+    int32_t status;             /* out: SIM_OK or this stream's error                              */
+    int32_t pad;
+} sim_frames;
+
+/* Pushes frames to n distinct streams at once, with exactly the result of n sim_push_frames
+ * calls.  Every stream's selection and chain kernels are queued on its own HIP stream before the
+ * host waits on any of them, and so are the orderings, so the streams' work overlaps on the GPU
+ * (streams of mixed resolution and method may be combined).  Validation of every entry (and a
+ * handle listed twice, SIM_E_INVAL) happens before any work is queued; on a validation error
+ * nothing changes.  Errors after that are reported per entry in `status` and affect only that
+ * stream.  Returns SIM_OK or the first error. */
+int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n);
+
 /* Number of events produced and not yet drained. */
 int sim_pending_events(sim_stream* s, uint64_t* n);
 
@@ -184,6 +206,63 @@ const char* sim_strerror(int status);
 /* Text describing the HIP failure that poisoned the handle (call, source line, HIP's message);
  * empty when there was none.  Valid until the next call on the handle. */
 const char* sim_last_error(sim_stream* s);
+
+/* ------------------------------------------------------------------------------------------
+ * Serving: many virtual cameras, continuous batching.
+ *
+ * A server owns cameras (one simulator stream each, with its device-resident state and a device
+ * staging queue of `queue_depth` frames).  srv_admit creates a camera if a slot is free and its
+ * estimated HBM footprint (srv_footprint) fits the remaining budget, else returns SIM_E_BUSY and
+ * changes nothing; srv_release frees both.  srv_submit queues one frame (copied to the camera's
+ * staging queue; SIM_E_BUSY when the queue is full, SIM_E_ORDER when t_us does not increase).
+ * srv_step runs every queued frame of every camera as one batched push (sim_push_batch), so the
+ * cameras' GPU work overlaps; frames submitted after a step started wait for the next one.  The
+ * latency of a frame is the time from its arrival stamp (srv_now_ns clock; 0 = now) to the end
+ * of the step that ordered its events.  Results per camera are exactly those of the camera's
+ * frames pushed alone.  A server is not thread-safe.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct sim_server sim_server;
+
+typedef struct sim_server_stats {
+    uint64_t cameras;             /* admitted and not released                                     */
+    uint64_t admissions;
+    uint64_t rejected_admissions; /* SIM_E_BUSY from srv_admit                                     */
+    uint64_t submitted;           /* frames accepted by srv_submit                                 */
+    uint64_t rejected_frames;     /* SIM_E_BUSY from srv_submit (queue full)                       */
+    uint64_t completed;           /* frames whose events are ordered                               */
+    uint64_t failed_frames;       /* frames of a camera whose push failed in a step                */
+    uint64_t steps;
+    uint64_t events;
+    uint64_t hbm_used, hbm_budget;/* footprint estimates of the admitted cameras, and the budget   */
+    double p50_ms, p99_ms, max_ms;/* per-frame latency, arrival to ordered events                  */
+} sim_server_stats;
+
+/* Estimated device bytes of one camera with this configuration and staging queue depth. */
+int srv_footprint(const sim_config* cfg, int32_t queue_depth, uint64_t* bytes);
+int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_depth,
+               sim_server** out);
+int srv_destroy(sim_server* srv);
+int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam);
+int srv_release(sim_server* srv, int32_t cam);
+/* frame: uint8 [H][W]; flow: float32 [H][W][2] for the interval ending at this frame (required
+ * for SIM_DENSE / SIM_SPARSE except on a camera's first frame); both host or both device.  The
+ * inputs are copied into the camera's staging slot before the call returns, so the caller may
+ * reuse or free them at once; a device input must be complete (its writes synchronised) at the
+ * call.  SIM_E_BUSY when the camera's queue is full (call srv_step), SIM_E_ORDER when t_us does
+ * not increase. */
+int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* flow,
+               int64_t t_us, int32_t mem_kind, int64_t arrival_ns);
+/* One continuous-batching step; *n_frames receives the frames completed.  Returns SIM_OK or the
+ * first per-camera error (that camera's queued frames are dropped and counted as failed). */
+int srv_step(sim_server* srv, uint64_t* n_frames);
+/* Drains a camera's ordered events as packed keys (as sim_drain_keys). */
+int srv_drain(sim_server* srv, int32_t cam, uint64_t* dst, uint64_t max_events, int32_t mem_kind,
+              uint64_t* n_written);
+/* The simulator stream of a camera (owned by the server). */
+int srv_stream(sim_server* srv, int32_t cam, sim_stream** out);
+int srv_get_stats(sim_server* srv, sim_server_stats* out);
+int srv_clear_stats(sim_server* srv);
+int64_t srv_now_ns(void);
 
 #ifdef __cplusplus
 }

@@ -99,6 +99,18 @@ struct sim_stream {
     sim_stats stats;
     char last_error[256] = {0};
 
+    // window in flight (between the launch, check and order phases of a push)
+    struct Job {
+        bool active = false;
+        int K = 0;
+        int nbits = 0;
+        int max_slots = 0;
+        KeyLayout lay;
+        ChainArgs a;
+        int64_t t_last = 0;
+        uint64_t n_total = 0, n_valid = 0;
+    } job;
+
     // kernel timing (sim_set_kernel_timing)
     bool timing = false;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -230,9 +242,16 @@ void build_lut(sim_stream* s) {
 
 int check_mem_kind(int32_t k) { return (k == SIM_MEM_HOST || k == SIM_MEM_DEVICE) ? SIM_OK : SIM_E_INVAL; }
 
-// Runs one window of K intervals whose frames/flows are already on the device.
-int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
-               int K, uint64_t* n_new) {
+// A window of K intervals whose frames/flows are already on the device runs in three phases, so
+// that a batch of streams can interleave them: every stream's kernels are queued on its own HIP
+// stream before any host wait.
+//   launch: per-interval tables, counter resets, selection (or frame save), chain kernel, and an
+//           asynchronous read of the overflow counters;
+//   check:  wait for the counters; re-run overflowed chains after growing the arena until none
+//           overflows; concatenate the sub-arenas and read the event count asynchronously;
+//   order:  wait for the count; sort into the FIFO; advance the stream's state.
+int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
+               int K) {
     const int W = s->cfg.width, H = s->cfg.height;
     uint64_t max_delta = 0;
     for (int i = 0; i < K; ++i) {
@@ -259,7 +278,6 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
     HIP_TRY(s, hipMemsetAsync(s->d_reserve, 0,
                               (size_t)kArenaStripes * kCounterStride * sizeof(unsigned long long),
                               s->stream));
-
     const bool sparse = s->cfg.method == SIM_SPARSE;
     uint8_t* prev_out = s->d_prev[1 - s->cur];
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[0], s->stream));
@@ -316,15 +334,26 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
     a.lay = lay;
     const int max_slots = sparse ? kActStripes * s->act_cap : (int)s->npix;
 
+    s->job.active = true;
+    s->job.K = K;
+    s->job.nbits = nbits;
+    s->job.max_slots = max_slots;
+    s->job.lay = lay;
+    s->job.t_last = t_us[K - 1];
+    a.arena = s->d_arena;
+    a.stripe_cap = s->stripe_cap;
+    HIP_TRY(s, launch_chain(a, max_slots, s->stream));
+    if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s->stream));
+    s->job.a = a;
+    return SIM_OK;
+}
+
+int win_check(sim_stream* s) {
+    ChainArgs& a = s->job.a;
     bool first = true;
     for (;;) {
-        a.arena = s->d_arena;
-        a.stripe_cap = s->stripe_cap;
-        if (s->timing && !first) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
-        HIP_TRY(s, launch_chain(a, max_slots, s->stream));
-        if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
-        HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
-                                  hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(s, hipStreamSynchronize(s->stream));
         if (s->timing) {
             float ms = 0.0f;
@@ -353,6 +382,13 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
         HIP_TRY(s, launch_clamp(s->d_reserve, old, s->stream));
         HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, sizeof(unsigned long long), s->stream));
         s->stats.retries++;
+        a.arena = s->d_arena;
+        a.stripe_cap = s->stripe_cap;
+        if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
+        HIP_TRY(s, launch_chain(a, s->job.max_slots, s->stream));
+        if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
+        HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s->stream));
     }
     // every chain has finished: concatenate the sub-arenas, then order the events
     {
@@ -363,6 +399,10 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
                              s->d_counters + 2, s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 3 * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s->stream));
+    return SIM_OK;
+}
+
+int win_order(sim_stream* s, uint64_t* n_new) {
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const uint64_t n_total = s->h_counters[2];
     const uint64_t n_valid = n_total - s->h_counters[1];
@@ -377,10 +417,10 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
         cv.enabled = 1;
         cv.n_sentinel = s->d_counters + 1;
         cv.tbase = s->d_tbase;
-        cv.K = K;
-        cv.lay = lay;
+        cv.K = s->job.K;
+        cv.lay = s->job.lay;
         if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[3], s->stream));
-        HIP_TRY(s, launch_sort(s->d_alt, s->d_alt2, s->d_counters + 2, n_total, nbits,
+        HIP_TRY(s, launch_sort(s->d_alt, s->d_alt2, s->d_counters + 2, n_total, s->job.nbits,
                                s->d_hist, s->d_totals, s->d_fifo + s->fifo_tail, cv, s->stream));
         if (s->timing) {
             HIP_TRY(s, hipEventRecord(s->ev[4], s->stream));
@@ -393,12 +433,96 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
     }
     s->fifo_tail += n_valid;
     s->cur = 1 - s->cur;
-    s->t_prev = t_us[K - 1];
-    s->stats.intervals += (uint64_t)K;
-    s->stats.frames += (uint64_t)K;
+    s->t_prev = s->job.t_last;
+    s->stats.intervals += (uint64_t)s->job.K;
+    s->stats.frames += (uint64_t)s->job.K;
     s->stats.events += n_valid;
+    s->job.active = false;
     if (n_new) *n_new += n_valid;
     return SIM_OK;
+}
+
+// Argument and timestamp validation of a push (no state change, no device work).
+int push_validate(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
+                  const int64_t* t_us, int32_t mem_kind) {
+    if (!s) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    if (n_frames < 1 || !frames || !t_us || check_mem_kind(mem_kind)) return SIM_E_INVAL;
+    const int first = s->started ? 0 : 1;     // frames consumed by initialisation
+    const int n_int = n_frames - first;
+    if (n_int > 0 && s->S > 1 && !flows) return SIM_E_INVAL;
+    int64_t prev = s->started ? s->t_prev : t_us[0];
+    const int64_t epoch = s->started ? s->epoch : t_us[0];
+    for (int j = first; j < n_frames; ++j) {
+        if (t_us[j] <= prev) return SIM_E_ORDER;
+        if ((uint64_t)(t_us[j] - prev) >= kMaxInterval) return SIM_E_RANGE;
+        if (t_us[j] - epoch >= kMaxEpochSpan) return SIM_E_RANGE;
+        prev = t_us[j];
+    }
+    return SIM_OK;
+}
+
+struct Staged {
+    const uint8_t* frames = nullptr;   // device copy (or the caller's device pointer)
+    const float* flows = nullptr;
+    int first = 0;                     // frames consumed by initialisation
+    int n_int = 0;                     // intervals to simulate
+};
+
+// Copies host inputs to the device and initialises a fresh stream from its first frame.
+int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
+               const int64_t* t_us, int32_t mem_kind, Staged* out) {
+    const size_t fbytes = (size_t)s->npix;
+    const size_t flfloats = (size_t)s->npix * 2;
+    out->first = s->started ? 0 : 1;
+    out->n_int = n_frames - out->first;
+    out->frames = frames;
+    out->flows = flows;
+    if (mem_kind == SIM_MEM_HOST) {
+        uint64_t cap = s->stage_frames_cap;
+        int rc = grow(s, &s->d_stage_frames, &cap, (uint64_t)n_frames * fbytes, 0);
+        s->stage_frames_cap = (size_t)cap;
+        if (rc) return rc;
+        HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, frames, (size_t)n_frames * fbytes,
+                                  hipMemcpyHostToDevice, s->stream));
+        out->frames = s->d_stage_frames;
+        if (out->n_int > 0 && s->S > 1) {
+            cap = s->stage_flows_cap;
+            rc = grow(s, &s->d_stage_flows, &cap, (uint64_t)out->n_int * flfloats, 0);
+            s->stage_flows_cap = (size_t)cap;
+            if (rc) return rc;
+            HIP_TRY(s, hipMemcpyAsync(s->d_stage_flows, flows,
+                                      (size_t)out->n_int * flfloats * 4, hipMemcpyHostToDevice,
+                                      s->stream));
+            out->flows = s->d_stage_flows;
+        }
+    }
+    if (!s->started) {
+        HIP_TRY(s, launch_init(out->frames, s->d_lut, s->d_lref, s->d_prev[s->cur], s->npix,
+                               s->stream));
+        s->started = true;
+        s->epoch = t_us[0];
+        s->t_prev = t_us[0];
+        s->stats.frames += 1;
+    }
+    return SIM_OK;
+}
+
+const uint8_t* window_frames(const sim_stream* s, const Staged& st, int j) {
+    return st.frames + (size_t)(st.first + j) * (size_t)s->npix;
+}
+
+const float* window_flows(const sim_stream* s, const Staged& st, int j) {
+    return s->S > 1 ? st.flows + (size_t)j * 2 * (size_t)s->npix : nullptr;
+}
+
+int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
+               int K, uint64_t* n_new) {
+    int rc = win_launch(s, frames, flows, t_us, K);
+    if (!rc) rc = win_check(s);
+    if (!rc) rc = win_order(s, n_new);
+    if (rc) s->job.active = false;
+    return rc;
 }
 
 }  // namespace
@@ -552,67 +676,73 @@ int sim_clear_stats(sim_stream* s) {
 
 int sim_push_frames(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
                     const int64_t* t_us, int32_t mem_kind, uint64_t* n_new_events) {
-    if (!s) return SIM_E_INVAL;
-    if (s->poisoned) return SIM_E_POISONED;
     if (n_new_events) *n_new_events = 0;
-    if (n_frames < 1 || !frames || !t_us || check_mem_kind(mem_kind)) return SIM_E_INVAL;
-    const int first = s->started ? 0 : 1;     // frames consumed by initialisation
-    const int n_int = n_frames - first;
-    if (n_int > 0 && s->S > 1 && !flows) return SIM_E_INVAL;
-    // validate every timestamp before queueing any work
-    int64_t prev = s->started ? s->t_prev : t_us[0];
-    const int64_t epoch = s->started ? s->epoch : t_us[0];
-    for (int j = first; j < n_frames; ++j) {
-        if (t_us[j] <= prev) return SIM_E_ORDER;
-        if ((uint64_t)(t_us[j] - prev) >= kMaxInterval) return SIM_E_RANGE;
-        if (t_us[j] - epoch >= kMaxEpochSpan) return SIM_E_RANGE;
-        prev = t_us[j];
-    }
-    const size_t fbytes = (size_t)s->npix;
-    const size_t flfloats = (size_t)s->npix * 2;
-
-    // stage host inputs on the device
-    const uint8_t* dframes = frames;
-    const float* dflows = flows;
-    if (mem_kind == SIM_MEM_HOST) {
-        uint64_t cap = s->stage_frames_cap;
-        int rc = grow(s, &s->d_stage_frames, &cap, (uint64_t)n_frames * fbytes, 0);
-        s->stage_frames_cap = (size_t)cap;
-        if (rc) return rc;
-        HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, frames, (size_t)n_frames * fbytes,
-                                  hipMemcpyHostToDevice, s->stream));
-        dframes = s->d_stage_frames;
-        if (n_int > 0 && s->S > 1) {
-            cap = s->stage_flows_cap;
-            rc = grow(s, &s->d_stage_flows, &cap, (uint64_t)n_int * flfloats, 0);
-            s->stage_flows_cap = (size_t)cap;
-            if (rc) return rc;
-            HIP_TRY(s, hipMemcpyAsync(s->d_stage_flows, flows, (size_t)n_int * flfloats * 4,
-                                      hipMemcpyHostToDevice, s->stream));
-            dflows = s->d_stage_flows;
-        }
-    }
-
-    if (!s->started) {
-        HIP_TRY(s, launch_init(dframes, s->d_lut, s->d_lref, s->d_prev[s->cur], s->npix,
-                               s->stream));
-        s->started = true;
-        s->epoch = t_us[0];
-        s->t_prev = t_us[0];
-        s->stats.frames += 1;
-    }
+    int rc = push_validate(s, n_frames, frames, flows, t_us, mem_kind);
+    if (rc) return rc;
+    Staged st;
+    rc = push_stage(s, n_frames, frames, flows, t_us, mem_kind, &st);
+    if (rc) return rc;
     uint64_t total = 0;
-    for (int j = 0; j < n_int; j += kMaxWindow) {
-        const int K = std::min(kMaxWindow, n_int - j);
-        const uint8_t* wf = dframes + (size_t)(first + j) * fbytes;
-        const float* wfl = (s->S > 1) ? dflows + (size_t)j * flfloats : nullptr;
+    for (int j = 0; j < st.n_int; j += kMaxWindow) {
+        const int K = std::min(kMaxWindow, st.n_int - j);
         uint64_t nn = 0;
-        int rc = run_window(s, wf, wfl, t_us + first + j, K, &nn);
+        rc = run_window(s, window_frames(s, st, j), window_flows(s, st, j), t_us + st.first + j,
+                        K, &nn);
         if (rc) return rc;
         total += nn;
     }
     if (n_new_events) *n_new_events = total;
     return SIM_OK;
+}
+
+int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
+    if (!streams || !items || n < 0) return SIM_E_INVAL;
+    // validate everything (and reject a handle listed twice) before queueing any work
+    int first_err = SIM_OK;
+    for (int i = 0; i < n; ++i) {
+        items[i].n_new_events = 0;
+        items[i].status = push_validate(streams[i], items[i].n_frames, items[i].frames,
+                                        items[i].flows, items[i].t_us, items[i].mem_kind);
+        for (int j = 0; j < i && items[i].status == SIM_OK; ++j)
+            if (streams[j] == streams[i]) items[i].status = SIM_E_INVAL;
+        if (items[i].status && !first_err) first_err = items[i].status;
+    }
+    if (first_err) return first_err;
+    std::vector<Staged> st(n);
+    int max_int = 0;
+    for (int i = 0; i < n; ++i) {
+        sim_frames& it = items[i];
+        it.status = push_stage(streams[i], it.n_frames, it.frames, it.flows, it.t_us, it.mem_kind,
+                               &st[i]);
+        if (it.status && !first_err) first_err = it.status;
+        if (!it.status) max_int = std::max(max_int, st[i].n_int);
+    }
+    // window by window, each phase across every stream before the next phase: the launches of
+    // all streams are queued on their HIP streams before the host waits on any of them
+    for (int j = 0; j < max_int; j += kMaxWindow) {
+        for (int i = 0; i < n; ++i) {
+            sim_frames& it = items[i];
+            if (it.status || j >= st[i].n_int) continue;
+            const int K = std::min(kMaxWindow, st[i].n_int - j);
+            it.status = win_launch(streams[i], window_frames(streams[i], st[i], j),
+                                   window_flows(streams[i], st[i], j), it.t_us + st[i].first + j,
+                                   K);
+        }
+        for (int i = 0; i < n; ++i) {
+            sim_frames& it = items[i];
+            if (it.status || !streams[i]->job.active) continue;
+            it.status = win_check(streams[i]);
+        }
+        for (int i = 0; i < n; ++i) {
+            sim_frames& it = items[i];
+            if (!streams[i]->job.active) continue;
+            if (!it.status) it.status = win_order(streams[i], &it.n_new_events);
+            streams[i]->job.active = false;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (items[i].status && !first_err) first_err = items[i].status;
+    return first_err;
 }
 
 int sim_push_frame(sim_stream* s, const uint8_t* frame, const float* flow, int64_t t_us,

@@ -1,0 +1,309 @@
+// Continuous-batching server over the simulator's C ABI (srv_* in include/sim.h).
+//
+// Many virtual cameras, each with its own device-resident simulator state (reference levels,
+// previous frame, event buffers) and a device staging queue for frames that arrived and wait for
+// the GPU.  Cameras are admitted while their estimated HBM footprint fits the budget and a slot is
+// free; releasing a camera returns both.  srv_step() takes every queued frame of every camera and
+// runs them as one batched push (sim_push_batch), so different cameras' work overlaps on the
+// device while frames that arrive meanwhile wait for the next step.  Per frame, the latency from
+// its arrival stamp to the end of the step that ordered its events is recorded.
+#include <math.h>
+#include <string.h>
+#include <time.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/sim.h"
+#include "evsim_internal.h"
+
+namespace {
+
+struct Camera {
+    bool used = false;
+    sim_stream* s = nullptr;
+    sim_config cfg;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t footprint = 0;
+    int64_t npix = 0;
+    bool interp = false;          // needs flows
+    bool started = false;         // has received its first frame (in a push)
+    int q = 0;                    // frames queued in staging
+    uint8_t* d_frames = nullptr;  // [qcap][H][W]
+    float* d_flows = nullptr;     // [qcap][H][W][2], slot j = flow of the interval ending at frame j
+    std::vector<int64_t> t_us;
+    std::vector<int64_t> arrival_ns;
+    int64_t last_t = 0;
+    bool any_t = false;
+};
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+void release_camera(Camera& c) {
+    if (c.s) sim_destroy(c.s);
+    if (c.d_frames) (void)hipFree(c.d_frames);
+    if (c.d_flows) (void)hipFree(c.d_flows);
+    if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
+    c = Camera();
+}
+
+}  // namespace
+
+struct sim_server {
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    int qcap = 0;
+    std::vector<Camera> cams;
+    std::vector<float> lat_ms;     // per completed frame
+    sim_server_stats st;
+};
+
+extern "C" {
+
+int srv_footprint(const sim_config* cfg, int32_t queue_depth, uint64_t* bytes) {
+    if (!cfg || !bytes || queue_depth < 1) return SIM_E_INVAL;
+    if (cfg->width < 1 || cfg->height < 1 || cfg->width > 4096 || cfg->height > 4096)
+        return SIM_E_INVAL;
+    const uint64_t npix = (uint64_t)cfg->width * (uint64_t)cfg->height;
+    const bool sparse = cfg->method == SIM_SPARSE;
+    const bool interp = cfg->method != SIM_BASIC;
+    // reference levels 4, previous frames 2, chain resume points 4, event arena at its initial
+    // capacity of 2 keys per pixel 16, sort buffers 32, FIFO 16; sparse: selection masks 16 and
+    // active list 4; staging: one frame (+ flow) per queued slot
+    uint64_t per_px = 4 + 2 + 4 + 16 + 32 + 16 + (sparse ? 20 : 0);
+    per_px += (uint64_t)queue_depth * (1 + (interp ? 8 : 0));
+    *bytes = npix * per_px + (1u << 20);
+    return SIM_OK;
+}
+
+int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_depth,
+               sim_server** out) {
+    if (!out || max_cameras < 1 || max_cameras > 65536 || queue_depth < 1 || queue_depth > 128)
+        return SIM_E_INVAL;
+    *out = nullptr;
+    sim_server* srv = new (std::nothrow) sim_server();
+    if (!srv) return SIM_E_NOMEM;
+    srv->budget = hbm_budget_bytes;
+    srv->qcap = queue_depth;
+    try {
+        srv->cams.resize(max_cameras);
+    } catch (...) {
+        delete srv;
+        return SIM_E_NOMEM;
+    }
+    memset(&srv->st, 0, sizeof(srv->st));
+    srv->st.hbm_budget = hbm_budget_bytes;
+    *out = srv;
+    return SIM_OK;
+}
+
+int srv_destroy(sim_server* srv) {
+    if (!srv) return SIM_E_INVAL;
+    for (Camera& c : srv->cams)
+        if (c.used) release_camera(c);
+    delete srv;
+    return SIM_OK;
+}
+
+int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
+    if (!srv || !cfg || !cam) return SIM_E_INVAL;
+    *cam = -1;
+    uint64_t fp = 0;
+    int rc = srv_footprint(cfg, srv->qcap, &fp);
+    if (rc) return rc;
+    int slot = -1;
+    for (int i = 0; i < (int)srv->cams.size(); ++i)
+        if (!srv->cams[i].used) {
+            slot = i;
+            break;
+        }
+    if (slot < 0 || srv->used + fp > srv->budget) {
+        srv->st.rejected_admissions++;
+        return SIM_E_BUSY;
+    }
+    Camera c;
+    c.cfg = *cfg;
+    c.npix = (int64_t)cfg->width * cfg->height;
+    c.interp = cfg->method != SIM_BASIC;
+    c.footprint = fp;
+    if (cfg->hip_stream) {
+        c.stream = (hipStream_t)cfg->hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIM_E_NOMEM;
+        }
+        c.own_stream = true;
+        c.cfg.hip_stream = (void*)c.stream;
+    }
+    rc = sim_create(&c.cfg, &c.s);
+    bool ok = rc == SIM_OK;
+    ok = ok && hipMalloc((void**)&c.d_frames, (size_t)srv->qcap * c.npix) == hipSuccess;
+    if (ok && c.interp)
+        ok = hipMalloc((void**)&c.d_flows, (size_t)srv->qcap * c.npix * 2 * sizeof(float)) ==
+             hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        c.used = true;
+        release_camera(c);
+        return rc ? rc : SIM_E_NOMEM;
+    }
+    try {
+        c.t_us.resize(srv->qcap);
+        c.arrival_ns.resize(srv->qcap);
+    } catch (...) {
+        c.used = true;
+        release_camera(c);
+        return SIM_E_NOMEM;
+    }
+    c.used = true;
+    srv->cams[slot] = c;
+    srv->used += fp;
+    srv->st.cameras++;
+    srv->st.admissions++;
+    srv->st.hbm_used = srv->used;
+    *cam = slot;
+    return SIM_OK;
+}
+
+int srv_release(sim_server* srv, int32_t cam) {
+    if (!srv || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used)
+        return SIM_E_INVAL;
+    srv->used -= srv->cams[cam].footprint;
+    release_camera(srv->cams[cam]);
+    srv->st.cameras--;
+    srv->st.hbm_used = srv->used;
+    return SIM_OK;
+}
+
+int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* flow,
+               int64_t t_us, int32_t mem_kind, int64_t arrival_ns) {
+    if (!srv || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used || !frame)
+        return SIM_E_INVAL;
+    if (mem_kind != SIM_MEM_HOST && mem_kind != SIM_MEM_DEVICE) return SIM_E_INVAL;
+    Camera& c = srv->cams[cam];
+    const bool first_ever = !c.started && c.q == 0;
+    if (c.interp && !first_ever && !flow) return SIM_E_INVAL;
+    if (c.any_t && t_us <= c.last_t) return SIM_E_ORDER;
+    if (c.q >= srv->qcap) {
+        srv->st.rejected_frames++;
+        return SIM_E_BUSY;
+    }
+    const hipMemcpyKind k = mem_kind == SIM_MEM_HOST ? hipMemcpyHostToDevice
+                                                     : hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(c.d_frames + (size_t)c.q * c.npix, frame, (size_t)c.npix, k, c.stream) !=
+        hipSuccess)
+        return SIM_E_HIP;
+    if (c.interp && flow) {
+        if (hipMemcpyAsync(c.d_flows + (size_t)c.q * c.npix * 2, flow,
+                           (size_t)c.npix * 2 * sizeof(float), k, c.stream) != hipSuccess)
+            return SIM_E_HIP;
+    }
+    if (hipStreamSynchronize(c.stream) != hipSuccess)
+        return SIM_E_HIP;   // the caller may reuse or free its buffer once we return
+    c.t_us[c.q] = t_us;
+    c.arrival_ns[c.q] = arrival_ns ? arrival_ns : now_ns();
+    c.q++;
+    c.last_t = t_us;
+    c.any_t = true;
+    srv->st.submitted++;
+    return SIM_OK;
+}
+
+int srv_step(sim_server* srv, uint64_t* n_frames) {
+    if (!srv) return SIM_E_INVAL;
+    if (n_frames) *n_frames = 0;
+    std::vector<sim_stream*> handles;
+    std::vector<sim_frames> items;
+    std::vector<int> which;
+    for (int i = 0; i < (int)srv->cams.size(); ++i) {
+        Camera& c = srv->cams[i];
+        if (!c.used || c.q == 0) continue;
+        sim_frames it;
+        memset(&it, 0, sizeof(it));
+        it.n_frames = c.q;
+        it.mem_kind = SIM_MEM_DEVICE;
+        it.frames = c.d_frames;
+        // a camera's very first frame only initialises its state: its flow slot is unused
+        it.flows = c.interp ? (c.started ? c.d_flows : c.d_flows + (size_t)c.npix * 2) : nullptr;
+        it.t_us = c.t_us.data();
+        handles.push_back(c.s);
+        items.push_back(it);
+        which.push_back(i);
+    }
+    if (items.empty()) return SIM_OK;
+    const int rc = sim_push_batch(handles.data(), items.data(), (int32_t)items.size());
+    const int64_t done = now_ns();
+    uint64_t frames = 0;
+    for (size_t j = 0; j < items.size(); ++j) {
+        Camera& c = srv->cams[which[j]];
+        if (items[j].status == SIM_OK) {
+            for (int f = 0; f < c.q; ++f) {
+                srv->lat_ms.push_back((float)((double)(done - c.arrival_ns[f]) * 1e-6));
+            }
+            frames += (uint64_t)c.q;
+            srv->st.events += items[j].n_new_events;
+            c.started = true;
+        } else {
+            srv->st.failed_frames += (uint64_t)c.q;
+        }
+        c.q = 0;
+    }
+    srv->st.completed += frames;
+    srv->st.steps++;
+    if (n_frames) *n_frames = frames;
+    return rc;
+}
+
+int srv_drain(sim_server* srv, int32_t cam, uint64_t* dst, uint64_t max_events, int32_t mem_kind,
+              uint64_t* n_written) {
+    if (!srv || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used)
+        return SIM_E_INVAL;
+    return sim_drain_keys(srv->cams[cam].s, dst, max_events, mem_kind, n_written);
+}
+
+int srv_stream(sim_server* srv, int32_t cam, sim_stream** out) {
+    if (!srv || !out || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used)
+        return SIM_E_INVAL;
+    *out = srv->cams[cam].s;
+    return SIM_OK;
+}
+
+int srv_get_stats(sim_server* srv, sim_server_stats* out) {
+    if (!srv || !out) return SIM_E_INVAL;
+    *out = srv->st;
+    const size_t n = srv->lat_ms.size();
+    if (n) {
+        std::vector<float> v(srv->lat_ms);
+        auto pct = [&](double q) {
+            size_t k = (size_t)floor(q * (double)(n - 1) + 0.5);
+            std::nth_element(v.begin(), v.begin() + k, v.end());
+            return (double)v[k];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        out->max_ms = (double)*std::max_element(v.begin(), v.end());
+    }
+    return SIM_OK;
+}
+
+int srv_clear_stats(sim_server* srv) {
+    if (!srv) return SIM_E_INVAL;
+    const uint64_t cams = srv->st.cameras;
+    memset(&srv->st, 0, sizeof(srv->st));
+    srv->st.cameras = cams;
+    srv->st.hbm_budget = srv->budget;
+    srv->st.hbm_used = srv->used;
+    srv->lat_ms.clear();
+    return SIM_OK;
+}
+
+int64_t srv_now_ns(void) { return now_ns(); }
+
+}  // extern "C"

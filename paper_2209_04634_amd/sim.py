@@ -48,6 +48,20 @@ class SimStats(ctypes.Structure):
                 ("sort_launches", ctypes.c_uint64), ("sort_ms", ctypes.c_double)]
 
 
+class SimFrames(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("mem_kind", ctypes.c_int32),
+                ("frames", ctypes.c_void_p), ("flows", ctypes.c_void_p),
+                ("t_us", ctypes.c_void_p), ("n_new_events", ctypes.c_uint64),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "cameras", "admissions", "rejected_admissions", "submitted", "rejected_frames",
+        "completed", "failed_frames", "steps", "events", "hbm_used", "hbm_budget")] + \
+        [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
 EVENT_DTYPE = np.dtype([("t", "<i8"), ("x", "<u2"), ("y", "<u2"), ("p", "i1"), ("pad", "u1", 3)])
 assert EVENT_DTYPE.itemsize == ctypes.sizeof(SimEvent) == 16
 
@@ -90,6 +104,19 @@ def load() -> ctypes.CDLL:
         "sim_set_kernel_timing": (ctypes.c_int, [P, I32]),
         "sim_clear_stats": (ctypes.c_int, [P]),
         "sim_last_error": (ctypes.c_char_p, [P]),
+        "sim_push_batch": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(SimFrames), I32]),
+        "srv_footprint": (ctypes.c_int, [ctypes.POINTER(SimConfig), I32, PU64]),
+        "srv_create": (ctypes.c_int, [U64, I32, I32, ctypes.POINTER(P)]),
+        "srv_destroy": (ctypes.c_int, [P]),
+        "srv_admit": (ctypes.c_int, [P, ctypes.POINTER(SimConfig), ctypes.POINTER(I32)]),
+        "srv_release": (ctypes.c_int, [P, I32]),
+        "srv_submit": (ctypes.c_int, [P, I32, P, P, I64, I32, I64]),
+        "srv_step": (ctypes.c_int, [P, PU64]),
+        "srv_drain": (ctypes.c_int, [P, I32, P, U64, I32, PU64]),
+        "srv_stream": (ctypes.c_int, [P, I32, ctypes.POINTER(P)]),
+        "srv_get_stats": (ctypes.c_int, [P, ctypes.POINTER(ServerStats)]),
+        "srv_clear_stats": (ctypes.c_int, [P]),
+        "srv_now_ns": (I64, []),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -140,6 +167,28 @@ def _buffer(x, dtype, shape=None):
     return a.ctypes.data_as(ctypes.c_void_p), MEM_HOST, a
 
 
+def make_config(width: int, height: int, method: Union[str, int] = "basic",
+                transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
+                log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
+                event_capacity: int = 0, hip_stream=None) -> SimConfig:
+    lib = load()
+    cfg = SimConfig()
+    lib.sim_config_init(ctypes.byref(cfg))
+    cfg.width, cfg.height = int(width), int(height)
+    cfg.method = METHODS[method] if isinstance(method, str) else int(method)
+    cfg.transform = TRANSFORMS[transform] if isinstance(transform, str) else int(transform)
+    cfg.c_pos, cfg.c_neg, cfg.log_eps = float(c_pos), float(c_neg), float(log_eps)
+    cfg.n_interp, cfg.mask_threshold = int(n_interp), float(mask_threshold)
+    cfg.event_capacity = int(event_capacity)
+    if hip_stream == "torch":
+        import torch
+        hip_stream = torch.cuda.current_stream().cuda_stream
+    elif hip_stream is not None and hasattr(hip_stream, "cuda_stream"):
+        hip_stream = hip_stream.cuda_stream
+    cfg.hip_stream = ctypes.c_void_p(int(hip_stream)) if hip_stream else None
+    return cfg
+
+
 class Stream:
     """One simulated event camera (a sim_stream handle)."""
 
@@ -148,20 +197,8 @@ class Stream:
                  log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
                  event_capacity: int = 0, hip_stream=None):
         lib = load()
-        cfg = SimConfig()
-        lib.sim_config_init(ctypes.byref(cfg))
-        cfg.width, cfg.height = int(width), int(height)
-        cfg.method = METHODS[method] if isinstance(method, str) else int(method)
-        cfg.transform = TRANSFORMS[transform] if isinstance(transform, str) else int(transform)
-        cfg.c_pos, cfg.c_neg, cfg.log_eps = float(c_pos), float(c_neg), float(log_eps)
-        cfg.n_interp, cfg.mask_threshold = int(n_interp), float(mask_threshold)
-        cfg.event_capacity = int(event_capacity)
-        if hip_stream == "torch":
-            import torch
-            hip_stream = torch.cuda.current_stream().cuda_stream
-        elif hip_stream is not None and hasattr(hip_stream, "cuda_stream"):
-            hip_stream = hip_stream.cuda_stream
-        cfg.hip_stream = ctypes.c_void_p(int(hip_stream)) if hip_stream else None
+        cfg = make_config(width, height, method, transform, c_pos, c_neg, log_eps, n_interp,
+                          mask_threshold, event_capacity, hip_stream)
         h = ctypes.c_void_p()
         _check(lib.sim_create(ctypes.byref(cfg), ctypes.byref(h)), "sim_create")
         self._h = h
@@ -283,6 +320,123 @@ class Stream:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def push_batch(entries) -> list:
+    """Batched push: entries is a sequence of (stream, frames, flows, t_us).  Same result as one
+    push_frames per stream; the streams' GPU work overlaps.  Returns the per-stream event counts
+    and raises SimError (with the first failing stream's status) on error."""
+    lib = load()
+    n = len(entries)
+    handles = (ctypes.c_void_p * n)()
+    items = (SimFrames * n)()
+    keep = []
+    for i, (stream, frames, flows, t_us) in enumerate(entries):
+        H, W = stream.height, stream.width
+        nf = int(frames.shape[0])
+        fp, fk, fa = _buffer(frames, np.uint8, (nf, H, W))
+        lp, lk, la = _buffer(flows, np.float32, None)
+        if lk is not None and lk != fk:
+            raise ValueError("frames and flows must both be host or both be device memory")
+        t = np.ascontiguousarray(np.asarray(t_us, dtype=np.int64))
+        if t.shape != (nf,):
+            raise ValueError("need one timestamp per frame")
+        keep += [fa, la, t]
+        handles[i] = stream._h
+        items[i].n_frames = nf
+        items[i].mem_kind = fk
+        items[i].frames = fp
+        items[i].flows = lp
+        items[i].t_us = t.ctypes.data_as(ctypes.c_void_p)
+    rc = lib.sim_push_batch(handles, items, n)
+    if rc != OK:
+        bad = next((i for i in range(n) if items[i].status != OK), None)
+        where = "sim_push_batch" if bad is None else f"sim_push_batch (stream {bad})"
+        _check(rc, where, None if bad is None else entries[bad][0]._h)
+    return [items[i].n_new_events for i in range(n)]
+
+
+class Server:
+    """Continuous-batching server of many virtual cameras (srv_* in include/sim.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_cameras: int = 256, queue_depth: int = 8):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.srv_create(int(hbm_budget_bytes), int(max_cameras), int(queue_depth),
+                                    ctypes.byref(h)), "srv_create")
+        self._h = h
+        self.queue_depth = int(queue_depth)
+        self._shape = {}
+
+    @staticmethod
+    def footprint(queue_depth: int = 8, **cfg) -> int:
+        c = make_config(**cfg)
+        out = ctypes.c_uint64()
+        _check(load().srv_footprint(ctypes.byref(c), int(queue_depth), ctypes.byref(out)),
+               "srv_footprint")
+        return out.value
+
+    def admit(self, **cfg) -> int:
+        """Admits a camera (keyword arguments as Stream); raises SimError(E_BUSY) when it does
+        not fit the HBM budget or no slot is free."""
+        c = make_config(**cfg)
+        cam = ctypes.c_int32()
+        _check(self._lib.srv_admit(self._h, ctypes.byref(c), ctypes.byref(cam)), "srv_admit")
+        self._shape[cam.value] = (c.height, c.width)
+        return cam.value
+
+    def release(self, cam: int) -> None:
+        _check(self._lib.srv_release(self._h, int(cam)), "srv_release")
+        self._shape.pop(int(cam), None)
+
+    def submit(self, cam: int, frame, flow=None, t_us: int = 0, arrival_ns: int = 0) -> None:
+        H, W = self._shape[int(cam)]
+        fp, fk, fa = _buffer(frame, np.uint8, (H, W))
+        lp, lk, la = _buffer(flow, np.float32, (H, W, 2))
+        if lk is not None and lk != fk:
+            raise ValueError("frame and flow must both be host or both be device memory")
+        _check(self._lib.srv_submit(self._h, int(cam), fp, lp, int(t_us), fk, int(arrival_ns)),
+               "srv_submit")
+
+    def step(self) -> int:
+        n = ctypes.c_uint64()
+        _check(self._lib.srv_step(self._h, ctypes.byref(n)), "srv_step")
+        return n.value
+
+    def drain_keys(self, cam: int, max_events: Optional[int] = None) -> np.ndarray:
+        s = ctypes.c_void_p()
+        _check(self._lib.srv_stream(self._h, int(cam), ctypes.byref(s)), "srv_stream")
+        pend = ctypes.c_uint64()
+        _check(self._lib.sim_pending_events(s, ctypes.byref(pend)), "sim_pending_events")
+        n = pend.value if max_events is None else int(max_events)
+        arr = np.zeros(n, dtype=np.uint64)
+        got = ctypes.c_uint64()
+        _check(self._lib.srv_drain(self._h, int(cam), arr.ctypes.data_as(ctypes.c_void_p), n,
+                                   MEM_HOST, ctypes.byref(got)), "srv_drain")
+        return arr[:got.value]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.srv_get_stats(self._h, ctypes.byref(st)), "srv_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def clear_stats(self) -> None:
+        _check(self._lib.srv_clear_stats(self._h), "srv_clear_stats")
+
+    def now_ns(self) -> int:
+        return int(self._lib.srv_now_ns())
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.srv_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def decode_keys(keys: np.ndarray, epoch: int = 0):

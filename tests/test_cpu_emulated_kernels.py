@@ -133,6 +133,128 @@ def test_emulated_degenerate_shapes(emu_sim, shape):
         check(emu_sim, frames, flows, np.array([0, 900, 2100]), method=method, n_interp=4)
 
 
+def test_emulated_batched_push_equals_streams_alone(emu_sim):
+    """A batch mixing resolutions and methods gives each stream exactly its solo result, and
+    pushing the batch twice continues every stream's state."""
+    specs = [((48, 32), emu_sim.DENSE, 1), ((40, 24), emu_sim.SPARSE, 2), ((33, 17), emu_sim.BASIC, 3),
+             ((64, 40), emu_sim.SPARSE, 4)]
+    vids, solo = [], []
+    for (W, H), method, seed in specs:
+        v = synth.blob_video(synth.BlobVideoSpec(W, H, 7, 30.0, 6, seed=seed, motion="random",
+                                                 speed_max=5.0))
+        vids.append(v)
+        flows = None if method == emu_sim.BASIC else v.flows
+        solo.append(oracle_run(v.frames, flows, v.t_us, method=method, c_pos=0.15, c_neg=0.15,
+                               n_interp=5))
+    streams = [emu_sim.Stream(W, H, method=m, c_pos=0.15, c_neg=0.15, n_interp=5,
+                              event_capacity=64)
+               for (W, H), m, _ in specs]
+    # first half of every sequence, then the second half, each as one batch
+    for a, b in ((0, 4), (4, 7)):
+        entries = []
+        for st, v, ((W, H), m, _) in zip(streams, vids, specs):
+            fl = None
+            if m != emu_sim.BASIC:
+                fl = v.flows[max(a - 1, 0):b - 1]
+            entries.append((st, v.frames[a:b], fl, v.t_us[a:b]))
+        emu_sim.push_batch(entries)
+    for st, (ok, oref) in zip(streams, solo):
+        np.testing.assert_array_equal(st.drain_keys(), ok)
+        np.testing.assert_array_equal(st.reference(), oref)
+        st.close()
+
+
+def test_emulated_batch_validation_is_all_or_nothing(emu_sim):
+    v = synth.blob_video(synth.BlobVideoSpec(20, 12, 3, 30.0, 2, seed=1))
+    a = emu_sim.Stream(20, 12, method="dense")
+    b = emu_sim.Stream(20, 12, method="dense")
+    with pytest.raises(emu_sim.SimError) as e:
+        emu_sim.push_batch([(a, v.frames, v.flows, v.t_us), (b, v.frames, v.flows, v.t_us[::-1])])
+    assert e.value.status == emu_sim.E_ORDER
+    assert a.pending() == 0 and b.pending() == 0
+    with pytest.raises(emu_sim.SimError):
+        emu_sim.push_batch([(a, v.frames, v.flows, v.t_us), (a, v.frames, v.flows, v.t_us)])
+    emu_sim.push_batch([(a, v.frames, v.flows, v.t_us), (b, v.frames, v.flows, v.t_us)])
+    np.testing.assert_array_equal(a.drain_keys(), b.drain_keys())
+
+
+def _camera_videos(emu):
+    cams = [((40, 24), "dense", 11), ((33, 21), "sparse", 12), ((28, 16), "basic", 13),
+            ((48, 30), "sparse", 14)]
+    out = []
+    for (W, H), method, seed in cams:
+        v = synth.blob_video(synth.BlobVideoSpec(W, H, 9, 30.0, 5, seed=seed, motion="random",
+                                                 speed_max=5.0))
+        m = emu.METHODS[method]
+        flows = None if method == "basic" else v.flows
+        ok, oref = oracle_run(v.frames, flows, v.t_us, method=m, c_pos=0.15, c_neg=0.15,
+                              n_interp=4)
+        out.append(dict(W=W, H=H, method=method, v=v, ok=ok, oref=oref))
+    return out
+
+
+def test_emulated_server_results_match_cameras_alone(emu_sim):
+    """Frames of four cameras (mixed resolution and method) arrive interleaved; steps run at
+    irregular points, so batches mix cameras at different positions of their sequences.  Every
+    camera's events equal the oracle's for that camera alone."""
+    cams = _camera_videos(emu_sim)
+    srv = emu_sim.Server(hbm_budget_bytes=1 << 34, max_cameras=8, queue_depth=4)
+    ids = [srv.admit(width=c["W"], height=c["H"], method=c["method"], c_pos=0.15, c_neg=0.15,
+                     n_interp=4, event_capacity=16) for c in cams]
+    rng = np.random.default_rng(0)
+    pos = [0] * len(cams)
+    while any(p < 9 for p in pos):
+        i = int(rng.integers(len(cams)))
+        if pos[i] >= 9:
+            continue
+        c, k = cams[i], pos[i]
+        flow = None if (c["method"] == "basic" or k == 0) else c["v"].flows[k - 1]
+        try:
+            srv.submit(ids[i], c["v"].frames[k], flow, int(c["v"].t_us[k]))
+            pos[i] += 1
+        except emu_sim.SimError as e:
+            assert e.status == emu_sim.E_BUSY       # queue full: step, then retry
+            srv.step()
+        if rng.random() < 0.3:
+            srv.step()
+    srv.step()
+    for cid, c in zip(ids, cams):
+        np.testing.assert_array_equal(srv.drain_keys(cid), c["ok"])
+    st = srv.stats()
+    assert st["completed"] == 9 * len(cams) and st["failed_frames"] == 0
+    assert 0 <= st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    srv.close()
+
+
+def test_emulated_server_admission_by_footprint(emu_sim):
+    fp = emu_sim.Server.footprint(queue_depth=2, width=64, height=48, method="sparse")
+    srv = emu_sim.Server(hbm_budget_bytes=2 * fp + fp // 2, max_cameras=8, queue_depth=2)
+    a = srv.admit(width=64, height=48, method="sparse")
+    b = srv.admit(width=64, height=48, method="sparse")
+    with pytest.raises(emu_sim.SimError) as e:
+        srv.admit(width=64, height=48, method="sparse")
+    assert e.value.status == emu_sim.E_BUSY
+    st = srv.stats()
+    assert st["cameras"] == 2 and st["rejected_admissions"] == 1 and st["hbm_used"] == 2 * fp
+    srv.release(a)
+    c = srv.admit(width=64, height=48, method="sparse")          # memory freed: admitted
+    assert c == a
+    # queue depth 2: a third frame before a step is refused, and timestamps must increase
+    f = np.zeros((48, 64), np.uint8)
+    fl = np.zeros((48, 64, 2), np.float32)
+    srv.submit(b, f, None, 0)
+    srv.submit(b, f, fl, 10)
+    with pytest.raises(emu_sim.SimError) as e:
+        srv.submit(b, f, fl, 20)
+    assert e.value.status == emu_sim.E_BUSY
+    assert srv.step() == 2
+    with pytest.raises(emu_sim.SimError) as e:
+        srv.submit(b, f, fl, 10)
+    assert e.value.status == emu_sim.E_ORDER
+    assert srv.stats()["rejected_frames"] == 1
+    srv.close()
+
+
 ASAN_SCRIPT = textwrap.dedent("""
     import sys, numpy as np
     sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
@@ -153,6 +275,20 @@ ASAN_SCRIPT = textwrap.dedent("""
     rng = np.random.default_rng(1)
     f, fl = synth.random_frames(rng, 3, 5, 7)
     cases.append((f, fl, np.array([0, 10, 20]), dict(method=1, n_interp=40, event_capacity=1)))
+    from test_cpu_emulated_kernels import _camera_videos
+    cams = _camera_videos(sim)
+    srv = sim.Server(hbm_budget_bytes=1 << 34, max_cameras=4, queue_depth=3)
+    ids = [srv.admit(width=c["W"], height=c["H"], method=c["method"], c_pos=0.15, c_neg=0.15,
+                     n_interp=4, event_capacity=8) for c in cams]
+    for k in range(9):
+        for cid, c in zip(ids, cams):
+            fl = None if (c["method"] == "basic" or k == 0) else c["v"].flows[k - 1]
+            srv.submit(cid, c["v"].frames[k], fl, int(c["v"].t_us[k]))
+        if k % 3 == 2:
+            srv.step()
+    for cid, c in zip(ids, cams):
+        assert np.array_equal(srv.drain_keys(cid), c["ok"])
+    srv.close()
     for frames, flows, t, cfg in cases:
         ocfg = dict((k, v) for k, v in cfg.items() if k != "event_capacity")
         ok, oref = oracle_run(frames, flows, t, **ocfg)
