@@ -3,4 +3,5 @@
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may import this package.  The
 product library never loads it and shares no code with it.
 """
-from .oracle import OracleSim, build, lut, run_sequence, BASIC, DENSE, SPARSE, LOG, LINEAR  # noqa: F401
+from .oracle import (OracleSim, accumulate, build, event_rate, lut, run_sequence,  # noqa: F401
+                     BASIC, DENSE, SPARSE, DIFFERENCE, LOG, LINEAR, REFERENCE, MEMORYLESS)

@@ -17,7 +17,13 @@
  *   - Temporal up-sampling by flow-driven linear interpolation of intermediate frames (Sec. III,
  *     Sec. III-A); sparse variant interpolates only pixels whose frame-to-frame change passes a
  *     threshold, unselected pixels emit nothing (Sec. III-B, Sec. IV-B discussion).
- *   - Output: events <x, y, t, p> (Sec. III-A, Fig. 1 caption).
+ *   - Output: events <x, y, t, p> (Sec. III-A, Fig. 1 caption), or a frame of accumulated events
+ *     (same caption); the events/(pixel s) statistic of the statistical comparison (Sec. IV-C).
+ *   - Memoryless thresholding: every difference of consecutive (interpolated) frames is compared
+ *     with C_pos / C_neg on its own, strictly, one event at most per pixel and sub-frame
+ *     (Sec. III-A threshold equations, taken literally).
+ *   - Difference-frame interpolation: from three consecutive frames, two difference frames; the
+ *     flow between them interpolates further difference frames, each thresholded (Sec. III-C).
  *
  * Readings where the paper is silent:
  *   log transform ln(v/255 + eps) via a 256-entry table; interpolation of the transformed frames;
@@ -26,7 +32,15 @@
  *   with ties counted (>= C_pos, <= -C_neg); crossing times linear within a sub-interval, floored
  *   to integer microseconds; backlog crossings stamped at the sub-interval start; sparse selection
  *   |L1 - L0| >= m; first frame initialises state only; canonical order by (t, y, x, p) per
- *   interval, intervals in push order.
+ *   interval, intervals in push order.  Memoryless mode: strict > C_pos / < -C_neg on each
+ *   difference of consecutive samples, stamped at the later sample's time t0 + floor(k/S delta),
+ *   no reference level.  Difference method: events from the third frame on (the second gives the
+ *   first difference frame only); the supplied flow of an interval is the flow from the previous
+ *   difference frame to the current one; difference frames of transformed frames; always
+ *   memoryless; interpolated difference frames are not rescaled (the paper's larger thresholds
+ *   for this method, Table I, fit unscaled frames).  Accumulated frame: counts per pixel and
+ *   polarity over a half-open time window.  Events/(pixel s): mean and population standard
+ *   deviation over all pixels of the per-pixel count divided by the window length.
  *
  * Parity is pinned (tests/test_oracle_*.py) by: the exhaustive table check against an exact
  * logarithm, zero-event invariants, the closed-form per-pixel count floor(|dL|/C) of the basic
@@ -48,8 +62,9 @@
 #define OR_E_NOMEM (-3)
 #define OR_E_RANGE (-4)
 
-enum { OR_BASIC = 0, OR_DENSE = 1, OR_SPARSE = 2 };
+enum { OR_BASIC = 0, OR_DENSE = 1, OR_SPARSE = 2, OR_DIFFERENCE = 3 };
 enum { OR_LOG = 0, OR_LINEAR = 1 };
+enum { OR_REFERENCE = 0, OR_MEMORYLESS = 1 };
 
 typedef struct {
     int32_t width, height;
@@ -58,6 +73,8 @@ typedef struct {
     float log_eps;
     int32_t n_interp;        /* N interpolated frames; S = N + 1 (basic: S = 1) */
     float mask_threshold;    /* sparse: < 0 -> min(c_pos, c_neg) */
+    int32_t thresh_mode;     /* OR_REFERENCE or OR_MEMORYLESS; the difference method is always
+                                memoryless */
 } oracle_cfg;
 
 typedef struct {
@@ -66,6 +83,8 @@ typedef struct {
     float m;                 /* sparse selection threshold */
     float lut[256];
     uint8_t* prev;           /* previous camera frame */
+    uint8_t* prev2;          /* the frame before it (difference method) */
+    uint64_t n_int;          /* intervals pushed so far */
     float* lref;             /* per-pixel reference level */
     float* L0;               /* scratch: transformed previous frame */
     float* L1;               /* scratch: transformed current frame */
@@ -95,7 +114,8 @@ int oracle_lut(int32_t transform, float log_eps, float* lut) {
 
 static void or_destroy(oracle_sim* s) {
     if (!s) return;
-    free(s->prev); free(s->lref); free(s->L0); free(s->L1); free(s->V); free(s->ev);
+    free(s->prev); free(s->prev2); free(s->lref); free(s->L0); free(s->L1); free(s->V);
+    free(s->ev);
     free(s);
 }
 
@@ -106,7 +126,8 @@ int oracle_create(const oracle_cfg* cfg, oracle_sim** out) {
     *out = NULL;
     if (cfg->width < 1 || cfg->height < 1 || cfg->width > 4096 || cfg->height > 4096)
         return OR_E_INVAL;
-    if (cfg->method < OR_BASIC || cfg->method > OR_SPARSE) return OR_E_INVAL;
+    if (cfg->method < OR_BASIC || cfg->method > OR_DIFFERENCE) return OR_E_INVAL;
+    if (cfg->thresh_mode != OR_REFERENCE && cfg->thresh_mode != OR_MEMORYLESS) return OR_E_INVAL;
     if (!(cfg->c_pos > 0.0f) || !(cfg->c_neg > 0.0f)) return OR_E_INVAL;
     if (cfg->n_interp < 0 || cfg->n_interp > 255) return OR_E_INVAL;
     oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
@@ -117,11 +138,15 @@ int oracle_create(const oracle_cfg* cfg, oracle_sim** out) {
     s->m = cfg->mask_threshold < 0.0f ? fminf(cfg->c_pos, cfg->c_neg) : cfg->mask_threshold;
     size_t n = (size_t)cfg->width * (size_t)cfg->height;
     s->prev = (uint8_t*)malloc(n);
+    s->prev2 = (uint8_t*)malloc(n);
     s->lref = (float*)malloc(n * sizeof(float));
     s->L0 = (float*)malloc(n * sizeof(float));
     s->L1 = (float*)malloc(n * sizeof(float));
     s->V = (float*)malloc((size_t)(s->S + 1) * sizeof(float));
-    if (!s->prev || !s->lref || !s->L0 || !s->L1 || !s->V) { or_destroy(s); return OR_E_NOMEM; }
+    if (!s->prev || !s->prev2 || !s->lref || !s->L0 || !s->L1 || !s->V) {
+        or_destroy(s);
+        return OR_E_NOMEM;
+    }
     *out = s;
     return OR_OK;
 }
@@ -162,6 +187,54 @@ static int cmp_u64(const void* a, const void* b) {
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
+/* Difference-frame interpolation (Sec. III-C) for the interval (t0, t0 + delta]: difference frames
+ * D1 = T[prev] - T[prev2] and D2 = T[frame] - T[prev]; with the flow F between them, the
+ * interpolated difference frame at tau = k / S is (1 - tau) * D1(p - tau F) + tau * D2(p +
+ * (1 - tau) F) (the same gather-form blend and clamp-to-edge bilinear sampling as the frame
+ * methods, applied to difference frames); D_S = D2.  Each of D_1 .. D_S is thresholded on its
+ * own (> C_pos: positive, < -C_neg: negative) and its events are stamped at t0 + floor(k/S delta).
+ * On allocation failure n_ev is set to all ones. */
+static void difference_events(oracle_sim* s, const uint8_t* frame, const float* flow, int64_t t0,
+                              float delta) {
+    const int W = s->cfg.width, H = s->cfg.height, S = s->S;
+    const size_t n = (size_t)W * (size_t)H;
+    const float cp = s->cfg.c_pos, cn = s->cfg.c_neg;
+    float* D1 = s->L0;
+    float* D2 = s->L1;
+    for (size_t i = 0; i < n; ++i) {
+        D1[i] = s->lut[s->prev[i]] - s->lut[s->prev2[i]];
+        D2[i] = s->lut[frame[i]] - s->lut[s->prev[i]];
+    }
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const size_t p = (size_t)y * W + x;
+            for (int k = 1; k <= S; ++k) {
+                float Dk;
+                if (k == S) {
+                    Dk = D2[p];
+                } else {
+                    const float u = flow[2 * p], v = flow[2 * p + 1];
+                    const float tau = (float)k / (float)S;
+                    const float om = 1.0f - tau;
+                    const float a = bil(D1, W, H, (float)x - tau * u, (float)y - tau * v);
+                    const float b = bil(D2, W, H, (float)x + om * u, (float)y + om * v);
+                    Dk = om * a + tau * b;
+                }
+                int pol = 0;
+                if (Dk > cp) pol = 1;
+                else if (Dk < -cn) pol = -1;
+                if (!pol) continue;
+                const float phi = (float)k / (float)S;
+                const int64_t t = t0 + (int64_t)floorf(phi * delta);
+                if (push_event(s, t, x, y, pol) != OR_OK) {
+                    s->n_ev = (uint64_t)-1;
+                    return;
+                }
+            }
+        }
+    }
+}
+
 /* Push one camera frame taken at t_us.  The first frame only initialises the reference levels.
  * For later frames, the interval (t_prev, t_us] is simulated and its events are left, sorted by
  * key, in the internal buffer (oracle_events).  flow is [H][W][2] (dx, dy) in pixels per interval,
@@ -184,11 +257,27 @@ int oracle_push(oracle_sim* s, const uint8_t* frame, const float* flow, int64_t 
     }
     if (t_us <= s->t_prev) return OR_E_ORDER;
     if (t_us - s->epoch >= ((int64_t)1 << 39)) return OR_E_RANGE;
-    if (s->cfg.method != OR_BASIC && !flow) return OR_E_INVAL;
+    const int diff = s->cfg.method == OR_DIFFERENCE;
+    /* the difference method's first interval has one difference frame only: nothing to
+     * interpolate and no flow needed */
+    const int diff_first = diff && s->n_int == 0;
+    if (s->cfg.method != OR_BASIC && !diff_first && !flow) return OR_E_INVAL;
 
     const int64_t t0 = s->t_prev;
     const float delta = (float)(t_us - t0);
     const float cp = s->cfg.c_pos, cn = s->cfg.c_neg;
+    if (diff) {
+        if (!diff_first) difference_events(s, frame, flow, t0, delta);
+        if (s->n_ev == (uint64_t)-1) return OR_E_NOMEM;
+        qsort(s->ev, s->n_ev, sizeof(uint64_t), cmp_u64);
+        memcpy(s->prev2, s->prev, n);
+        memcpy(s->prev, frame, n);
+        s->t_prev = t_us;
+        s->n_int++;
+        if (n_events) *n_events = s->n_ev;
+        return OR_OK;
+    }
+    const int memoryless = s->cfg.thresh_mode == OR_MEMORYLESS;
     for (size_t i = 0; i < n; ++i) {
         s->L0[i] = s->lut[s->prev[i]];
         s->L1[i] = s->lut[frame[i]];
@@ -214,6 +303,21 @@ int oracle_push(oracle_sim* s, const uint8_t* frame, const float* flow, int64_t 
                     const float b = bil(s->L1, W, H, (float)x + om * u, (float)y + om * v);
                     V[k] = om * a + tau * b;
                 }
+            }
+            if (memoryless) {
+                /* each difference of consecutive samples on its own: one event at most, stamped
+                 * at the later sample's time */
+                for (int k = 0; k < S; ++k) {
+                    const float D = V[k + 1] - V[k];
+                    int pol = 0;
+                    if (D > cp) pol = 1;
+                    else if (D < -cn) pol = -1;
+                    if (!pol) continue;
+                    const float phi = (float)(k + 1) / (float)S;
+                    const int64_t t = t0 + (int64_t)floorf(phi * delta);
+                    if (push_event(s, t, x, y, pol) != OR_OK) return OR_E_NOMEM;
+                }
+                continue;
             }
             /* threshold crossings against the reference level, sub-interval by sub-interval */
             float R = s->lref[p];
@@ -243,8 +347,10 @@ int oracle_push(oracle_sim* s, const uint8_t* frame, const float* flow, int64_t 
         }
     }
     qsort(s->ev, s->n_ev, sizeof(uint64_t), cmp_u64);
+    memcpy(s->prev2, s->prev, n);
     memcpy(s->prev, frame, n);
     s->t_prev = t_us;
+    s->n_int++;
     if (n_events) *n_events = s->n_ev;
     return OR_OK;
 }
@@ -286,4 +392,43 @@ int oracle_pixel_samples(const oracle_sim* s, const uint8_t* f0, const uint8_t* 
     }
     free(L0); free(L1);
     return OR_OK;
+}
+
+/* Frame of accumulated events (Fig. 1 caption): for every key whose time t = epoch + (key >> 25)
+ * lies in [t_begin, t_end), adds one to counts[0][y][x] for a positive event or to
+ * counts[1][y][x] for a negative one.  counts is uint32 [2][H][W]. */
+void oracle_accumulate(const uint64_t* keys, uint64_t n, int64_t epoch, int64_t t_begin,
+                       int64_t t_end, int W, int H, uint32_t* counts) {
+    const size_t plane = (size_t)W * (size_t)H;
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t k = keys[i];
+        const int64_t t = epoch + (int64_t)(k >> 25);
+        if (t < t_begin || t >= t_end) continue;
+        const int y = (int)((k >> 13) & 0xFFF);
+        const int x = (int)((k >> 1) & 0xFFF);
+        const int pos = (int)(k & 1);
+        counts[(pos ? 0 : 1) * plane + (size_t)y * W + x] += 1;
+    }
+}
+
+/* Events per pixel and second over a window of `seconds` (the statistic of Sec. IV-C): with c the
+ * per-pixel event count (both polarities) of every pixel of the sensor, the mean of c / seconds
+ * and its population standard deviation over the pixels, from the exact integer sums
+ * S1 = sum c and S2 = sum c^2:  m1 = S1 / npix,  m2 = S2 / npix,
+ * mean = m1 / seconds,  std = sqrt(max(m2 - m1 * m1, 0)) / seconds  (double precision). */
+void oracle_event_rate(const uint32_t* counts, int W, int H, double seconds, double* mean,
+                       double* stddev, uint64_t* sums) {
+    const size_t plane = (size_t)W * (size_t)H;
+    uint64_t s1 = 0, s2 = 0;
+    for (size_t p = 0; p < plane; ++p) {
+        const uint64_t c = (uint64_t)counts[p] + (uint64_t)counts[plane + p];
+        s1 += c;
+        s2 += c * c;
+    }
+    const double m1 = (double)s1 / (double)plane;
+    const double m2 = (double)s2 / (double)plane;
+    const double var = m2 - m1 * m1;
+    *mean = m1 / seconds;
+    *stddev = sqrt(var > 0.0 ? var : 0.0) / seconds;
+    if (sums) { sums[0] = s1; sums[1] = s2; }
 }

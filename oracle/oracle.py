@@ -13,8 +13,9 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
-BASIC, DENSE, SPARSE = 0, 1, 2
+BASIC, DENSE, SPARSE, DIFFERENCE = 0, 1, 2, 3
 LOG, LINEAR = 0, 1
+REFERENCE, MEMORYLESS = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -31,7 +32,7 @@ class _Cfg(ctypes.Structure):
                 ("method", ctypes.c_int32), ("transform", ctypes.c_int32),
                 ("c_pos", ctypes.c_float), ("c_neg", ctypes.c_float),
                 ("log_eps", ctypes.c_float), ("n_interp", ctypes.c_int32),
-                ("mask_threshold", ctypes.c_float)]
+                ("mask_threshold", ctypes.c_float), ("thresh_mode", ctypes.c_int32)]
 
 
 _lib = None
@@ -51,6 +52,13 @@ def _bind(lib):
     lib.oracle_lref.argtypes = [P, P]
     lib.oracle_pixel_samples.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int, P]
     lib.oracle_destroy.argtypes = [P]
+    lib.oracle_accumulate.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int, ctypes.c_int, P]
+    lib.oracle_accumulate.restype = None
+    lib.oracle_event_rate.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), P]
+    lib.oracle_event_rate.restype = None
     return lib
 
 
@@ -82,10 +90,10 @@ def lut(transform: int = LOG, log_eps: float = 1e-3) -> np.ndarray:
 class OracleSim:
     def __init__(self, width: int, height: int, method: int = BASIC, transform: int = LOG,
                  c_pos: float = 0.2, c_neg: float = 0.2, log_eps: float = 1e-3,
-                 n_interp: int = 10, mask_threshold: float = -1.0):
+                 n_interp: int = 10, mask_threshold: float = -1.0, thresh_mode: int = REFERENCE):
         self.width, self.height = width, height
         cfg = _Cfg(width, height, method, transform, c_pos, c_neg, log_eps, n_interp,
-                   mask_threshold)
+                   mask_threshold, thresh_mode)
         h = ctypes.c_void_p()
         self._lib = _load()
         rc = self._lib.oracle_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -148,6 +156,32 @@ def run_sequence(frames: np.ndarray, flows: Optional[np.ndarray], t_us: Sequence
         if k > 0:
             out.append(ev)
     return out
+
+
+def accumulate(keys: np.ndarray, epoch: int, t_begin: int, t_end: int, width: int,
+               height: int, counts: Optional[np.ndarray] = None) -> np.ndarray:
+    """Adds the events of `keys` with t in [t_begin, t_end) to uint32 counts [2][H][W]
+    (plane 0 positive, plane 1 negative); returns the counts."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    if counts is None:
+        counts = np.zeros((2, height, width), dtype=np.uint32)
+    assert counts.dtype == np.uint32 and counts.shape == (2, height, width)
+    assert counts.flags.c_contiguous
+    _load().oracle_accumulate(_ptr(keys), keys.size, int(epoch), int(t_begin), int(t_end),
+                              width, height, _ptr(counts))
+    return counts
+
+
+def event_rate(counts: np.ndarray, t_begin: int, t_end: int):
+    """Events per pixel and second over [t_begin, t_end) from accumulated counts: returns
+    (mean, std, (S1, S2))."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    _, H, W = counts.shape
+    mean, std = ctypes.c_double(), ctypes.c_double()
+    sums = np.zeros(2, dtype=np.uint64)
+    _load().oracle_event_rate(_ptr(counts), W, H, (t_end - t_begin) * 1e-6, ctypes.byref(mean),
+                              ctypes.byref(std), _ptr(sums))
+    return mean.value, std.value, (int(sums[0]), int(sums[1]))
 
 
 def decode(keys: np.ndarray, epoch: int = 0):

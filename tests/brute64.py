@@ -134,3 +134,80 @@ def solve_sequence(frames: np.ndarray, flows, t_us, method: str, transform: str 
                     ev[(x, y)] = lst
         out.append(ev)
     return out, near
+
+
+def _time_on_grid(t0: int, j: int, S: int, delta: float, t_tol: float = 0.25):
+    """t0 + floor(j/S * delta) exactly (rational arithmetic), and whether an fp32 evaluation of
+    the product could land on the other side of an integer."""
+    num = j * int(delta)
+    q, r = divmod(num, S)
+    frac = r / S
+    exact = min(frac, 1.0 - frac) > max(delta, 1.0) * 2.0 ** -22
+    return t0 + q, exact
+
+
+def _difference_samples64(Dprev: np.ndarray, Dcur: np.ndarray, flow: np.ndarray,
+                          S: int) -> np.ndarray:
+    """[S+1, H, W]: the difference frames interpolated at tau = k/S, index 0 = Dprev, S = Dcur."""
+    return samples64(Dprev, Dcur, flow, S)
+
+
+def solve_memoryless_sequence(frames: np.ndarray, flows, t_us, method: str,
+                              transform: str = "log", c_pos: float = 0.2, c_neg: float = 0.2,
+                              eps: float = 1e-3, n_interp: int = 10, mask: float = -1.0,
+                              tie_tol: float = 3e-5):
+    """Memoryless thresholding (Sec. III-A equations taken literally) in float64: for the frame
+    methods every difference of consecutive samples V_{k+1} - V_k, for the difference method
+    (Sec. III-C) every interpolated difference frame D_k (k = 1..S), fires once if it is above
+    C_pos (positive) or below -C_neg (negative), stamped at the later sample's time.  Returns
+    (events, near_tie) like solve_sequence; a pixel is a near-tie when a compared value is within
+    tie_tol (relative) of a threshold or, for the sparse method, of the selection threshold."""
+    T, H, W = frames.shape
+    lut = table64(transform, eps)
+    cp, cn = float(np.float32(c_pos)), float(np.float32(c_neg))
+    m = min(cp, cn) if mask < 0 else float(np.float32(mask))
+    S = 1 if method == "basic" else n_interp + 1
+    near = np.zeros((H, W), dtype=bool)
+    out = []
+    for i in range(1, T):
+        L0, L1 = lut[frames[i - 1]], lut[frames[i]]
+        t0, t1 = int(t_us[i - 1]), int(t_us[i])
+        delta = float(t1 - t0)
+        ev = {}
+        if method == "difference":
+            if i == 1:
+                out.append(ev)
+                continue
+            Dprev = L0 - lut[frames[i - 2]]
+            Dcur = L1 - L0
+            V = _difference_samples64(Dprev, Dcur, flows[i - 1], S)
+            values = V[1:]                                     # D_1 .. D_S
+        else:
+            V = samples64(L0, L1, flows[i - 1], S) if S > 1 else np.stack([L0, L1])
+            values = V[1:] - V[:-1]                             # V_{k+1} - V_k, k = 0..S-1
+        for y in range(H):
+            for x in range(W):
+                if method == "sparse":
+                    d = abs(L1[y, x] - L0[y, x])
+                    if abs(d - m) < tie_tol * max(1.0, abs(L0[y, x]), abs(L1[y, x])):
+                        near[y, x] = True
+                    if not d >= m:
+                        continue
+                lst = []
+                for k in range(S):
+                    D = values[k, y, x]
+                    if method == "difference":
+                        scale = max(1.0, float(np.max(np.abs(V[:, y, x]))),
+                                    abs(L0[y, x]), abs(L1[y, x]))
+                    else:
+                        scale = max(1.0, abs(V[k, y, x]), abs(V[k + 1, y, x]))
+                    if abs(D - cp) < tie_tol * scale or abs(D + cn) < tie_tol * scale:
+                        near[y, x] = True
+                    pol = 1 if D > cp else (-1 if D < -cn else 0)
+                    if pol:
+                        t, exact = _time_on_grid(t0, k + 1, S, delta)
+                        lst.append((t, pol, exact))
+                if lst:
+                    ev[(x, y)] = lst
+        out.append(ev)
+    return out, near

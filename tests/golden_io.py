@@ -9,8 +9,10 @@ from typing import Dict, List, Optional, Tuple
 import numpy as np
 
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-METHODS = {"basic": 0, "dense": 1, "sparse": 2}
+NEXT_DIR = os.path.join(GOLDEN_DIR, "next")
+METHODS = {"basic": 0, "dense": 1, "sparse": 2, "difference": 3}
 TRANSFORMS = {"log": 0, "linear": 1}
+THRESH = {"reference": 0, "memoryless": 1}
 
 
 @dataclasses.dataclass
@@ -59,6 +61,8 @@ def load(path: str) -> Golden:
     out_cfg = dict(method=METHODS[cfg["method"]], transform=TRANSFORMS[cfg["transform"]],
                    c_pos=float(cfg["c_pos"]), c_neg=float(cfg["c_neg"]),
                    n_interp=int(cfg["n_interp"]), mask_threshold=float(cfg["mask"]))
+    if "thresh" in cfg:
+        out_cfg["thresh_mode"] = THRESH[cfg["thresh"]]
     fr = np.array(frames, dtype=np.uint8).reshape(len(frames), H, W)
     fl = np.zeros((len(frames) - 1, H, W, 2), dtype=np.float32)
     for i, vals in flows.items():
@@ -68,4 +72,10 @@ def load(path: str) -> Golden:
 
 
 def all_fixtures() -> List[str]:
+    """Fixtures of the reference-level thresholding of the three frame methods."""
     return sorted(glob.glob(os.path.join(GOLDEN_DIR, "*.txt")))
+
+
+def next_fixtures() -> List[str]:
+    """Fixtures of the memoryless thresholding and of the difference-frame method."""
+    return sorted(glob.glob(os.path.join(NEXT_DIR, "*.txt")))

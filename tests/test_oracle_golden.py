@@ -6,7 +6,8 @@ import golden_io
 from oracle.oracle import OracleSim, decode
 
 
-@pytest.mark.parametrize("path", golden_io.all_fixtures(), ids=lambda p: p.rsplit("/", 1)[-1])
+@pytest.mark.parametrize("path", golden_io.all_fixtures() + golden_io.next_fixtures(),
+                         ids=lambda p: p.rsplit("/", 1)[-1])
 def test_oracle_matches_hand_worked_fixture(oracle_mod, path):
     g = golden_io.load(path)
     T, H, W = g.frames.shape
