@@ -10,9 +10,11 @@
  *   - parameters are the contrast thresholds C_pos / C_neg and the number of interpolated frames
  *     (Sec. IV-A, Table I);
  *   - outputs are events <x, y, t, p> (Sec. III-A, Fig. 1 caption).
- * Three methods: BASIC (difference of consecutive frames, Sec. III and IV-A reference bar),
- * DENSE (dense flow interpolation, Sec. III-A) and SPARSE (interpolation only at pixels whose
- * frame-to-frame change reaches a threshold, Sec. III-B).
+ * Four methods: BASIC (difference of consecutive frames, Sec. III and IV-A reference bar),
+ * DENSE (dense flow interpolation, Sec. III-A), SPARSE (interpolation only at pixels whose
+ * frame-to-frame change reaches a threshold, Sec. III-B) and DIFFERENCE (interpolation of
+ * difference frames, Sec. III-C).  Outputs can also be read as a frame of accumulated events
+ * (Fig. 1 caption) and as the events/(pixel s) statistic (Sec. IV-C).
  *
  * Arithmetic (identical on every entry point; fp32, one rounding per operation, no contraction):
  *   L = T[I] with T the 256-entry transform table (LOG: ln(v/255 + eps) rounded once from double;
@@ -25,6 +27,15 @@
  *   t_{i-1} + floor(((k + theta) / S) * (t_i - t_{i-1})) with theta the crossing fraction inside
  *   the sub-interval (0 when the level was already passed at its start).  SPARSE skips pixels
  *   with |L1 - L0| < mask_threshold entirely (no events, R unchanged).
+ * Memoryless thresholding (thresh_mode = SIM_THRESH_MEMORYLESS; the paper's Sec. III-A equations
+ *   taken literally): no reference level; each difference D = V_{k+1} - V_k fires once, positive
+ *   if D > C_pos, negative if D < -C_neg (strict), at t_{i-1} + floor(((k + 1) / S) * delta).
+ * DIFFERENCE (always memoryless): from three consecutive frames the difference frames
+ *   D1 = L_{i-1} - L_{i-2} and D2 = L_i - L_{i-1} (texel by texel); the flow supplied for the
+ *   interval is the flow from D1 to D2; D_k = w * bil(D1, x - tau u, y - tau v) +
+ *   tau * bil(D2, x + w u, y + w v) for 0 < k < S and D_S = D2; each D_k (k = 1..S) fires as
+ *   above at t_{i-1} + floor((k / S) * delta).  The first interval (two frames, one difference
+ *   frame) emits nothing; its flow is not read.
  *
  * Event order: within each frame interval events are sorted by (t, y, x, p) with p = -1 before
  * p = +1; intervals follow in push order.
@@ -59,13 +70,14 @@ extern "C" {
 #define SIM_E_BUSY (-7)      /* server: no slot or memory for the request (nothing changed)     */
 #define SIM_E_EMPTY (-8)     /* server: nothing to return yet                                   */
 
-enum { SIM_BASIC = 0, SIM_DENSE = 1, SIM_SPARSE = 2 };
+enum { SIM_BASIC = 0, SIM_DENSE = 1, SIM_SPARSE = 2, SIM_DIFFERENCE = 3 };
+enum { SIM_THRESH_REFERENCE = 0, SIM_THRESH_MEMORYLESS = 1 };
 enum { SIM_LOG = 0, SIM_LINEAR = 1 };
 enum { SIM_MEM_HOST = 0, SIM_MEM_DEVICE = 1 };
 
 typedef struct sim_config {
     int32_t width, height;      /* 1..4096 each (12-bit x and y fields of the packed key)          */
-    int32_t method;             /* SIM_BASIC | SIM_DENSE | SIM_SPARSE                               */
+    int32_t method;             /* SIM_BASIC | SIM_DENSE | SIM_SPARSE | SIM_DIFFERENCE              */
     int32_t transform;          /* SIM_LOG (default) | SIM_LINEAR (the paper's linear difference)  */
     float c_pos, c_neg;         /* threshold magnitudes > 0; the paper writes C_neg as negative     */
     float log_eps;              /* SIM_LOG offset inside the logarithm, > 0 (default 1e-3)          */
@@ -74,6 +86,9 @@ typedef struct sim_config {
     float mask_threshold;       /* SIM_SPARSE selection m: < 0 -> min(c_pos, c_neg); 0 -> all px   */
     uint64_t event_capacity;    /* initial device event buffer (events); grows on demand; 0 = auto */
     void* hip_stream;           /* hipStream_t to order all work on; NULL -> library-owned stream   */
+    int32_t thresh_mode;        /* SIM_THRESH_REFERENCE (default: reference level, event pixel) |   */
+                                /* SIM_THRESH_MEMORYLESS (paper's equations); DIFFERENCE: ignored   */
+    int32_t reserved;           /* must be 0                                                        */
 } sim_config;
 
 /* One event as drained to the host (16 bytes). */
@@ -105,13 +120,15 @@ typedef struct sim_stats {
 typedef struct sim_stream sim_stream;
 
 /* Fills cfg with defaults: 0x0 image, SIM_BASIC, SIM_LOG, C = 0.2, eps = 1e-3, N = 10, m = -1,
- * automatic capacity, library-owned stream.  Width and height must be set before sim_create. */
+ * automatic capacity, library-owned stream, reference-level thresholding.  Width and height must
+ * be set before sim_create. */
 void sim_config_init(sim_config* cfg);
 
 /* Creates a stream (device state: reference levels, previous frame, table, event buffers).
  * cfg is copied.  On success *out owns the handle until sim_destroy.  Errors: SIM_E_INVAL
- * (dimension out of 1..4096, method/transform unknown, thresholds not > 0 or so small that
- * R + C == R for some reachable R, n_interp outside 0..255, log_eps not > 0), SIM_E_NOMEM. */
+ * (dimension out of 1..4096, method/transform/thresh_mode unknown, reserved not 0, thresholds
+ * not > 0 or so small that R + C == R for some reachable R, n_interp outside 0..255, log_eps not
+ * > 0), SIM_E_NOMEM. */
 int sim_create(const sim_config* cfg, sim_stream** out);
 
 /* Releases every resource of the handle after the work queued on its stream completes. */
@@ -124,7 +141,8 @@ int sim_reset(sim_stream* s);
 /* Pushes one frame taken at t_us (frame interval semantics of Sec. III-A: the pair of frames
  * (previous, this one) defines one interval).  frame: uint8 [height][width], row-major, no
  * padding.  flow: float32 [height][width][2] (dx, dy in pixels per interval, motion from the
- * previous frame to this one); required for SIM_DENSE / SIM_SPARSE except on the first frame,
+ * previous frame to this one; for SIM_DIFFERENCE the flow between the interval's difference
+ * frames); required for SIM_DENSE / SIM_SPARSE / SIM_DIFFERENCE except on the first frame,
  * ignored otherwise (may be NULL).  mem_kind tells whether frame and flow are host or device
  * pointers; host inputs are copied before the call returns, device inputs must stay valid until
  * the work queued on the stream has completed.  The first push only initialises the reference
@@ -203,6 +221,25 @@ int sim_set_kernel_timing(sim_stream* s, int32_t enable);
 /* Static text for a status code. */
 const char* sim_strerror(int status);
 
+/* Frame of accumulated events (Fig. 1 caption: the methods output either the events or a frame
+ * of accumulated events): adds, for every pending (not yet drained) event with
+ * t_begin <= t < t_end, one to counts[0][y][x] if it is positive or to counts[1][y][x] if it is
+ * negative.  counts: uint32 [2][height][width], caller-owned, host or device (mem_kind); it is
+ * added to, not cleared.  Host counts are complete when the call returns; device counts are
+ * written in stream order on the handle's stream.  Pending events are not consumed.  Errors:
+ * SIM_E_INVAL (NULL counts, t_end < t_begin, bad mem_kind). */
+int sim_accumulate(sim_stream* s, int64_t t_begin, int64_t t_end, uint32_t* counts,
+                   int32_t mem_kind);
+
+/* Events per pixel and second (the statistic of Sec. IV-C) of the pending events with
+ * t_begin <= t < t_end: with c the per-pixel count of both polarities over all width * height
+ * pixels, S1 = sum c and S2 = sum c^2 (exact integers), m1 = S1 / npix, m2 = S2 / npix and
+ * T = (t_end - t_begin) * 1e-6 s, *mean = m1 / T and *stddev = sqrt(max(m2 - m1 * m1, 0)) / T
+ * (population deviation over pixels; double precision).  sums (may be NULL) receives S1, S2.
+ * Synchronises the stream.  Errors: SIM_E_INVAL (NULL mean or stddev, t_end <= t_begin). */
+int sim_event_rate(sim_stream* s, int64_t t_begin, int64_t t_end, double* mean, double* stddev,
+                   uint64_t* sums);
+
 /* Text describing the HIP failure that poisoned the handle (call, source line, HIP's message);
  * empty when there was none.  Valid until the next call on the handle. */
 const char* sim_last_error(sim_stream* s);
@@ -245,11 +282,11 @@ int srv_destroy(sim_server* srv);
 int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam);
 int srv_release(sim_server* srv, int32_t cam);
 /* frame: uint8 [H][W]; flow: float32 [H][W][2] for the interval ending at this frame (required
- * for SIM_DENSE / SIM_SPARSE except on a camera's first frame); both host or both device.  The
- * inputs are copied into the camera's staging slot before the call returns, so the caller may
- * reuse or free them at once; a device input must be complete (its writes synchronised) at the
- * call.  SIM_E_BUSY when the camera's queue is full (call srv_step), SIM_E_ORDER when t_us does
- * not increase. */
+ * for SIM_DENSE / SIM_SPARSE / SIM_DIFFERENCE except on a camera's first frame); both host or
+ * both device.  The inputs are copied into the camera's staging slot before the call returns,
+ * so the caller may reuse or free them at once; a device input must be complete (its writes
+ * synchronised) at the call.  SIM_E_BUSY when the camera's queue is full (call srv_step),
+ * SIM_E_ORDER when t_us does not increase. */
 int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* flow,
                int64_t t_us, int32_t mem_kind, int64_t arrival_ns);
 /* One continuous-batching step; *n_frames receives the frames completed.  Returns SIM_OK or the

@@ -23,7 +23,13 @@ constexpr int kActStripes = 8;       // active-pixel sub-lists (one per group of
 constexpr int kStatStripes = 64;     // statistics counters
 constexpr int kSelectPx = 1024;      // pixels per selection block (4 per thread)
 
-enum Method { kBasic = 0, kDense = 1, kSparse = 2 };
+enum Method { kBasic = 0, kDense = 1, kSparse = 2, kDifference = 3 };
+
+// What the chain pass compares with the thresholds.
+//   kModeReference:  the interpolated series against a per-pixel reference level (event pixel);
+//   kModeMemoryless: each difference of consecutive samples on its own (paper's equations);
+//   kModeDifference: each interpolated difference frame on its own (difference method).
+enum ChainMode { kModeReference = 0, kModeMemoryless = 1, kModeDifference = 2 };
 
 // Layout of the unsorted "sort key" written by the simulation kernel, low bits first:
 //   p (1) | x (xb) | y (yb) | t_rel (tb) | interval index within the window (ib)
@@ -75,6 +81,9 @@ struct ChainArgs {
     int W, H, S, K, npix;
     float cpos, cneg;
     KeyLayout lay;
+    int mode;                   // ChainMode
+    const uint8_t* prev2;       // difference method: frame before `prev`
+    int first_emit;             // difference method: intervals below this emit nothing
 };
 
 struct ConvertArgs {
@@ -104,5 +113,15 @@ hipError_t launch_sort(uint64_t* keys, uint64_t* alt, const unsigned long long* 
                        uint64_t n_max, int nbits, uint32_t* hist, uint32_t* totals,
                        uint64_t* out, const ConvertArgs& cv, hipStream_t stream);
 size_t sort_hist_entries(uint64_t n_max);
+
+// Adds every packed key of keys[0, n) whose time field (t - epoch) lies in [t_lo, t_hi) to the
+// accumulated frame counts[2][H][W] (plane 0 positive, plane 1 negative).
+hipError_t launch_accumulate(const uint64_t* keys, uint64_t n, uint64_t t_lo, uint64_t t_hi,
+                             int W, int H, uint32_t* counts, hipStream_t stream);
+// Per-block partial sums (sum c, sum c^2) of c = counts[p] + counts[plane + p] over p < plane
+// into part[2 * block], part[2 * block + 1] for `blocks` = moments_blocks(plane) blocks.
+int moments_blocks(uint64_t plane);
+hipError_t launch_moments(const uint32_t* counts, uint64_t plane, unsigned long long* part,
+                          hipStream_t stream);
 
 }  // namespace evsim

@@ -74,6 +74,7 @@ struct PixelCtx {
     const float* stash;     // column of this thread's interior samples (stride 256) or null
     int W, H, x, y, S;
     float u, v;
+    const uint8_t* Fm;      // difference method: the frame before F0
 };
 
 __device__ __forceinline__ float sample_k(const PixelCtx& c, int k, float A1) {
@@ -125,6 +126,88 @@ __device__ __forceinline__ int crossings(const PixelCtx& c, float R, float A0, f
         A = B;
     }
     *Rout = R;
+    return n;
+}
+
+// Clamp-to-edge bilinear sample at (sx, sy) of the difference frame T[Fb] - T[Fa] (each texel
+// difference is one fp32 subtraction, then the same blend as `bilinear`).
+__device__ __forceinline__ float bilinear_diff(const uint8_t* __restrict__ Fa,
+                                               const uint8_t* __restrict__ Fb, const float* lut,
+                                               int W, int H, float sx, float sy) {
+    sx = fminf(fmaxf(sx, 0.0f), (float)(W - 1));
+    sy = fminf(fmaxf(sy, 0.0f), (float)(H - 1));
+    const int x0 = (int)floorf(sx);
+    const int y0 = (int)floorf(sy);
+    const float fx = sx - (float)x0;
+    const float fy = sy - (float)y0;
+    const int x1 = min(x0 + 1, W - 1);
+    const int y1 = min(y0 + 1, H - 1);
+    const float gx = 1.0f - fx;
+    const float gy = 1.0f - fy;
+    const int64_t r0 = (int64_t)y0 * W;
+    const int64_t r1 = (int64_t)y1 * W;
+    const float d00 = lut[Fb[r0 + x0]] - lut[Fa[r0 + x0]];
+    const float d01 = lut[Fb[r0 + x1]] - lut[Fa[r0 + x1]];
+    const float d10 = lut[Fb[r1 + x0]] - lut[Fa[r1 + x0]];
+    const float d11 = lut[Fb[r1 + x1]] - lut[Fa[r1 + x1]];
+    const float top = gx * d00 + fx * d01;
+    const float bot = gx * d10 + fx * d11;
+    return gy * top + fy * bot;
+}
+
+// Interior interpolated difference frame D_k (0 < k < S) of the difference method (Sec. III-C):
+// the same flow-guided blend as interp_sample, between D1 = T[F0] - T[Fm] and D2 = T[F1] - T[F0].
+__device__ __forceinline__ float interp_diff_sample(const uint8_t* Fm, const uint8_t* F0,
+                                                    const uint8_t* F1, const float* lut, int W,
+                                                    int H, int x, int y, float u, float v, int k,
+                                                    int S) {
+    const float tau = (float)k / (float)S;
+    const float om = 1.0f - tau;
+    const float a = bilinear_diff(Fm, F0, lut, W, H, (float)x - tau * u, (float)y - tau * v);
+    const float b = bilinear_diff(F0, F1, lut, W, H, (float)x + om * u, (float)y + om * v);
+    return om * a + tau * b;
+}
+
+template <int MODE>
+__device__ __forceinline__ float sample_mode(const PixelCtx& c, int k, float A1) {
+    if (k == c.S) return A1;
+    if (c.stash) return c.stash[(k - 1) * kSimThreads];
+    if constexpr (MODE == kModeDifference)
+        return interp_diff_sample(c.Fm, c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, k, c.S);
+    else
+        return interp_sample(c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, k, c.S);
+}
+
+// Memoryless thresholding of one pixel's interval (the paper's Sec. III-A equations taken
+// literally): the value compared at sub-frame k + 1 is V_{k+1} - V_k (kModeMemoryless, series
+// V_0 = A0 .. V_S = A1) or the interpolated difference frame D_{k+1} (kModeDifference, D_S = A1).
+// Strictly above C_pos fires positive, strictly below -C_neg negative, at most once per sub-frame,
+// stamped at the sub-frame's time t0 + floor((k + 1) / S * delta).  Counts (WRITE = false) or
+// writes (WRITE = true) the events and returns the count.
+template <int MODE, bool WRITE>
+__device__ __forceinline__ int flips(const PixelCtx& c, float A0, float A1, float cpos,
+                                     float cneg, float delta, uint64_t keyhi, int pbits,
+                                     uint64_t pixkey, uint64_t* out) {
+    int n = 0;
+    float A = A0;
+    for (int k = 0; k < c.S; ++k) {
+        const float B = sample_mode<MODE>(c, k + 1, A1);
+        const float D = (MODE == kModeMemoryless) ? B - A : B;
+        int pol = 0;
+        if (D > cpos)
+            pol = 1;
+        else if (D < -cneg)
+            pol = -1;
+        if (pol != 0) {
+            if (WRITE) {
+                const float phi = (float)(k + 1) / (float)c.S;
+                const uint64_t trel = (uint64_t)(int64_t)floorf(phi * delta);
+                out[n] = keyhi | (trel << pbits) | pixkey | (pol > 0 ? 1ull : 0ull);
+            }
+            ++n;
+        }
+        A = B;
+    }
     return n;
 }
 
@@ -277,7 +360,11 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
 // arena space with one atomic (no block barrier), and the lanes write their events.  If the
 // arena is full the wave fills its reservation with sentinels, stores each lane's current
 // interval as its resume point and stops; the host grows the arena and launches again.
+// MODE selects what is thresholded (ChainMode): the reference-level crossings of the event pixel,
+// or the paper's memoryless thresholding of sample differences or of interpolated difference
+// frames (no reference level, which is then neither read nor written).
 // ------------------------------------------------------------------------------------------
+template <int MODE>
 __global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
     extern __shared__ float smem[];
     float* lut = smem;
@@ -310,7 +397,8 @@ __global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
         if (a.K > 96) m3 = a.mask[3 * (int64_t)a.npix + p];
     }
     int i = valid ? next_selected(all, m0, m1, m2, m3, a.resume[slot], a.K) : a.K;
-    float R = valid ? a.lref[p] : 0.0f;
+    if constexpr (MODE == kModeDifference) i = max(i, a.first_emit);
+    float R = (MODE == kModeReference && valid) ? a.lref[p] : 0.0f;
 
     const int stash_n = (a.S - 1 <= kMaxStash) ? (a.S - 1) : 0;
     float* stash = smem + 256 + tid;
@@ -329,20 +417,38 @@ __global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
         c.u = 0.0f; c.v = 0.0f; c.stash = nullptr;
         c.F0 = i == 0 ? a.prev : a.frames + (int64_t)(i - 1) * a.fstride;
         c.F1 = a.frames + (int64_t)i * a.fstride;
+        if constexpr (MODE == kModeDifference)
+            c.Fm = i == 0 ? a.prev2 : (i == 1 ? a.prev : a.frames + (int64_t)(i - 2) * a.fstride);
         if (have) {
             A0 = lut[c.F0[p]];
             A1 = lut[c.F1[p]];
+            if constexpr (MODE == kModeDifference) {
+                // the two difference frames at this pixel: D1 (series start), D2 = D_S
+                const float Am = lut[c.Fm[p]];
+                const float D2 = A1 - A0;
+                A0 = A0 - Am;
+                A1 = D2;
+            }
             delta = a.delta[i];
             if (a.S > 1) {
                 const float* fl = a.flows + (int64_t)i * a.flstride + 2 * (int64_t)p;
                 c.u = fl[0];
                 c.v = fl[1];
-                for (int k = 1; k <= stash_n; ++k)
-                    stash[(k - 1) * kSimThreads] =
-                        interp_sample(c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
+                for (int k = 1; k <= stash_n; ++k) {
+                    if constexpr (MODE == kModeDifference)
+                        stash[(k - 1) * kSimThreads] = interp_diff_sample(
+                            c.Fm, c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
+                    else
+                        stash[(k - 1) * kSimThreads] =
+                            interp_sample(c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
+                }
                 if (stash_n) c.stash = stash;
             }
-            n = crossings<false>(c, R, A0, A1, a.cpos, a.cneg, delta, 0, pbits, 0, nullptr, &Rn);
+            if constexpr (MODE == kModeReference)
+                n = crossings<false>(c, R, A0, A1, a.cpos, a.cneg, delta, 0, pbits, 0, nullptr,
+                                     &Rn);
+            else
+                n = flips<MODE, false>(c, A0, A1, a.cpos, a.cneg, delta, 0, pbits, 0, nullptr);
         }
         const int inc = wave_incl_scan(n);
         const int total = __shfl(inc, 63, 64);
@@ -368,15 +474,19 @@ __global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
         if (have) {
             if (n > 0) {
                 const uint64_t keyhi = (uint64_t)i << ishift;
-                crossings<true>(c, R, A0, A1, a.cpos, a.cneg, delta, keyhi, pbits, pixkey,
-                                arena + base + (inc - n), &Rn);
+                if constexpr (MODE == kModeReference)
+                    crossings<true>(c, R, A0, A1, a.cpos, a.cneg, delta, keyhi, pbits, pixkey,
+                                    arena + base + (inc - n), &Rn);
+                else
+                    flips<MODE, true>(c, A0, A1, a.cpos, a.cneg, delta, keyhi, pbits, pixkey,
+                                      arena + base + (inc - n));
             }
             R = Rn;
             i = next_selected(all, m0, m1, m2, m3, i + 1, a.K);
         }
     }
     if (valid) {
-        a.lref[p] = R;
+        if constexpr (MODE == kModeReference) a.lref[p] = R;
         a.resume[slot] = failed ? i : a.K;
     }
 }
@@ -425,6 +535,56 @@ __global__ void k_clamp(unsigned long long* reserve, uint64_t cap) {
     if (s < kArenaStripes) {
         unsigned long long* r = reserve + s * kCounterStride;
         if (*r > cap) *r = cap;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Frame of accumulated events (Fig. 1 caption) and its per-pixel moments (the events/(pixel s)
+// statistic of Sec. IV-C).  Keys are packed ABI keys: (t - epoch) << 25 | y << 13 | x << 1 | p.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_accumulate(const uint64_t* __restrict__ keys, uint64_t n,
+                                                    uint64_t t_lo, uint64_t t_hi, int W, int H,
+                                                    uint32_t* __restrict__ counts) {
+    const uint64_t plane = (uint64_t)W * (uint64_t)H;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t k = keys[i];
+        const uint64_t t = k >> 25;
+        if (t < t_lo || t >= t_hi) continue;
+        const uint32_t y = (uint32_t)(k >> 13) & 0xFFFu;
+        const uint32_t x = (uint32_t)(k >> 1) & 0xFFFu;
+        if (x >= (uint32_t)W || y >= (uint32_t)H) continue;
+        atomicAdd(counts + ((k & 1ull) ? 0ull : plane) + (uint64_t)y * W + x, 1u);
+    }
+}
+
+constexpr int kMomentBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_moments(const uint32_t* __restrict__ counts,
+                                                 uint64_t plane,
+                                                 unsigned long long* __restrict__ part) {
+    __shared__ unsigned long long r1[256], r2[256];
+    const int tid = threadIdx.x;
+    unsigned long long s1 = 0, s2 = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + tid; p < plane; p += stride) {
+        const unsigned long long c = (unsigned long long)counts[p] + counts[plane + p];
+        s1 += c;
+        s2 += c * c;
+    }
+    r1[tid] = s1;
+    r2[tid] = s2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+            r1[tid] += r1[tid + h];
+            r2[tid] += r2[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[2 * blockIdx.x] = r1[0];
+        part[2 * blockIdx.x + 1] = r2[0];
     }
 }
 
@@ -560,7 +720,22 @@ hipError_t launch_chain(const ChainArgs& a, int max_slots, hipStream_t stream) {
     const size_t shmem = (size_t)(256 + stash_n * kSimThreads) * sizeof(float);
     const int blocks = (max_slots + kSimThreads - 1) / kSimThreads;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chain, dim3(blocks), dim3(kSimThreads), shmem, stream, a);
+    switch (a.mode) {
+        case kModeReference:
+            hipLaunchKernelGGL(k_chain<kModeReference>, dim3(blocks), dim3(kSimThreads), shmem,
+                               stream, a);
+            break;
+        case kModeMemoryless:
+            hipLaunchKernelGGL(k_chain<kModeMemoryless>, dim3(blocks), dim3(kSimThreads), shmem,
+                               stream, a);
+            break;
+        case kModeDifference:
+            hipLaunchKernelGGL(k_chain<kModeDifference>, dim3(blocks), dim3(kSimThreads), shmem,
+                               stream, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -612,6 +787,26 @@ hipError_t launch_sort(uint64_t* keys, uint64_t* alt, const unsigned long long* 
         src = dst;
         dst = t;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const uint64_t* keys, uint64_t n, uint64_t t_lo, uint64_t t_hi,
+                             int W, int H, uint32_t* counts, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)blocks), dim3(256), 0, stream, keys, n, t_lo,
+                       t_hi, W, H, counts);
+    return hipGetLastError();
+}
+
+int moments_blocks(uint64_t plane) {
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((plane + 255) / 256, kMomentBlocks));
+}
+
+hipError_t launch_moments(const uint32_t* counts, uint64_t plane, unsigned long long* part,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_moments, dim3((unsigned)moments_blocks(plane)), dim3(256), 0, stream,
+                       counts, plane, part);
     return hipGetLastError();
 }
 

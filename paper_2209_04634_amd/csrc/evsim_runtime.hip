@@ -57,7 +57,9 @@ struct sim_stream {
     float* d_lut = nullptr;
     float* d_lref = nullptr;
     uint8_t* d_prev[2] = {nullptr, nullptr};
+    uint8_t* d_prev2[2] = {nullptr, nullptr};    // difference method: the frame before d_prev
     int cur = 0;
+    uint64_t n_int = 0;                          // intervals simulated since the first frame
 
     bool started = false;
     int64_t epoch = 0, t_prev = 0;
@@ -95,6 +97,12 @@ struct sim_stream {
     // FIFO of sorted packed keys
     uint64_t* d_fifo = nullptr;
     uint64_t fifo_cap = 0, fifo_head = 0, fifo_tail = 0;
+
+    // accumulated-frame scratch (sim_accumulate with host counts, sim_event_rate)
+    uint32_t* d_acc = nullptr;
+    uint64_t acc_cap = 0;
+    unsigned long long* d_moments = nullptr;     // per-block partial sums (sim_event_rate)
+    uint64_t moments_cap = 0;
 
     sim_stats stats;
     char last_error[256] = {0};
@@ -141,6 +149,10 @@ void free_stream(sim_stream* s) {
     dfree(s->d_lref);
     dfree(s->d_prev[0]);
     dfree(s->d_prev[1]);
+    dfree(s->d_prev2[0]);
+    dfree(s->d_prev2[1]);
+    dfree(s->d_acc);
+    dfree(s->d_moments);
     dfree(s->d_arena);
     dfree(s->d_reserve);
     dfree(s->d_stats);
@@ -305,6 +317,11 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
         HIP_TRY(s, hipMemsetAsync(s->d_resume, 0, (size_t)s->npix * sizeof(int), s->stream));
         HIP_TRY(s, launch_copy_u8(frames + (size_t)(K - 1) * s->npix, prev_out, s->npix,
                                   s->stream));
+        if (s->cfg.method == SIM_DIFFERENCE) {
+            // the frame before the window's last one becomes the next window's second-to-last
+            const uint8_t* src = K >= 2 ? frames + (size_t)(K - 2) * s->npix : s->d_prev[s->cur];
+            HIP_TRY(s, launch_copy_u8(src, s->d_prev2[1 - s->cur], s->npix, s->stream));
+        }
     }
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
 
@@ -332,6 +349,12 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
     a.cpos = s->cfg.c_pos;
     a.cneg = s->cfg.c_neg;
     a.lay = lay;
+    if (s->cfg.method == SIM_DIFFERENCE)
+        a.mode = kModeDifference;
+    else
+        a.mode = s->cfg.thresh_mode == SIM_THRESH_MEMORYLESS ? kModeMemoryless : kModeReference;
+    a.prev2 = s->d_prev2[s->cur];
+    a.first_emit = s->n_int == 0 ? 1 : 0;   // difference method: three frames are needed
     const int max_slots = sparse ? kActStripes * s->act_cap : (int)s->npix;
 
     s->job.active = true;
@@ -434,6 +457,7 @@ int win_order(sim_stream* s, uint64_t* n_new) {
     s->fifo_tail += n_valid;
     s->cur = 1 - s->cur;
     s->t_prev = s->job.t_last;
+    s->n_int += (uint64_t)s->job.K;
     s->stats.intervals += (uint64_t)s->job.K;
     s->stats.frames += (uint64_t)s->job.K;
     s->stats.events += n_valid;
@@ -503,6 +527,7 @@ int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const flo
         s->started = true;
         s->epoch = t_us[0];
         s->t_prev = t_us[0];
+        s->n_int = 0;
         s->stats.frames += 1;
     }
     return SIM_OK;
@@ -563,7 +588,10 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     *out = nullptr;
     if (cfg->width < 1 || cfg->height < 1 || cfg->width > 4096 || cfg->height > 4096)
         return SIM_E_INVAL;
-    if (cfg->method < SIM_BASIC || cfg->method > SIM_SPARSE) return SIM_E_INVAL;
+    if (cfg->method < SIM_BASIC || cfg->method > SIM_DIFFERENCE) return SIM_E_INVAL;
+    if (cfg->thresh_mode != SIM_THRESH_REFERENCE && cfg->thresh_mode != SIM_THRESH_MEMORYLESS)
+        return SIM_E_INVAL;
+    if (cfg->reserved != 0) return SIM_E_INVAL;
     if (cfg->transform != SIM_LOG && cfg->transform != SIM_LINEAR) return SIM_E_INVAL;
     if (!(cfg->c_pos > 0.0f) || !(cfg->c_neg > 0.0f) || !isfinite(cfg->c_pos) ||
         !isfinite(cfg->c_neg))
@@ -617,6 +645,10 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     ok = ok && dev_alloc(&s->d_stats, (size_t)kStatStripes * kCounterStride) == hipSuccess;
     ok = ok && dev_alloc(&s->d_totals, 256) == hipSuccess;
     ok = ok && dev_alloc(&s->d_counters, 4) == hipSuccess;
+    if (cfg->method == SIM_DIFFERENCE) {
+        ok = ok && dev_alloc(&s->d_prev2[0], s->npix) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_prev2[1], s->npix) == hipSuccess;
+    }
     if (cfg->method == SIM_SPARSE) {
         ok = ok && dev_alloc(&s->d_mask, (size_t)kMaskWords * s->npix) == hipSuccess;
         ok = ok && dev_alloc(&s->d_act, (size_t)kActStripes * s->act_cap) == hipSuccess;
@@ -815,6 +847,85 @@ int sim_get_reference(sim_stream* s, float* dst, int32_t mem_kind) {
                                                        : hipMemcpyDeviceToDevice,
                               s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return SIM_OK;
+}
+
+namespace {
+
+// Window [t_begin, t_end) in the key's time field (t - epoch); false when it holds no key time.
+bool key_window(const sim_stream* s, int64_t t_begin, int64_t t_end, uint64_t* lo, uint64_t* hi) {
+    if (!s->started || t_end <= s->epoch || t_end <= t_begin) return false;
+    *lo = t_begin > s->epoch ? (uint64_t)(t_begin - s->epoch) : 0;
+    *hi = (uint64_t)(t_end - s->epoch);
+    return *lo < *hi;
+}
+
+}  // namespace
+
+int sim_accumulate(sim_stream* s, int64_t t_begin, int64_t t_end, uint32_t* counts,
+                   int32_t mem_kind) {
+    if (!s || !counts || t_end < t_begin || check_mem_kind(mem_kind)) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    uint64_t lo = 0, hi = 0;
+    const uint64_t n = s->fifo_tail - s->fifo_head;
+    if (n == 0 || !key_window(s, t_begin, t_end, &lo, &hi)) return SIM_OK;
+    const size_t bytes = 2 * (size_t)s->npix * sizeof(uint32_t);
+    uint32_t* dst = counts;
+    if (mem_kind == SIM_MEM_HOST) {
+        int rc = grow(s, &s->d_acc, &s->acc_cap, 2 * (uint64_t)s->npix, 0);
+        if (rc) return rc;
+        HIP_TRY(s, hipMemcpyAsync(s->d_acc, counts, bytes, hipMemcpyHostToDevice, s->stream));
+        dst = s->d_acc;
+    }
+    HIP_TRY(s, launch_accumulate(s->d_fifo + s->fifo_head, n, lo, hi, s->cfg.width,
+                                 s->cfg.height, dst, s->stream));
+    if (mem_kind == SIM_MEM_HOST) {
+        HIP_TRY(s, hipMemcpyAsync(counts, s->d_acc, bytes, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+    }
+    return SIM_OK;
+}
+
+int sim_event_rate(sim_stream* s, int64_t t_begin, int64_t t_end, double* mean, double* stddev,
+                   uint64_t* sums) {
+    if (!s || !mean || !stddev || t_end <= t_begin) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    const uint64_t plane = (uint64_t)s->npix;
+    int rc = grow(s, &s->d_acc, &s->acc_cap, 2 * plane, 0);
+    if (!rc) rc = grow(s, &s->d_moments, &s->moments_cap, 2 * (uint64_t)moments_blocks(plane), 0);
+    if (rc) return rc;
+    HIP_TRY(s, hipMemsetAsync(s->d_acc, 0, 2 * plane * sizeof(uint32_t), s->stream));
+    uint64_t lo = 0, hi = 0;
+    const uint64_t n = s->fifo_tail - s->fifo_head;
+    if (n && key_window(s, t_begin, t_end, &lo, &hi))
+        HIP_TRY(s, launch_accumulate(s->d_fifo + s->fifo_head, n, lo, hi, s->cfg.width,
+                                     s->cfg.height, s->d_acc, s->stream));
+    HIP_TRY(s, launch_moments(s->d_acc, plane, s->d_moments, s->stream));
+    const int nb = moments_blocks(plane);
+    std::vector<unsigned long long> part;
+    try {
+        part.resize(2 * (size_t)nb);
+    } catch (...) {
+        return SIM_E_NOMEM;
+    }
+    HIP_TRY(s, hipMemcpyAsync(part.data(), s->d_moments, part.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    uint64_t s1 = 0, s2 = 0;
+    for (int b = 0; b < nb; ++b) {
+        s1 += part[2 * b];
+        s2 += part[2 * b + 1];
+    }
+    const double seconds = (double)(t_end - t_begin) * 1e-6;
+    const double m1 = (double)s1 / (double)plane;
+    const double m2 = (double)s2 / (double)plane;
+    const double var = m2 - m1 * m1;
+    *mean = m1 / seconds;
+    *stddev = sqrt(var > 0.0 ? var : 0.0) / seconds;
+    if (sums) {
+        sums[0] = s1;
+        sums[1] = s2;
+    }
     return SIM_OK;
 }
 

@@ -15,11 +15,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libevsim.so")
 
-BASIC, DENSE, SPARSE = 0, 1, 2
+BASIC, DENSE, SPARSE, DIFFERENCE = 0, 1, 2, 3
 LOG, LINEAR = 0, 1
+REFERENCE, MEMORYLESS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-METHODS = {"basic": BASIC, "dense": DENSE, "sparse": SPARSE}
+METHODS = {"basic": BASIC, "dense": DENSE, "sparse": SPARSE, "difference": DIFFERENCE}
 TRANSFORMS = {"log": LOG, "linear": LINEAR}
+THRESH_MODES = {"reference": REFERENCE, "memoryless": MEMORYLESS}
 
 OK, E_INVAL, E_ORDER, E_NOMEM, E_RANGE, E_HIP, E_POISONED, E_BUSY, E_EMPTY = 0, -1, -2, -3, -4, -5, -6, -7, -8
 
@@ -30,7 +32,8 @@ class SimConfig(ctypes.Structure):
                 ("c_pos", ctypes.c_float), ("c_neg", ctypes.c_float),
                 ("log_eps", ctypes.c_float), ("n_interp", ctypes.c_int32),
                 ("mask_threshold", ctypes.c_float), ("event_capacity", ctypes.c_uint64),
-                ("hip_stream", ctypes.c_void_p)]
+                ("hip_stream", ctypes.c_void_p), ("thresh_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SimEvent(ctypes.Structure):
@@ -117,6 +120,9 @@ def load() -> ctypes.CDLL:
         "srv_get_stats": (ctypes.c_int, [P, ctypes.POINTER(ServerStats)]),
         "srv_clear_stats": (ctypes.c_int, [P]),
         "srv_now_ns": (I64, []),
+        "sim_accumulate": (ctypes.c_int, [P, I64, I64, P, I32]),
+        "sim_event_rate": (ctypes.c_int, [P, I64, I64, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double), PU64]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -152,7 +158,9 @@ def _buffer(x, dtype, shape=None):
         return None, None, None
     if _is_torch(x):
         import torch
-        want = {np.uint8: torch.uint8, np.float32: torch.float32, np.int64: torch.int64}[dtype]
+        # uint32 buffers travel as int32 tensors (same bits)
+        want = {np.uint8: torch.uint8, np.float32: torch.float32, np.int64: torch.int64,
+                np.uint32: torch.int32}[dtype]
         if x.dtype != want:
             raise TypeError(f"expected {want}, got {x.dtype}")
         if not x.is_contiguous():
@@ -170,7 +178,8 @@ def _buffer(x, dtype, shape=None):
 def make_config(width: int, height: int, method: Union[str, int] = "basic",
                 transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
                 log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
-                event_capacity: int = 0, hip_stream=None) -> SimConfig:
+                event_capacity: int = 0, hip_stream=None,
+                thresh_mode: Union[str, int] = "reference") -> SimConfig:
     lib = load()
     cfg = SimConfig()
     lib.sim_config_init(ctypes.byref(cfg))
@@ -180,6 +189,8 @@ def make_config(width: int, height: int, method: Union[str, int] = "basic",
     cfg.c_pos, cfg.c_neg, cfg.log_eps = float(c_pos), float(c_neg), float(log_eps)
     cfg.n_interp, cfg.mask_threshold = int(n_interp), float(mask_threshold)
     cfg.event_capacity = int(event_capacity)
+    cfg.thresh_mode = (THRESH_MODES[thresh_mode] if isinstance(thresh_mode, str)
+                       else int(thresh_mode))
     if hip_stream == "torch":
         import torch
         hip_stream = torch.cuda.current_stream().cuda_stream
@@ -195,10 +206,11 @@ class Stream:
     def __init__(self, width: int, height: int, method: Union[str, int] = "basic",
                  transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
                  log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
-                 event_capacity: int = 0, hip_stream=None):
+                 event_capacity: int = 0, hip_stream=None,
+                 thresh_mode: Union[str, int] = "reference"):
         lib = load()
         cfg = make_config(width, height, method, transform, c_pos, c_neg, log_eps, n_interp,
-                          mask_threshold, event_capacity, hip_stream)
+                          mask_threshold, event_capacity, hip_stream, thresh_mode)
         h = ctypes.c_void_p()
         _check(lib.sim_create(ctypes.byref(cfg), ctypes.byref(h)), "sim_create")
         self._h = h
@@ -266,6 +278,30 @@ class Stream:
         _check(self._lib.sim_drain_keys(self._h, arr.ctypes.data_as(ctypes.c_void_p), n,
                                         MEM_HOST, ctypes.byref(got)), "sim_drain_keys", self._h)
         return arr[:got.value]
+
+    def accumulate(self, t_begin: int, t_end: int, counts=None):
+        """Adds the pending events with t_begin <= t < t_end to a frame of accumulated events
+        uint32 [2, H, W] (plane 0 positive, plane 1 negative): a new numpy array, a numpy array
+        `counts`, or a torch int32 device tensor `counts` (stream-ordered).  Pending events stay
+        pending."""
+        shape = (2, self.height, self.width)
+        if counts is None:
+            counts = np.zeros(shape, dtype=np.uint32)
+        if not _is_torch(counts) and (counts.dtype != np.uint32 or not counts.flags.c_contiguous):
+            raise TypeError("counts must be a C-contiguous uint32 array")
+        ptr, kind, keep = _buffer(counts, np.uint32, shape)
+        _check(self._lib.sim_accumulate(self._h, int(t_begin), int(t_end), ptr, kind),
+               "sim_accumulate", self._h)
+        return counts
+
+    def event_rate(self, t_begin: int, t_end: int):
+        """Events per pixel and second of the pending events in [t_begin, t_end): returns
+        (mean, standard deviation over pixels, (sum c, sum c^2))."""
+        mean, std = ctypes.c_double(), ctypes.c_double()
+        sums = (ctypes.c_uint64 * 2)()
+        _check(self._lib.sim_event_rate(self._h, int(t_begin), int(t_end), ctypes.byref(mean),
+                                        ctypes.byref(std), sums), "sim_event_rate", self._h)
+        return mean.value, std.value, (int(sums[0]), int(sums[1]))
 
     # -- state ----------------------------------------------------------------------------
     @property

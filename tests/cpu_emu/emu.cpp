@@ -25,8 +25,12 @@
 #endif
 
 namespace evsim {
-// dynamic shared memory ("extern __shared__ float smem[]") of the block that is running
-thread_local float smem[1 << 16];
+// Dynamic shared memory ("extern __shared__ float smem[]") of the block that is running.  The
+// initializer is not a constant, so the compiler emits this variable's TLS init function: g++
+// calls that function unconditionally from function templates that declare the array `extern`,
+// and without a definition the call would jump to address 0.
+static float zero_value() { return 0.0f; }
+thread_local float smem[1 << 16] = {zero_value()};
 }
 
 // Minimal x86-64 (System V) stack switch: saves the callee-saved registers and the SSE/x87
@@ -280,6 +284,9 @@ uint64_t emu_wave_exchange(int op, uint64_t value, int arg, int line) {
 void emu_run_grid(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body,
                   const char* name) {
     if (shmem > sizeof(evsim::smem)) die("dynamic shared memory request too large");
+    if (getenv("EMU_TRACE"))
+        fprintf(stderr, "emu: launch %s grid %u block %u shmem %zu\n", name, grid.x, block.x,
+                shmem);
     if (block.y != 1 || block.z != 1 || block.x == 0 || block.x > 1024) die("unsupported block");
     g_gdim = grid;
     g_bdim = block;

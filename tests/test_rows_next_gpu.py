@@ -1,0 +1,107 @@
+"""GPU parity of the memoryless thresholding (the paper's Sec. III-A equations taken literally),
+the difference-frame method (Sec. III-C), the accumulated event frame (Fig. 1 caption) and the
+events/(pixel s) statistic (Sec. IV-C): through the C ABI, bit for bit against the CPU oracle.
+
+Collected after the parity tests of the reference-level path, so a failure here cannot hide them.
+"""
+import numpy as np
+import pytest
+
+import golden_io
+from oracle.oracle import accumulate as oracle_accumulate, event_rate as oracle_event_rate
+from paper_2209_04634_amd import sim, synth
+from test_parity_gpu import assert_parity, oracle_keys
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("path", golden_io.next_fixtures(), ids=lambda p: p.rsplit("/", 1)[-1])
+def test_next_hand_worked_fixtures(path):
+    g = golden_io.load(path)
+    for mode in ("window", "single"):
+        s = sim.Stream(g.frames.shape[2], g.frames.shape[1], **g.cfg)
+        if mode == "window":
+            s.push_frames(g.frames, g.flows, g.t_us)
+        else:
+            for k in range(len(g.t_us)):
+                s.push(g.frames[k], None if k == 0 else g.flows[k - 1], g.t_us[k])
+        t, x, y, p = sim.decode_keys(s.drain_keys(), g.t_us[0])
+        assert list(zip(t.tolist(), x.tolist(), y.tolist(), p.tolist())) == \
+            [e for iv in g.events for e in iv], mode
+        np.testing.assert_array_equal(s.reference(), g.lref)
+        s.close()
+
+
+@pytest.mark.parametrize("S", [1, 2, 11, 33])
+@pytest.mark.parametrize("method", [sim.BASIC, sim.DENSE, sim.SPARSE, sim.DIFFERENCE])
+def test_memoryless_ragged_image(method, S):
+    """A 61x97 image (ragged against every tile), four intervals; S = 33 exceeds the LDS stash
+    so interior samples are recomputed."""
+    if method == sim.BASIC and S != 1:
+        pytest.skip("basic has one sub-interval")
+    rng = np.random.default_rng(900 + 100 * S + method)
+    frames, flows = synth.random_frames(rng, 5, 61, 97, flow_scale=3.0)
+    t = np.array([0, 33333, 50000, 83333, 90001])
+    C = 0.3 if method == sim.BASIC else 0.05
+    assert_parity(frames, flows, t, modes=("window", "single"), method=method, c_pos=C,
+                  c_neg=C * 1.2, n_interp=S - 1, thresh_mode=sim.MEMORYLESS)
+
+
+def test_difference_346x260_full_sequence():
+    """The dense workload's 346x260 60-frame blob video through the difference method (Table I:
+    10 interpolated difference frames), one window, chunks and device inputs."""
+    v = synth.blob_video(synth.dense_346x260())
+    n = assert_parity(v.frames, v.flows, v.t_us, modes=("window", "chunks", "device"),
+                      method=sim.DIFFERENCE, c_pos=0.3, c_neg=0.3, n_interp=10,
+                      event_capacity=1 << 23)
+    assert n > 10000
+
+
+def test_memoryless_dense_346x260_full_sequence():
+    v = synth.blob_video(synth.dense_346x260())
+    n = assert_parity(v.frames, v.flows, v.t_us, modes=("window", "chunks"), method=sim.DENSE,
+                      c_pos=0.03, c_neg=0.03, n_interp=10, thresh_mode=sim.MEMORYLESS,
+                      event_capacity=1 << 23)
+    assert n > 10000
+
+
+def test_memoryless_sparse_1280x720_full_sequence():
+    v = synth.blob_video(synth.sparse_1280x720())
+    n = assert_parity(v.frames, v.flows, v.t_us, method=sim.SPARSE, c_pos=0.03, c_neg=0.03,
+                      n_interp=10, thresh_mode=sim.MEMORYLESS, event_capacity=1 << 24)
+    assert n > 10000
+
+
+def test_difference_spans_windows():
+    """140 frames in one push: two windows; the second takes its older frames from the state."""
+    spec = synth.BlobVideoSpec(64, 48, 140, 60.0, 6, seed=4, motion="random", speed_max=3.0)
+    v = synth.blob_video(spec)
+    assert_parity(v.frames, v.flows, v.t_us, modes=("window", "chunks"), method=sim.DIFFERENCE,
+                  c_pos=0.05, c_neg=0.05, n_interp=3)
+
+
+def test_accumulated_frame_and_event_rate():
+    """Accumulated frames (host numpy and device int32 tensor) and the events/(pixel s)
+    statistic of the sparse 1280x720 sequence over 1/fps windows and the whole sequence."""
+    import torch
+    v = synth.blob_video(synth.sparse_1280x720())
+    cfg = dict(method=sim.SPARSE, c_pos=0.2, c_neg=0.2, n_interp=10)
+    ok, _ = oracle_keys(v.frames, v.flows, v.t_us, **cfg)
+    s = sim.Stream(1280, 720, **cfg)
+    s.push_frames(v.frames, v.flows, v.t_us)
+    epoch = int(v.t_us[0])
+    t = [int(x) for x in v.t_us]
+    windows = [(t[10], t[11]), (t[0], t[-1] + 1), (t[50] + 7, t[90] - 3), (t[-1] + 1, t[-1] + 9)]
+    for a, b in windows:
+        ref = oracle_accumulate(ok, epoch, a, b, 1280, 720)
+        np.testing.assert_array_equal(s.accumulate(a, b), ref)
+        dev = torch.zeros((2, 720, 1280), dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()            # the zero fill runs on torch's stream
+        s.accumulate(a, b, counts=dev)
+        s.sync()
+        np.testing.assert_array_equal(dev.cpu().numpy().view(np.uint32), ref)
+        m, sd, sums = s.event_rate(a, b)
+        rm, rsd, rsums = oracle_event_rate(ref, a, b)
+        assert sums == rsums and m == rm and sd == rsd
+    assert s.pending() == len(ok)
+    s.close()
