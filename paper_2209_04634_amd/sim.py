@@ -175,6 +175,20 @@ def _buffer(x, dtype, shape=None):
     return a.ctypes.data_as(ctypes.c_void_p), MEM_HOST, a
 
 
+def _check_flows(flows, needed: int, H: int, W: int) -> None:
+    """The library reads `needed` flow fields of [H, W, 2] from `flows`: refuse anything smaller
+    before it reaches the device."""
+    if needed <= 0:
+        return
+    if flows is None:
+        raise ValueError(f"{needed} flow field(s) [H, W, 2] required")
+    shape = tuple(flows.shape)
+    if len(shape) == 3:
+        shape = (1,) + shape
+    if len(shape) != 4 or shape[1:] != (H, W, 2) or shape[0] < needed:
+        raise ValueError(f"flows must be [>= {needed}, {H}, {W}, 2], got {tuple(flows.shape)}")
+
+
 def make_config(width: int, height: int, method: Union[str, int] = "basic",
                 transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
                 log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
@@ -217,6 +231,16 @@ class Stream:
         self._lib = lib
         self.width, self.height = int(width), int(height)
         self.method = cfg.method
+        self.n_interp = cfg.n_interp
+
+    def _flows_needed(self, n_frames: int) -> int:
+        """Flow fields a push of n_frames reads: one per simulated interval for the
+        interpolating methods with S > 1 (the first frame of a stream only initialises it)."""
+        if self.method == BASIC or self.n_interp == 0:
+            return 0
+        e = ctypes.c_int64()
+        started = self._lib.sim_epoch(self._h, ctypes.byref(e)) == OK
+        return n_frames - (0 if started else 1)
 
     # -- frames ---------------------------------------------------------------------------
     def push(self, frame, flow=None, t_us: int = 0) -> int:
@@ -236,6 +260,7 @@ class Stream:
         H, W = self.height, self.width
         n = int(frames.shape[0])
         fp, fk, fa = _buffer(frames, np.uint8, (n, H, W))
+        _check_flows(flows, self._flows_needed(n), H, W)
         lp, lk, la = _buffer(flows, np.float32, None)
         if lk is not None and lk != fk:
             raise ValueError("frames and flows must both be host or both be device memory")
@@ -371,6 +396,7 @@ def push_batch(entries) -> list:
         H, W = stream.height, stream.width
         nf = int(frames.shape[0])
         fp, fk, fa = _buffer(frames, np.uint8, (nf, H, W))
+        _check_flows(flows, stream._flows_needed(nf), H, W)
         lp, lk, la = _buffer(flows, np.float32, None)
         if lk is not None and lk != fk:
             raise ValueError("frames and flows must both be host or both be device memory")

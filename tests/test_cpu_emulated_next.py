@@ -229,3 +229,26 @@ def test_emulated_next_paths_are_memory_safe_under_asan(tmp_path):
     res = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env,
                          timeout=900)
     assert res.returncode == 0 and "asan-clean" in res.stdout, res.stderr[-4000:]
+
+
+def test_binding_refuses_short_flow_arrays(emu_sim):
+    """The binding checks that a push hands over every flow field the library will read, so a
+    short array never reaches the device."""
+    rng = np.random.default_rng(0)
+    frames, flows = synth.random_frames(rng, 4, 6, 9)
+    for method in ("dense", "sparse", "difference"):
+        s = emu_sim.Stream(9, 6, method=method, n_interp=2)
+        with pytest.raises(ValueError):
+            s.push_frames(frames, flows[:2], [0, 1, 2, 3])       # needs 3
+        with pytest.raises(ValueError):
+            s.push_frames(frames, flows[:, :5], [0, 1, 2, 3])    # wrong image shape
+        s.push_frames(frames[:1], None, [0])                     # first frame: no flow
+        with pytest.raises(ValueError):
+            s.push_frames(frames[1:], flows[:2], [1, 2, 3])      # started: needs 3
+        with pytest.raises(ValueError):
+            emu_sim.push_batch([(s, frames[1:], None, [1, 2, 3])])
+        s.push_frames(frames[1:], flows, [1, 2, 3])
+        s.close()
+    s = emu_sim.Stream(9, 6, method="basic")
+    s.push_frames(frames, None, [0, 1, 2, 3])                    # basic reads no flow
+    s.close()
