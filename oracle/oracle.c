@@ -65,6 +65,7 @@
 enum { OR_BASIC = 0, OR_DENSE = 1, OR_SPARSE = 2, OR_DIFFERENCE = 3 };
 enum { OR_LOG = 0, OR_LINEAR = 1 };
 enum { OR_REFERENCE = 0, OR_MEMORYLESS = 1 };
+enum { OR_FLOW_SUPPLIED = 0, OR_FLOW_LK = 1 };
 
 typedef struct {
     int32_t width, height;
@@ -75,7 +76,15 @@ typedef struct {
     float mask_threshold;    /* sparse: < 0 -> min(c_pos, c_neg) */
     int32_t thresh_mode;     /* OR_REFERENCE or OR_MEMORYLESS; the difference method is always
                                 memoryless */
+    int32_t flow_source;     /* OR_FLOW_SUPPLIED or OR_FLOW_LK (dense and sparse methods) */
+    int32_t lk_levels, lk_radius, lk_iters;
+    float lk_eps, lk_min_trace, lk_min_ratio;
 } oracle_cfg;
+
+typedef struct {
+    int32_t levels, radius, iters;
+    float eps, min_trace, min_ratio;
+} oracle_lk;
 
 typedef struct {
     oracle_cfg cfg;
@@ -91,6 +100,7 @@ typedef struct {
     float* V;                /* scratch: S + 1 samples of one pixel */
     int started;
     int64_t t_prev, epoch;
+    float* lkflow;           /* flow estimated by Lucas-Kanade for the current interval */
     uint64_t* ev;            /* events of the last pushed interval (sorted keys) */
     uint64_t n_ev, cap_ev;
     uint64_t n_selected;     /* sparse: pixels selected in the last interval */
@@ -112,10 +122,12 @@ int oracle_lut(int32_t transform, float log_eps, float* lut) {
     return OR_OK;
 }
 
+static int lk_params_ok(const oracle_lk* P);
+
 static void or_destroy(oracle_sim* s) {
     if (!s) return;
     free(s->prev); free(s->prev2); free(s->lref); free(s->L0); free(s->L1); free(s->V);
-    free(s->ev);
+    free(s->lkflow); free(s->ev);
     free(s);
 }
 
@@ -128,6 +140,13 @@ int oracle_create(const oracle_cfg* cfg, oracle_sim** out) {
         return OR_E_INVAL;
     if (cfg->method < OR_BASIC || cfg->method > OR_DIFFERENCE) return OR_E_INVAL;
     if (cfg->thresh_mode != OR_REFERENCE && cfg->thresh_mode != OR_MEMORYLESS) return OR_E_INVAL;
+    if (cfg->flow_source != OR_FLOW_SUPPLIED && cfg->flow_source != OR_FLOW_LK) return OR_E_INVAL;
+    if (cfg->flow_source == OR_FLOW_LK) {
+        const oracle_lk P = {cfg->lk_levels, cfg->lk_radius, cfg->lk_iters, cfg->lk_eps,
+                             cfg->lk_min_trace, cfg->lk_min_ratio};
+        if (!lk_params_ok(&P)) return OR_E_INVAL;
+        if (cfg->method != OR_DENSE && cfg->method != OR_SPARSE) return OR_E_INVAL;
+    }
     if (!(cfg->c_pos > 0.0f) || !(cfg->c_neg > 0.0f)) return OR_E_INVAL;
     if (cfg->n_interp < 0 || cfg->n_interp > 255) return OR_E_INVAL;
     oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
@@ -143,7 +162,9 @@ int oracle_create(const oracle_cfg* cfg, oracle_sim** out) {
     s->L0 = (float*)malloc(n * sizeof(float));
     s->L1 = (float*)malloc(n * sizeof(float));
     s->V = (float*)malloc((size_t)(s->S + 1) * sizeof(float));
-    if (!s->prev || !s->prev2 || !s->lref || !s->L0 || !s->L1 || !s->V) {
+    if (cfg->flow_source == OR_FLOW_LK) s->lkflow = (float*)calloc(2 * n, sizeof(float));
+    if (!s->prev || !s->prev2 || !s->lref || !s->L0 || !s->L1 || !s->V ||
+        (cfg->flow_source == OR_FLOW_LK && !s->lkflow)) {
         or_destroy(s);
         return OR_E_NOMEM;
     }
@@ -166,6 +187,196 @@ static float bil(const float* L, int W, int H, float sx, float sy) {
     float top = gx * L[(size_t)y0 * W + x0] + fx * L[(size_t)y0 * W + x1];
     float bot = gx * L[(size_t)y1 * W + x0] + fx * L[(size_t)y1 * W + x1];
     return gy * top + fy * bot;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Pyramidal Lucas-Kanade flow (the sparse method estimates flow with Lucas-Kanade at the selected
+ * pixels, Sec. III-B, IV-A; here written from the published method: Lucas and Kanade's
+ * least-squares window fit, iterated, coarse to fine over an image pyramid).
+ *   Pyramid: level 0 is the frame's intensity; level l+1 has ceil(W/2) x ceil(H/2) texels, each
+ *   the 1-2-1 x 1-2-1 binomial average (/16) of level l around (2x, 2y), clamped at the border.
+ *   Gradient texels: central differences (T(x+1) - T(x-1)) / 2, clamped.  Samples at real
+ *   positions: clamp-to-edge bilinear of texels.
+ *   Per pixel p, from the coarsest level down, with guess g (0 at the top) and window offsets
+ *   (dx, dy) in [-r, r]^2 around u = p / 2^l: G = sum of [ix^2, ix iy; ix iy, iy^2] of the
+ *   gradients of I; the level is rejected (flow 0, invalid) unless trace(G) >= min_trace * N
+ *   (N = (2r+1)^2 texels: enough texture) and det(G) >= min_ratio * trace(G)^2 (no aperture
+ *   problem).  Then up to `iters` steps: b = sum of (I(u + d) - J(u + d + g + v)) [ix, iy],
+ *   step = G^-1 b (by Cramer's rule), v += step, stop once |step|^2 < eps.  Next level:
+ *   g = 2 (g + v); at level 0 the flow is g + v.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int W, H;
+    float* v;
+} or_img;
+
+static float img_at(const or_img* im, int x, int y) {
+    x = x < 0 ? 0 : (x >= im->W ? im->W - 1 : x);
+    y = y < 0 ? 0 : (y >= im->H ? im->H - 1 : y);
+    return im->v[(size_t)y * im->W + x];
+}
+
+static void pyr_down(const or_img* a, or_img* b) {
+    for (int y = 0; y < b->H; ++y) {
+        for (int x = 0; x < b->W; ++x) {
+            const int cx = 2 * x, cy = 2 * y;
+            const float c = img_at(a, cx, cy);
+            const float edges = img_at(a, cx - 1, cy) + img_at(a, cx + 1, cy) +
+                                img_at(a, cx, cy - 1) + img_at(a, cx, cy + 1);
+            const float corners = img_at(a, cx - 1, cy - 1) + img_at(a, cx + 1, cy - 1) +
+                                  img_at(a, cx - 1, cy + 1) + img_at(a, cx + 1, cy + 1);
+            b->v[(size_t)y * b->W + x] = ((4.0f * c + 2.0f * edges) + corners) * 0.0625f;
+        }
+    }
+}
+
+static float grad_x(const or_img* im, int x, int y) {
+    return (img_at(im, x + 1, y) - img_at(im, x - 1, y)) * 0.5f;
+}
+
+static float grad_y(const or_img* im, int x, int y) {
+    return (img_at(im, x, y + 1) - img_at(im, x, y - 1)) * 0.5f;
+}
+
+typedef struct {
+    int x0, y0, x1, y1;
+    float fx, fy, gx, gy;
+} or_tap;
+
+static or_tap tap_at(int W, int H, float sx, float sy) {
+    or_tap t;
+    sx = fminf(fmaxf(sx, 0.0f), (float)(W - 1));
+    sy = fminf(fmaxf(sy, 0.0f), (float)(H - 1));
+    t.x0 = (int)floorf(sx);
+    t.y0 = (int)floorf(sy);
+    t.fx = sx - (float)t.x0;
+    t.fy = sy - (float)t.y0;
+    t.x1 = t.x0 + 1 < W ? t.x0 + 1 : W - 1;
+    t.y1 = t.y0 + 1 < H ? t.y0 + 1 : H - 1;
+    t.gx = 1.0f - t.fx;
+    t.gy = 1.0f - t.fy;
+    return t;
+}
+
+/* kind 0: intensity, 1: x gradient, 2: y gradient texels */
+static float texel(const or_img* im, int kind, int x, int y) {
+    return kind == 0 ? im->v[(size_t)y * im->W + x] : (kind == 1 ? grad_x(im, x, y) : grad_y(im, x, y));
+}
+
+static float bil_tap(const or_img* im, int kind, or_tap t) {
+    const float top = t.gx * texel(im, kind, t.x0, t.y0) + t.fx * texel(im, kind, t.x1, t.y0);
+    const float bot = t.gx * texel(im, kind, t.x0, t.y1) + t.fx * texel(im, kind, t.x1, t.y1);
+    return t.gy * top + t.fy * bot;
+}
+
+/* Flow of integer pixel (px, py) from pyramid I to pyramid J; returns 1 if valid. */
+static int lk_point(const or_img* I, const or_img* J, const oracle_lk* P, int px, int py,
+                    float* fx, float* fy) {
+    const int r = P->radius;
+    const float N = (float)((2 * r + 1) * (2 * r + 1));
+    float gx = 0.0f, gy = 0.0f;
+    for (int l = P->levels; l >= 0; --l) {
+        const float sc = ldexpf(1.0f, -l);
+        const float ux = (float)px * sc, uy = (float)py * sc;
+        float Gxx = 0.0f, Gxy = 0.0f, Gyy = 0.0f;
+        for (int dy = -r; dy <= r; ++dy) {
+            for (int dx = -r; dx <= r; ++dx) {
+                const or_tap t = tap_at(I[l].W, I[l].H, ux + (float)dx, uy + (float)dy);
+                const float ix = bil_tap(&I[l], 1, t), iy = bil_tap(&I[l], 2, t);
+                Gxx += ix * ix;
+                Gxy += ix * iy;
+                Gyy += iy * iy;
+            }
+        }
+        const float trace = Gxx + Gyy;
+        const float det = Gxx * Gyy - Gxy * Gxy;
+        if (!(trace >= P->min_trace * N) || !(det >= P->min_ratio * trace * trace)) {
+            *fx = 0.0f;
+            *fy = 0.0f;
+            return 0;
+        }
+        float vx = 0.0f, vy = 0.0f;
+        for (int k = 0; k < P->iters; ++k) {
+            float bx = 0.0f, by = 0.0f;
+            for (int dy = -r; dy <= r; ++dy) {
+                for (int dx = -r; dx <= r; ++dx) {
+                    const float x = ux + (float)dx, y = uy + (float)dy;
+                    const or_tap t = tap_at(I[l].W, I[l].H, x, y);
+                    const float ix = bil_tap(&I[l], 1, t), iy = bil_tap(&I[l], 2, t);
+                    const float i0 = bil_tap(&I[l], 0, t);
+                    const or_tap u = tap_at(J[l].W, J[l].H, x + (gx + vx), y + (gy + vy));
+                    const float d = i0 - bil_tap(&J[l], 0, u);
+                    bx += d * ix;
+                    by += d * iy;
+                }
+            }
+            const float ex = (Gyy * bx - Gxy * by) / det;
+            const float ey = (Gxx * by - Gxy * bx) / det;
+            vx += ex;
+            vy += ey;
+            if (ex * ex + ey * ey < P->eps) break;
+        }
+        if (l > 0) {
+            gx = 2.0f * (gx + vx);
+            gy = 2.0f * (gy + vy);
+        } else {
+            *fx = gx + vx;
+            *fy = gy + vy;
+        }
+    }
+    return 1;
+}
+
+static int lk_params_ok(const oracle_lk* P) {
+    return P->levels >= 0 && P->levels <= 4 && P->radius >= 1 && P->radius <= 15 &&
+           P->iters >= 1 && P->iters <= 100 && P->eps >= 0.0f && P->min_trace >= 0.0f &&
+           P->min_ratio >= 0.0f;
+}
+
+/* Pyramids of one frame: levels 0..L in one allocation; returns NULL on failure. */
+static float* build_pyramid(const uint8_t* f, int W, int H, int L, or_img* lv) {
+    size_t total = 0;
+    int w = W, h = H;
+    for (int l = 0; l <= L; ++l) {
+        total += (size_t)w * h;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    float* mem = (float*)malloc(total * sizeof(float));
+    if (!mem) return NULL;
+    size_t off = 0;
+    w = W;
+    h = H;
+    for (int l = 0; l <= L; ++l) {
+        lv[l].W = w;
+        lv[l].H = h;
+        lv[l].v = mem + off;
+        off += (size_t)w * h;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    for (size_t i = 0; i < (size_t)W * H; ++i) lv[0].v[i] = (float)f[i];
+    for (int l = 1; l <= L; ++l) pyr_down(&lv[l - 1], &lv[l]);
+    return mem;
+}
+
+/* Lucas-Kanade flow from f0 to f1 at pixel indices points[j] = y * W + x: flow[2j], flow[2j+1]
+ * (dx, dy), valid[j] (may be NULL). */
+int oracle_lk_flow(const uint8_t* f0, const uint8_t* f1, int W, int H, const oracle_lk* P,
+                   const uint32_t* points, uint64_t n, float* flow, uint8_t* valid) {
+    if (!f0 || !f1 || !P || W < 1 || H < 1 || !lk_params_ok(P)) return OR_E_INVAL;
+    or_img I[5], J[5];
+    float* a = build_pyramid(f0, W, H, P->levels, I);
+    float* b = build_pyramid(f1, W, H, P->levels, J);
+    if (!a || !b) { free(a); free(b); return OR_E_NOMEM; }
+    for (uint64_t j = 0; j < n; ++j) {
+        const int px = (int)(points[j] % (uint32_t)W), py = (int)(points[j] / (uint32_t)W);
+        const int ok = lk_point(I, J, P, px, py, &flow[2 * j], &flow[2 * j + 1]);
+        if (valid) valid[j] = (uint8_t)ok;
+    }
+    free(a);
+    free(b);
+    return OR_OK;
 }
 
 static int push_event(oracle_sim* s, int64_t t, int x, int y, int pol) {
@@ -261,7 +472,8 @@ int oracle_push(oracle_sim* s, const uint8_t* frame, const float* flow, int64_t 
     /* the difference method's first interval has one difference frame only: nothing to
      * interpolate and no flow needed */
     const int diff_first = diff && s->n_int == 0;
-    if (s->cfg.method != OR_BASIC && !diff_first && !flow) return OR_E_INVAL;
+    if (s->cfg.method != OR_BASIC && !diff_first && !flow && s->cfg.flow_source != OR_FLOW_LK)
+        return OR_E_INVAL;
 
     const int64_t t0 = s->t_prev;
     const float delta = (float)(t_us - t0);
@@ -281,6 +493,28 @@ int oracle_push(oracle_sim* s, const uint8_t* frame, const float* flow, int64_t 
     for (size_t i = 0; i < n; ++i) {
         s->L0[i] = s->lut[s->prev[i]];
         s->L1[i] = s->lut[frame[i]];
+    }
+    if (s->cfg.flow_source == OR_FLOW_LK && S > 1) {
+        /* estimate the flow at every pixel that will be interpolated (sparse: the selected) */
+        uint32_t* pts = (uint32_t*)malloc(n * sizeof(uint32_t));
+        float* fl = (float*)malloc(2 * n * sizeof(float));
+        if (!pts || !fl) { free(pts); free(fl); return OR_E_NOMEM; }
+        uint64_t np = 0;
+        for (size_t i = 0; i < n; ++i)
+            if (s->cfg.method != OR_SPARSE || fabsf(s->L1[i] - s->L0[i]) >= s->m)
+                pts[np++] = (uint32_t)i;
+        const oracle_lk P = {s->cfg.lk_levels, s->cfg.lk_radius, s->cfg.lk_iters, s->cfg.lk_eps,
+                             s->cfg.lk_min_trace, s->cfg.lk_min_ratio};
+        int rc = oracle_lk_flow(s->prev, frame, W, H, &P, pts, np, fl, NULL);
+        if (rc == OR_OK)
+            for (uint64_t j = 0; j < np; ++j) {
+                s->lkflow[2 * (size_t)pts[j]] = fl[2 * j];
+                s->lkflow[2 * (size_t)pts[j] + 1] = fl[2 * j + 1];
+            }
+        free(pts);
+        free(fl);
+        if (rc != OR_OK) return rc;
+        flow = s->lkflow;
     }
     float* V = s->V;
     for (int y = 0; y < H; ++y) {

@@ -16,6 +16,9 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 BASIC, DENSE, SPARSE, DIFFERENCE = 0, 1, 2, 3
 LOG, LINEAR = 0, 1
 REFERENCE, MEMORYLESS = 0, 1
+FLOW_SUPPLIED, FLOW_LK = 0, 1
+LK_DEFAULTS = dict(lk_levels=3, lk_radius=7, lk_iters=10, lk_eps=1e-4, lk_min_trace=1.0,
+                   lk_min_ratio=1e-3)
 
 
 def build(force: bool = True) -> str:
@@ -32,7 +35,17 @@ class _Cfg(ctypes.Structure):
                 ("method", ctypes.c_int32), ("transform", ctypes.c_int32),
                 ("c_pos", ctypes.c_float), ("c_neg", ctypes.c_float),
                 ("log_eps", ctypes.c_float), ("n_interp", ctypes.c_int32),
-                ("mask_threshold", ctypes.c_float), ("thresh_mode", ctypes.c_int32)]
+                ("mask_threshold", ctypes.c_float), ("thresh_mode", ctypes.c_int32),
+                ("flow_source", ctypes.c_int32), ("lk_levels", ctypes.c_int32),
+                ("lk_radius", ctypes.c_int32), ("lk_iters", ctypes.c_int32),
+                ("lk_eps", ctypes.c_float), ("lk_min_trace", ctypes.c_float),
+                ("lk_min_ratio", ctypes.c_float)]
+
+
+class _Lk(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("min_trace", ctypes.c_float), ("min_ratio", ctypes.c_float)]
 
 
 _lib = None
@@ -59,6 +72,8 @@ def _bind(lib):
                                       ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), P]
     lib.oracle_event_rate.restype = None
+    lib.oracle_lk_flow.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Lk), P,
+                                   ctypes.c_uint64, P, P]
     return lib
 
 
@@ -90,10 +105,17 @@ def lut(transform: int = LOG, log_eps: float = 1e-3) -> np.ndarray:
 class OracleSim:
     def __init__(self, width: int, height: int, method: int = BASIC, transform: int = LOG,
                  c_pos: float = 0.2, c_neg: float = 0.2, log_eps: float = 1e-3,
-                 n_interp: int = 10, mask_threshold: float = -1.0, thresh_mode: int = REFERENCE):
+                 n_interp: int = 10, mask_threshold: float = -1.0, thresh_mode: int = REFERENCE,
+                 flow_source: int = FLOW_SUPPLIED, **lk):
         self.width, self.height = width, height
+        lkp = dict(LK_DEFAULTS)
+        for k, v in lk.items():
+            if k not in lkp:
+                raise TypeError(f"unknown argument {k}")
+            lkp[k] = v
         cfg = _Cfg(width, height, method, transform, c_pos, c_neg, log_eps, n_interp,
-                   mask_threshold, thresh_mode)
+                   mask_threshold, thresh_mode, flow_source, lkp["lk_levels"], lkp["lk_radius"],
+                   lkp["lk_iters"], lkp["lk_eps"], lkp["lk_min_trace"], lkp["lk_min_ratio"])
         h = ctypes.c_void_p()
         self._lib = _load()
         rc = self._lib.oracle_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -182,6 +204,28 @@ def event_rate(counts: np.ndarray, t_begin: int, t_end: int):
     _load().oracle_event_rate(_ptr(counts), W, H, (t_end - t_begin) * 1e-6, ctypes.byref(mean),
                               ctypes.byref(std), _ptr(sums))
     return mean.value, std.value, (int(sums[0]), int(sums[1]))
+
+
+def lk_flow(f0: np.ndarray, f1: np.ndarray, points=None, levels: int = 3, radius: int = 7,
+            iters: int = 10, eps: float = 1e-4, min_trace: float = 1.0,
+            min_ratio: float = 1e-3):
+    """Pyramidal Lucas-Kanade flow from f0 to f1 (uint8 [H, W]) at pixel indices `points`
+    (y * W + x; default every pixel): returns (flow float32 [n, 2], valid bool [n])."""
+    f0 = np.ascontiguousarray(f0, dtype=np.uint8)
+    f1 = np.ascontiguousarray(f1, dtype=np.uint8)
+    H, W = f0.shape
+    assert f1.shape == (H, W)
+    if points is None:
+        points = np.arange(H * W, dtype=np.uint32)
+    points = np.ascontiguousarray(points, dtype=np.uint32)
+    flow = np.zeros((points.size, 2), dtype=np.float32)
+    valid = np.zeros(points.size, dtype=np.uint8)
+    P = _Lk(levels, radius, iters, eps, min_trace, min_ratio)
+    rc = _load().oracle_lk_flow(_ptr(f0), _ptr(f1), W, H, ctypes.byref(P), _ptr(points),
+                                points.size, _ptr(flow), _ptr(valid))
+    if rc != 0:
+        raise ValueError(f"oracle_lk_flow failed ({rc})")
+    return flow, valid.astype(bool)
 
 
 def decode(keys: np.ndarray, epoch: int = 0):
