@@ -72,6 +72,7 @@ extern "C" {
 
 enum { SIM_BASIC = 0, SIM_DENSE = 1, SIM_SPARSE = 2, SIM_DIFFERENCE = 3 };
 enum { SIM_THRESH_REFERENCE = 0, SIM_THRESH_MEMORYLESS = 1 };
+enum { SIM_FLOW_SUPPLIED = 0, SIM_FLOW_LK = 1 };
 enum { SIM_LOG = 0, SIM_LINEAR = 1 };
 enum { SIM_MEM_HOST = 0, SIM_MEM_DEVICE = 1 };
 
@@ -88,8 +89,20 @@ typedef struct sim_config {
     void* hip_stream;           /* hipStream_t to order all work on; NULL -> library-owned stream   */
     int32_t thresh_mode;        /* SIM_THRESH_REFERENCE (default: reference level, event pixel) |   */
                                 /* SIM_THRESH_MEMORYLESS (paper's equations); DIFFERENCE: ignored   */
-    int32_t reserved;           /* must be 0                                                        */
+    int32_t flow_source;        /* SIM_FLOW_SUPPLIED (default: flow passed with each frame) |       */
+                                /* SIM_FLOW_LK (estimated on the device, see sim_lk_flow; DENSE and */
+                                /* SPARSE only; the flow arguments are then ignored and may be NULL) */
 } sim_config;
+
+/* Parameters of the pyramidal Lucas-Kanade estimator (sim_lk_flow, SIM_FLOW_LK). */
+typedef struct sim_lk_params {
+    int32_t levels;             /* pyramid levels above full resolution, 0..4 (default 3)           */
+    int32_t radius;             /* window half size r: (2r+1)^2 texels, 1..15 (default 7)            */
+    int32_t iterations;         /* Gauss-Newton steps per level, 1..100 (default 10)                */
+    float eps;                  /* stop a level once |step|^2 < eps, px^2 (default 1e-4)            */
+    float min_trace;            /* texture: trace(G) >= min_trace * (2r+1)^2 (default 1)            */
+    float min_ratio;            /* aperture: det(G) >= min_ratio * trace(G)^2 (default 1e-3)       */
+} sim_lk_params;
 
 /* One event as drained to the host (16 bytes). */
 typedef struct sim_event {
@@ -126,9 +139,9 @@ void sim_config_init(sim_config* cfg);
 
 /* Creates a stream (device state: reference levels, previous frame, table, event buffers).
  * cfg is copied.  On success *out owns the handle until sim_destroy.  Errors: SIM_E_INVAL
- * (dimension out of 1..4096, method/transform/thresh_mode unknown, reserved not 0, thresholds
- * not > 0 or so small that R + C == R for some reachable R, n_interp outside 0..255, log_eps not
- * > 0), SIM_E_NOMEM. */
+ * (dimension out of 1..4096, method/transform/thresh_mode/flow_source unknown, SIM_FLOW_LK
+ * with a method other than DENSE or SPARSE, thresholds not > 0 or so small that R + C == R for
+ * some reachable R, n_interp outside 0..255, log_eps not > 0), SIM_E_NOMEM. */
 int sim_create(const sim_config* cfg, sim_stream** out);
 
 /* Releases every resource of the handle after the work queued on its stream completes. */
@@ -239,6 +252,33 @@ int sim_accumulate(sim_stream* s, int64_t t_begin, int64_t t_end, uint32_t* coun
  * Synchronises the stream.  Errors: SIM_E_INVAL (NULL mean or stddev, t_end <= t_begin). */
 int sim_event_rate(sim_stream* s, int64_t t_begin, int64_t t_end, double* mean, double* stddev,
                    uint64_t* sums);
+
+/* Fills p with the defaults listed in sim_lk_params. */
+void sim_lk_params_init(sim_lk_params* p);
+
+/* Parameters used by a SIM_FLOW_LK stream from its next push on (defaults until called).
+ * Errors: SIM_E_INVAL (NULL, a field out of its range). */
+int sim_set_lk_params(sim_stream* s, const sim_lk_params* p);
+
+/* Pyramidal Lucas-Kanade flow (the sparse method's flow estimator, Sec. III-B; the method of
+ * Lucas and Kanade, iterated coarse to fine) from frame f0 to frame f1 (uint8 [height][width])
+ * at the pixel indices points[j] = y * width + x: flow[2j], flow[2j+1] = (dx, dy) in pixels,
+ * valid[j] (may be NULL) = 1, or 0 with flow (0, 0) where the window lacks texture, has only
+ * one-dimensional structure, or the index is outside the image.
+ *   Pyramid: level 0 = intensity; level l+1 (ceil(W/2) x ceil(H/2)) = 1-2-1 x 1-2-1 binomial
+ *   average / 16 around (2x, 2y), clamped.  Gradients: central differences / 2, clamped.
+ *   Samples: clamp-to-edge bilinear.  From the coarsest level, guess g = 0, window offsets
+ *   d in [-r, r]^2 around u = p / 2^l: G = sum [ix^2, ix iy; ix iy, iy^2]; valid only if
+ *   trace(G) >= min_trace (2r+1)^2 and det(G) >= min_ratio trace(G)^2; up to `iterations` steps
+ *   b = sum (I(u+d) - J(u+d+g+v)) [ix, iy], step = G^-1 b, v += step, until |step|^2 < eps;
+ *   g = 2 (g + v) between levels; flow = g + v.  fp32, one rounding per operation.
+ * Every pointer is host or device memory as mem_kind says; work is ordered on hip_stream (NULL:
+ * a stream of the call) and complete when the call returns.  params NULL: defaults.
+ * Errors: SIM_E_INVAL (NULL pointers with n_points > 0, dimensions outside 1..4096, params out
+ * of range), SIM_E_NOMEM, SIM_E_HIP. */
+int sim_lk_flow(const uint8_t* f0, const uint8_t* f1, int32_t width, int32_t height,
+                const uint32_t* points, uint64_t n_points, float* flow, uint8_t* valid,
+                const sim_lk_params* params, int32_t mem_kind, void* hip_stream);
 
 /* Text describing the HIP failure that poisoned the handle (call, source line, HIP's message);
  * empty when there was none.  Valid until the next call on the handle. */

@@ -371,7 +371,9 @@ int oracle_lk_flow(const uint8_t* f0, const uint8_t* f1, int W, int H, const ora
     if (!a || !b) { free(a); free(b); return OR_E_NOMEM; }
     for (uint64_t j = 0; j < n; ++j) {
         const int px = (int)(points[j] % (uint32_t)W), py = (int)(points[j] / (uint32_t)W);
-        const int ok = lk_point(I, J, P, px, py, &flow[2 * j], &flow[2 * j + 1]);
+        int ok = 0;
+        flow[2 * j] = flow[2 * j + 1] = 0.0f;
+        if (py < H) ok = lk_point(I, J, P, px, py, &flow[2 * j], &flow[2 * j + 1]);
         if (valid) valid[j] = (uint8_t)ok;
     }
     free(a);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libevsim.so")
-SOURCES = ["evsim_kernels.hip", "evsim_runtime.hip", "evsim_server.hip"]
+SOURCES = ["evsim_kernels.hip", "evsim_runtime.hip", "evsim_server.hip", "evsim_lk.hip"]
 ARCH = os.environ.get("EVSIM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -124,4 +124,49 @@ int moments_blocks(uint64_t plane);
 hipError_t launch_moments(const uint32_t* counts, uint64_t plane, unsigned long long* part,
                           hipStream_t stream);
 
+// ------------------------------------------------------------------------------------------
+// Pyramidal Lucas-Kanade flow (evsim_lk.hip).
+// ------------------------------------------------------------------------------------------
+constexpr int kLkMaxLevels = 4;      // pyramid levels above full resolution
+
+struct LkParams {
+    int levels, radius, iters;
+    float eps, min_trace, min_ratio;
+};
+
+// Layout of one frame's pyramid inside a float buffer: level l has w[l] x h[l] texels at off[l].
+struct PyrLayout {
+    int levels;
+    int w[kLkMaxLevels + 1], h[kLkMaxLevels + 1];
+    uint64_t off[kLkMaxLevels + 1];
+    uint64_t total;                  // floats per frame
+};
+PyrLayout pyr_layout(int W, int H, int levels);
+
+// Pyramids of n uint8 frames, frame f's written at pyr + f * lay.total.  Frame 0 is `first`,
+// frame f > 0 is rest + (f - 1) * fstride (a window's previous frame, then its frames).
+hipError_t launch_pyramids(const uint8_t* first, const uint8_t* rest, int64_t fstride, int n,
+                           const PyrLayout& lay, float* pyr, hipStream_t stream);
+
+// Flow of every pixel index points[j] from pyramid a to pyramid b.
+hipError_t launch_lk_points(const float* a, const float* b, const PyrLayout& lay,
+                            const LkParams& P, const uint32_t* points, uint64_t n, float* flow,
+                            uint8_t* valid, hipStream_t stream);
+
+// Flow of a window: for every chain slot's pixel (active list of the sparse method, or every
+// pixel) and every selected interval i, the flow from pyramid i to pyramid i + 1 into
+// flow + i * 2 * npix + 2 * p (the layout of supplied flows).
+struct LkWindowArgs {
+    const float* pyr;                // K + 1 pyramids (previous frame, then the window's frames)
+    PyrLayout lay;
+    LkParams P;
+    const uint32_t* mask;            // sparse: [kMaskWords][npix]; null: every interval
+    const uint32_t* act_px;          // sparse: active sub-lists; null: slot = pixel
+    const unsigned int* n_active;
+    int act_cap;
+    int npix, W, K;
+    float* flow;
+};
+hipError_t launch_lk_window(const LkWindowArgs& a, int max_slots, hipStream_t stream);
+
 }  // namespace evsim

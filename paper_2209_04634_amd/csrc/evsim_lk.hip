@@ -1,0 +1,277 @@
+// Pyramidal Lucas-Kanade flow on gfx950: the flow the sparse method needs at its selected pixels
+// (Sec. III-B, where the paper estimates it with Lucas-Kanade) estimated on the device instead of
+// supplied.  The method is Lucas and Kanade's least-squares window fit, iterated, coarse to fine:
+//   pyramid level 0 = the frame's intensity; level l+1 (ceil(W/2) x ceil(H/2)) = the 1-2-1 x 1-2-1
+//   binomial average (/16) of level l around (2x, 2y), clamped; gradient texels are central
+//   differences (T(x+1) - T(x-1)) / 2, clamped; samples at real positions are clamp-to-edge
+//   bilinear blends of texels.  Per pixel p, from the coarsest level down with guess g (0 at the
+//   top), window offsets (dx, dy) in [-r, r]^2 around u = p / 2^l: G = sum [ix^2, ix iy; ix iy,
+//   iy^2]; the pixel is invalid (flow 0) unless trace(G) >= min_trace (2r+1)^2 and det(G) >=
+//   min_ratio trace(G)^2; then up to `iters` steps b = sum (I(u+d) - J(u+d+g+v)) [ix, iy],
+//   step = G^-1 b (Cramer's rule), v += step, stopping once |step|^2 < eps; g = 2 (g + v) for the
+//   next level, flow = g + v at level 0.
+// Every value of the pyramid and of the gradients is exact in fp32 (dyadic with at most 24
+// significant bits for <= 4 levels of 8-bit input), and every other operation is one fp32
+// operation with one rounding in the order written (-ffp-contract=off).
+#include "evsim_internal.h"
+
+#include <algorithm>
+
+#pragma clang fp contract(off)
+
+namespace evsim {
+
+PyrLayout pyr_layout(int W, int H, int levels) {
+    PyrLayout L;
+    L.levels = levels;
+    uint64_t off = 0;
+    int w = W, h = H;
+    for (int l = 0; l <= kLkMaxLevels; ++l) {
+        L.w[l] = w;
+        L.h[l] = h;
+        L.off[l] = off;
+        if (l <= levels) off += (uint64_t)w * (uint64_t)h;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    L.total = off;
+    return L;
+}
+
+namespace {
+
+struct Level {
+    const float* v;
+    int w, h;
+};
+
+__device__ __forceinline__ Level level_of(const float* pyr, const PyrLayout& L, int l) {
+    Level r;
+    r.v = pyr + L.off[l];
+    r.w = L.w[l];
+    r.h = L.h[l];
+    return r;
+}
+
+__device__ __forceinline__ float texel_at(const Level& T, int x, int y) {
+    x = x < 0 ? 0 : (x >= T.w ? T.w - 1 : x);
+    y = y < 0 ? 0 : (y >= T.h ? T.h - 1 : y);
+    return T.v[(int64_t)y * T.w + x];
+}
+
+struct Tap {
+    int x0, y0, x1, y1;
+    float fx, fy, gx, gy;
+};
+
+__device__ __forceinline__ Tap tap_at(const Level& T, float sx, float sy) {
+    Tap t;
+    sx = fminf(fmaxf(sx, 0.0f), (float)(T.w - 1));
+    sy = fminf(fmaxf(sy, 0.0f), (float)(T.h - 1));
+    t.x0 = (int)floorf(sx);
+    t.y0 = (int)floorf(sy);
+    t.fx = sx - (float)t.x0;
+    t.fy = sy - (float)t.y0;
+    t.x1 = min(t.x0 + 1, T.w - 1);
+    t.y1 = min(t.y0 + 1, T.h - 1);
+    t.gx = 1.0f - t.fx;
+    t.gy = 1.0f - t.fy;
+    return t;
+}
+
+// kind 0: intensity; 1: x gradient; 2: y gradient texel at (x, y) (inside the level).
+template <int KIND>
+__device__ __forceinline__ float texel(const Level& T, int x, int y) {
+    if constexpr (KIND == 0)
+        return T.v[(int64_t)y * T.w + x];
+    else if constexpr (KIND == 1)
+        return (texel_at(T, x + 1, y) - texel_at(T, x - 1, y)) * 0.5f;
+    else
+        return (texel_at(T, x, y + 1) - texel_at(T, x, y - 1)) * 0.5f;
+}
+
+template <int KIND>
+__device__ __forceinline__ float bil_tap(const Level& T, const Tap& t) {
+    const float top = t.gx * texel<KIND>(T, t.x0, t.y0) + t.fx * texel<KIND>(T, t.x1, t.y0);
+    const float bot = t.gx * texel<KIND>(T, t.x0, t.y1) + t.fx * texel<KIND>(T, t.x1, t.y1);
+    return t.gy * top + t.fy * bot;
+}
+
+// Flow of integer pixel (px, py) from pyramid A to pyramid B; returns true if valid.
+__device__ bool lk_point(const float* A, const float* B, const PyrLayout& L, const LkParams& P,
+                         int px, int py, float* fx, float* fy) {
+    const int r = P.radius;
+    const float N = (float)((2 * r + 1) * (2 * r + 1));
+    float gx = 0.0f, gy = 0.0f;
+    for (int l = P.levels; l >= 0; --l) {
+        const Level I = level_of(A, L, l);
+        const Level J = level_of(B, L, l);
+        const float sc = ldexpf(1.0f, -l);
+        const float ux = (float)px * sc, uy = (float)py * sc;
+        float Gxx = 0.0f, Gxy = 0.0f, Gyy = 0.0f;
+        for (int dy = -r; dy <= r; ++dy) {
+            for (int dx = -r; dx <= r; ++dx) {
+                const Tap t = tap_at(I, ux + (float)dx, uy + (float)dy);
+                const float ix = bil_tap<1>(I, t), iy = bil_tap<2>(I, t);
+                Gxx += ix * ix;
+                Gxy += ix * iy;
+                Gyy += iy * iy;
+            }
+        }
+        const float trace = Gxx + Gyy;
+        const float det = Gxx * Gyy - Gxy * Gxy;
+        if (!(trace >= P.min_trace * N) || !(det >= P.min_ratio * trace * trace)) {
+            *fx = 0.0f;
+            *fy = 0.0f;
+            return false;
+        }
+        float vx = 0.0f, vy = 0.0f;
+        for (int k = 0; k < P.iters; ++k) {
+            float bx = 0.0f, by = 0.0f;
+            for (int dy = -r; dy <= r; ++dy) {
+                for (int dx = -r; dx <= r; ++dx) {
+                    const float x = ux + (float)dx, y = uy + (float)dy;
+                    const Tap t = tap_at(I, x, y);
+                    const float ix = bil_tap<1>(I, t), iy = bil_tap<2>(I, t);
+                    const float i0 = bil_tap<0>(I, t);
+                    const Tap u = tap_at(J, x + (gx + vx), y + (gy + vy));
+                    const float d = i0 - bil_tap<0>(J, u);
+                    bx += d * ix;
+                    by += d * iy;
+                }
+            }
+            const float ex = (Gyy * bx - Gxy * by) / det;
+            const float ey = (Gxx * by - Gxy * bx) / det;
+            vx += ex;
+            vy += ey;
+            if (ex * ex + ey * ey < P.eps) break;
+        }
+        if (l > 0) {
+            gx = 2.0f * (gx + vx);
+            gy = 2.0f * (gy + vy);
+        } else {
+            *fx = gx + vx;
+            *fy = gy + vy;
+        }
+    }
+    return true;
+}
+
+// Level 0 of every frame: intensity as float.
+__global__ __launch_bounds__(256) void k_pyr_base(const uint8_t* __restrict__ first,
+                                                  const uint8_t* __restrict__ rest,
+                                                  int64_t fstride, int n, int64_t npix,
+                                                  uint64_t total, float* __restrict__ pyr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t all = (int64_t)n * npix;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < all; i += stride) {
+        const int64_t f = i / npix, p = i - f * npix;
+        const uint8_t* src = f == 0 ? first : rest + (f - 1) * fstride;
+        pyr[(uint64_t)f * total + (uint64_t)p] = (float)src[p];
+    }
+}
+
+// Level l of every frame from level l - 1.
+__global__ __launch_bounds__(256) void k_pyr_down(PyrLayout L, int l, int n,
+                                                  float* __restrict__ pyr) {
+    const int w = L.w[l], h = L.h[l];
+    const int64_t per = (int64_t)w * h;
+    const int64_t all = (int64_t)n * per;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < all; i += stride) {
+        const int64_t f = i / per, q = i - f * per;
+        const int y = (int)(q / w), x = (int)(q - (int64_t)y * w);
+        Level a;
+        a.v = pyr + (uint64_t)f * L.total + L.off[l - 1];
+        a.w = L.w[l - 1];
+        a.h = L.h[l - 1];
+        const int cx = 2 * x, cy = 2 * y;
+        const float c = texel_at(a, cx, cy);
+        const float edges = texel_at(a, cx - 1, cy) + texel_at(a, cx + 1, cy) +
+                            texel_at(a, cx, cy - 1) + texel_at(a, cx, cy + 1);
+        const float corners = texel_at(a, cx - 1, cy - 1) + texel_at(a, cx + 1, cy - 1) +
+                              texel_at(a, cx - 1, cy + 1) + texel_at(a, cx + 1, cy + 1);
+        pyr[(uint64_t)f * L.total + L.off[l] + (uint64_t)q] =
+            ((4.0f * c + 2.0f * edges) + corners) * 0.0625f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lk_points(const float* __restrict__ A,
+                                                   const float* __restrict__ B, PyrLayout L,
+                                                   LkParams P, const uint32_t* __restrict__ pts,
+                                                   uint64_t n, float* __restrict__ flow,
+                                                   uint8_t* __restrict__ valid) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t p = pts[j];
+    const int W = L.w[0];
+    const int py = (int)(p / (uint32_t)W), px = (int)(p - (uint32_t)py * (uint32_t)W);
+    float fx = 0.0f, fy = 0.0f;
+    // an index outside the image is invalid (flow 0) rather than read out of bounds
+    const bool ok = py < L.h[0] && lk_point(A, B, L, P, px, py, &fx, &fy);
+    flow[2 * j] = fx;
+    flow[2 * j + 1] = fy;
+    if (valid) valid[j] = ok ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_lk_window(LkWindowArgs a) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    int p;
+    if (a.act_px) {
+        const int stripe = slot / a.act_cap;
+        if (stripe >= kActStripes ||
+            slot - stripe * a.act_cap >= (int)a.n_active[stripe * kCounterStride])
+            return;
+        p = (int)a.act_px[slot];
+    } else {
+        if (slot >= a.npix) return;
+        p = slot;
+    }
+    const int py = p / a.W, px = p - py * a.W;
+    for (int i = 0; i < a.K; ++i) {
+        if (a.mask && !((a.mask[(int64_t)(i >> 5) * a.npix + p] >> (i & 31)) & 1u)) continue;
+        float fx = 0.0f, fy = 0.0f;
+        lk_point(a.pyr + (uint64_t)i * a.lay.total, a.pyr + (uint64_t)(i + 1) * a.lay.total,
+                 a.lay, a.P, px, py, &fx, &fy);
+        float* out = a.flow + (int64_t)i * 2 * a.npix + 2 * (int64_t)p;
+        out[0] = fx;
+        out[1] = fy;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pyramids(const uint8_t* first, const uint8_t* rest, int64_t fstride, int n,
+                           const PyrLayout& lay, float* pyr, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t npix = (int64_t)lay.w[0] * lay.h[0];
+    int64_t blocks = std::min<int64_t>(((int64_t)n * npix + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_pyr_base, dim3((unsigned)blocks), dim3(256), 0, stream, first, rest,
+                       fstride, n, npix, lay.total, pyr);
+    for (int l = 1; l <= lay.levels; ++l) {
+        const int64_t per = (int64_t)lay.w[l] * lay.h[l];
+        blocks = std::min<int64_t>(((int64_t)n * per + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_pyr_down, dim3((unsigned)blocks), dim3(256), 0, stream, lay, l, n,
+                           pyr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lk_points(const float* a, const float* b, const PyrLayout& lay,
+                            const LkParams& P, const uint32_t* points, uint64_t n, float* flow,
+                            uint8_t* valid, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_lk_points, dim3((unsigned)blocks), dim3(256), 0, stream, a, b, lay, P,
+                       points, n, flow, valid);
+    return hipGetLastError();
+}
+
+hipError_t launch_lk_window(const LkWindowArgs& a, int max_slots, hipStream_t stream) {
+    const int blocks = (max_slots + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lk_window, dim3(blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace evsim

@@ -98,6 +98,13 @@ struct sim_stream {
     uint64_t* d_fifo = nullptr;
     uint64_t fifo_cap = 0, fifo_head = 0, fifo_tail = 0;
 
+    // flow estimation (SIM_FLOW_LK): pyramids of a window's frames, estimated flow fields
+    LkParams lk;
+    float* d_pyr = nullptr;
+    uint64_t pyr_cap = 0;
+    float* d_lkflow = nullptr;
+    uint64_t lkflow_cap = 0;
+
     // accumulated-frame scratch (sim_accumulate with host counts, sim_event_rate)
     uint32_t* d_acc = nullptr;
     uint64_t acc_cap = 0;
@@ -153,6 +160,8 @@ void free_stream(sim_stream* s) {
     dfree(s->d_prev2[1]);
     dfree(s->d_acc);
     dfree(s->d_moments);
+    dfree(s->d_pyr);
+    dfree(s->d_lkflow);
     dfree(s->d_arena);
     dfree(s->d_reserve);
     dfree(s->d_stats);
@@ -254,6 +263,23 @@ void build_lut(sim_stream* s) {
 
 int check_mem_kind(int32_t k) { return (k == SIM_MEM_HOST || k == SIM_MEM_DEVICE) ? SIM_OK : SIM_E_INVAL; }
 
+bool lk_ok(const sim_lk_params& p) {
+    return p.levels >= 0 && p.levels <= kLkMaxLevels && p.radius >= 1 && p.radius <= 15 &&
+           p.iterations >= 1 && p.iterations <= 100 && p.eps >= 0.0f && p.min_trace >= 0.0f &&
+           p.min_ratio >= 0.0f;
+}
+
+LkParams lk_from(const sim_lk_params& p) {
+    LkParams r;
+    r.levels = p.levels;
+    r.radius = p.radius;
+    r.iters = p.iterations;
+    r.eps = p.eps;
+    r.min_trace = p.min_trace;
+    r.min_ratio = p.min_ratio;
+    return r;
+}
+
 // A window of K intervals whose frames/flows are already on the device runs in three phases, so
 // that a batch of streams can interleave them: every stream's kernels are queued on its own HIP
 // stream before any host wait.
@@ -322,6 +348,38 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
             const uint8_t* src = K >= 2 ? frames + (size_t)(K - 2) * s->npix : s->d_prev[s->cur];
             HIP_TRY(s, launch_copy_u8(src, s->d_prev2[1 - s->cur], s->npix, s->stream));
         }
+    }
+    const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
+    if (estimate) {
+        // flow of every selected pixel-interval, from the pyramids of the previous frame and the
+        // window's frames, into the layout of supplied flows
+        const PyrLayout pl = pyr_layout(W, H, s->lk.levels);
+        uint64_t cap = s->pyr_cap;
+        int rc = grow(s, &s->d_pyr, &cap, (uint64_t)(K + 1) * pl.total, 0);
+        s->pyr_cap = cap;
+        if (!rc) {
+            cap = s->lkflow_cap;
+            rc = grow(s, &s->d_lkflow, &cap, (uint64_t)K * 2 * (uint64_t)s->npix, 0);
+            s->lkflow_cap = cap;
+        }
+        if (rc) return rc;
+        HIP_TRY(s, launch_pyramids(s->d_prev[s->cur], frames, s->npix, K + 1, pl, s->d_pyr,
+                                   s->stream));
+        LkWindowArgs la;
+        la.pyr = s->d_pyr;
+        la.lay = pl;
+        la.P = s->lk;
+        la.mask = sparse ? s->d_mask : nullptr;
+        la.act_px = sparse ? s->d_act : nullptr;
+        la.n_active = sparse ? s->d_nact : nullptr;
+        la.act_cap = s->act_cap;
+        la.npix = (int)s->npix;
+        la.W = W;
+        la.K = K;
+        la.flow = s->d_lkflow;
+        HIP_TRY(s, launch_lk_window(la, sparse ? kActStripes * s->act_cap : (int)s->npix,
+                                    s->stream));
+        flows = s->d_lkflow;
     }
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
 
@@ -474,7 +532,8 @@ int push_validate(sim_stream* s, int32_t n_frames, const uint8_t* frames, const 
     if (n_frames < 1 || !frames || !t_us || check_mem_kind(mem_kind)) return SIM_E_INVAL;
     const int first = s->started ? 0 : 1;     // frames consumed by initialisation
     const int n_int = n_frames - first;
-    if (n_int > 0 && s->S > 1 && !flows) return SIM_E_INVAL;
+    if (n_int > 0 && s->S > 1 && !flows && s->cfg.flow_source == SIM_FLOW_SUPPLIED)
+        return SIM_E_INVAL;
     int64_t prev = s->started ? s->t_prev : t_us[0];
     const int64_t epoch = s->started ? s->epoch : t_us[0];
     for (int j = first; j < n_frames; ++j) {
@@ -510,7 +569,7 @@ int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const flo
         HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, frames, (size_t)n_frames * fbytes,
                                   hipMemcpyHostToDevice, s->stream));
         out->frames = s->d_stage_frames;
-        if (out->n_int > 0 && s->S > 1) {
+        if (out->n_int > 0 && s->S > 1 && s->cfg.flow_source == SIM_FLOW_SUPPLIED) {
             cap = s->stage_flows_cap;
             rc = grow(s, &s->d_stage_flows, &cap, (uint64_t)out->n_int * flfloats, 0);
             s->stage_flows_cap = (size_t)cap;
@@ -538,7 +597,8 @@ const uint8_t* window_frames(const sim_stream* s, const Staged& st, int j) {
 }
 
 const float* window_flows(const sim_stream* s, const Staged& st, int j) {
-    return s->S > 1 ? st.flows + (size_t)j * 2 * (size_t)s->npix : nullptr;
+    if (s->S <= 1 || s->cfg.flow_source != SIM_FLOW_SUPPLIED) return nullptr;
+    return st.flows + (size_t)j * 2 * (size_t)s->npix;
 }
 
 int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
@@ -591,7 +651,11 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     if (cfg->method < SIM_BASIC || cfg->method > SIM_DIFFERENCE) return SIM_E_INVAL;
     if (cfg->thresh_mode != SIM_THRESH_REFERENCE && cfg->thresh_mode != SIM_THRESH_MEMORYLESS)
         return SIM_E_INVAL;
-    if (cfg->reserved != 0) return SIM_E_INVAL;
+    if (cfg->flow_source != SIM_FLOW_SUPPLIED && cfg->flow_source != SIM_FLOW_LK)
+        return SIM_E_INVAL;
+    if (cfg->flow_source == SIM_FLOW_LK && cfg->method != SIM_DENSE &&
+        cfg->method != SIM_SPARSE)
+        return SIM_E_INVAL;
     if (cfg->transform != SIM_LOG && cfg->transform != SIM_LINEAR) return SIM_E_INVAL;
     if (!(cfg->c_pos > 0.0f) || !(cfg->c_neg > 0.0f) || !isfinite(cfg->c_pos) ||
         !isfinite(cfg->c_neg))
@@ -618,6 +682,11 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     s->m = cfg->mask_threshold < 0.0f ? std::min(cfg->c_pos, cfg->c_neg) : cfg->mask_threshold;
     s->npix = (int64_t)cfg->width * cfg->height;
     s->ntiles = (int)((s->npix + kSimThreads - 1) / kSimThreads);
+    {
+        sim_lk_params d;
+        sim_lk_params_init(&d);
+        s->lk = lk_from(d);
+    }
     memset(&s->stats, 0, sizeof(s->stats));
 
     bool ok = true;
@@ -927,6 +996,105 @@ int sim_event_rate(sim_stream* s, int64_t t_begin, int64_t t_end, double* mean, 
         sums[1] = s2;
     }
     return SIM_OK;
+}
+
+void sim_lk_params_init(sim_lk_params* p) {
+    if (!p) return;
+    p->levels = 3;
+    p->radius = 7;
+    p->iterations = 10;
+    p->eps = 1e-4f;
+    p->min_trace = 1.0f;
+    p->min_ratio = 1e-3f;
+}
+
+int sim_set_lk_params(sim_stream* s, const sim_lk_params* p) {
+    if (!s || !p || !lk_ok(*p)) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    s->lk = lk_from(*p);
+    return SIM_OK;
+}
+
+int sim_lk_flow(const uint8_t* f0, const uint8_t* f1, int32_t width, int32_t height,
+                const uint32_t* points, uint64_t n_points, float* flow, uint8_t* valid,
+                const sim_lk_params* params, int32_t mem_kind, void* hip_stream) {
+    sim_lk_params P;
+    if (params)
+        P = *params;
+    else
+        sim_lk_params_init(&P);
+    if (!lk_ok(P) || width < 1 || height < 1 || width > 4096 || height > 4096 ||
+        check_mem_kind(mem_kind))
+        return SIM_E_INVAL;
+    if (n_points == 0) return SIM_OK;
+    if (!f0 || !f1 || !points || !flow) return SIM_E_INVAL;
+    const bool host = mem_kind == SIM_MEM_HOST;
+    const size_t npix = (size_t)width * (size_t)height;
+    const PyrLayout pl = pyr_layout(width, height, P.levels);
+    hipStream_t st = (hipStream_t)hip_stream;
+    bool own = false;
+    if (!st) {
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIM_E_HIP;
+        }
+        own = true;
+    }
+    float* d_pyr = nullptr;
+    uint8_t* d_frames = nullptr;
+    uint32_t* d_pts = nullptr;
+    float* d_flow = nullptr;
+    uint8_t* d_valid = nullptr;
+    int rc = SIM_OK;
+    bool ok = dev_alloc(&d_pyr, 2 * pl.total) == hipSuccess;
+    if (ok && host) {
+        ok = dev_alloc(&d_frames, 2 * npix) == hipSuccess &&
+             dev_alloc(&d_pts, n_points) == hipSuccess &&
+             dev_alloc(&d_flow, 2 * n_points) == hipSuccess &&
+             (!valid || dev_alloc(&d_valid, n_points) == hipSuccess);
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        rc = SIM_E_NOMEM;
+    }
+    const uint8_t* a = f0;
+    const uint8_t* b = f1;
+    const uint32_t* pts = points;
+    float* fl = flow;
+    uint8_t* va = valid;
+    if (!rc && host) {
+        a = d_frames;
+        b = d_frames + npix;
+        pts = d_pts;
+        fl = d_flow;
+        va = d_valid;
+        if (hipMemcpyAsync(d_frames, f0, npix, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(d_frames + npix, f1, npix, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(d_pts, points, n_points * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           st) != hipSuccess)
+            rc = SIM_E_HIP;
+    }
+    if (!rc && (launch_pyramids(a, nullptr, 0, 1, pl, d_pyr, st) != hipSuccess ||
+                launch_pyramids(b, nullptr, 0, 1, pl, d_pyr + pl.total, st) != hipSuccess ||
+                launch_lk_points(d_pyr, d_pyr + pl.total, pl, lk_from(P), pts, n_points, fl, va,
+                                 st) != hipSuccess))
+        rc = SIM_E_HIP;
+    if (!rc && host) {
+        if (hipMemcpyAsync(flow, d_flow, 2 * n_points * sizeof(float), hipMemcpyDeviceToHost,
+                           st) != hipSuccess ||
+            (valid && hipMemcpyAsync(valid, d_valid, n_points, hipMemcpyDeviceToHost, st) !=
+                          hipSuccess))
+            rc = SIM_E_HIP;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = SIM_E_HIP;
+    if (rc == SIM_E_HIP) (void)hipGetLastError();
+    dfree(d_pyr);
+    dfree(d_frames);
+    dfree(d_pts);
+    dfree(d_flow);
+    dfree(d_valid);
+    if (own) (void)hipStreamDestroy(st);
+    return rc;
 }
 
 int sim_sync(sim_stream* s) {

@@ -28,7 +28,7 @@ struct Camera {
     bool own_stream = false;
     uint64_t footprint = 0;
     int64_t npix = 0;
-    bool interp = false;          // needs flows
+    bool interp = false;          // needs supplied flows
     bool started = false;         // has received its first frame (in a push)
     int q = 0;                    // frames queued in staging
     uint8_t* d_frames = nullptr;  // [qcap][H][W]
@@ -72,7 +72,7 @@ int srv_footprint(const sim_config* cfg, int32_t queue_depth, uint64_t* bytes) {
         return SIM_E_INVAL;
     const uint64_t npix = (uint64_t)cfg->width * (uint64_t)cfg->height;
     const bool sparse = cfg->method == SIM_SPARSE;
-    const bool interp = cfg->method != SIM_BASIC;
+    const bool interp = cfg->method != SIM_BASIC && cfg->flow_source == SIM_FLOW_SUPPLIED;
     // reference levels 4, previous frames 2, chain resume points 4, event arena at its initial
     // capacity of 2 keys per pixel 16, sort buffers 32, FIFO 16; sparse: selection masks 16 and
     // active list 4; difference method: the frames before the previous ones 2; staging: one
@@ -80,6 +80,9 @@ int srv_footprint(const sim_config* cfg, int32_t queue_depth, uint64_t* bytes) {
     uint64_t per_px = 4 + 2 + 4 + 16 + 32 + 16 + (sparse ? 20 : 0) +
                       (cfg->method == SIM_DIFFERENCE ? 2 : 0);
     per_px += (uint64_t)queue_depth * (1 + (interp ? 8 : 0));
+    // estimated flow: a pyramid (at most 4/3 of a float frame) per frame of a step and one
+    // flow field per interval
+    if (cfg->flow_source == SIM_FLOW_LK) per_px += (uint64_t)(queue_depth + 1) * 6 + 8 * queue_depth;
     *bytes = npix * per_px + (1u << 20);
     return SIM_OK;
 }
@@ -132,7 +135,7 @@ int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
     Camera c;
     c.cfg = *cfg;
     c.npix = (int64_t)cfg->width * cfg->height;
-    c.interp = cfg->method != SIM_BASIC;
+    c.interp = cfg->method != SIM_BASIC && cfg->flow_source == SIM_FLOW_SUPPLIED;
     c.footprint = fp;
     if (cfg->hip_stream) {
         c.stream = (hipStream_t)cfg->hip_stream;

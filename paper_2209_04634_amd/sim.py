@@ -18,10 +18,12 @@ LIB_PATH = os.path.join(HERE, "libevsim.so")
 BASIC, DENSE, SPARSE, DIFFERENCE = 0, 1, 2, 3
 LOG, LINEAR = 0, 1
 REFERENCE, MEMORYLESS = 0, 1
+FLOW_SUPPLIED, FLOW_LK = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 METHODS = {"basic": BASIC, "dense": DENSE, "sparse": SPARSE, "difference": DIFFERENCE}
 TRANSFORMS = {"log": LOG, "linear": LINEAR}
 THRESH_MODES = {"reference": REFERENCE, "memoryless": MEMORYLESS}
+FLOW_SOURCES = {"supplied": FLOW_SUPPLIED, "lk": FLOW_LK}
 
 OK, E_INVAL, E_ORDER, E_NOMEM, E_RANGE, E_HIP, E_POISONED, E_BUSY, E_EMPTY = 0, -1, -2, -3, -4, -5, -6, -7, -8
 
@@ -33,7 +35,13 @@ class SimConfig(ctypes.Structure):
                 ("log_eps", ctypes.c_float), ("n_interp", ctypes.c_int32),
                 ("mask_threshold", ctypes.c_float), ("event_capacity", ctypes.c_uint64),
                 ("hip_stream", ctypes.c_void_p), ("thresh_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flow_source", ctypes.c_int32)]
+
+
+class SimLkParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("min_trace", ctypes.c_float), ("min_ratio", ctypes.c_float)]
 
 
 class SimEvent(ctypes.Structure):
@@ -120,6 +128,10 @@ def load() -> ctypes.CDLL:
         "srv_get_stats": (ctypes.c_int, [P, ctypes.POINTER(ServerStats)]),
         "srv_clear_stats": (ctypes.c_int, [P]),
         "srv_now_ns": (I64, []),
+        "sim_lk_params_init": (None, [ctypes.POINTER(SimLkParams)]),
+        "sim_set_lk_params": (ctypes.c_int, [P, ctypes.POINTER(SimLkParams)]),
+        "sim_lk_flow": (ctypes.c_int, [P, P, I32, I32, P, U64, P, P,
+                                       ctypes.POINTER(SimLkParams), I32, P]),
         "sim_accumulate": (ctypes.c_int, [P, I64, I64, P, I32]),
         "sim_event_rate": (ctypes.c_int, [P, I64, I64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), PU64]),
@@ -175,6 +187,52 @@ def _buffer(x, dtype, shape=None):
     return a.ctypes.data_as(ctypes.c_void_p), MEM_HOST, a
 
 
+def lk_params(levels: int = 3, radius: int = 7, iterations: int = 10, eps: float = 1e-4,
+              min_trace: float = 1.0, min_ratio: float = 1e-3) -> SimLkParams:
+    p = SimLkParams()
+    load().sim_lk_params_init(ctypes.byref(p))
+    p.levels, p.radius, p.iterations = int(levels), int(radius), int(iterations)
+    p.eps, p.min_trace, p.min_ratio = float(eps), float(min_trace), float(min_ratio)
+    return p
+
+
+def lk_flow(f0, f1, points=None, hip_stream=None, **params):
+    """Pyramidal Lucas-Kanade flow from f0 to f1 (uint8 [H, W], numpy or torch device tensors)
+    at pixel indices `points` (y * W + x; default every pixel).  Returns (flow [n, 2] float32,
+    valid [n] bool) as numpy arrays for host inputs, torch tensors for device inputs."""
+    lib = load()
+    H, W = int(f0.shape[0]), int(f0.shape[1])
+    a, ka, keep_a = _buffer(f0, np.uint8, (H, W))
+    b, kb, keep_b = _buffer(f1, np.uint8, (H, W))
+    if ka != kb:
+        raise ValueError("f0 and f1 must both be host or both be device memory")
+    if ka == MEM_DEVICE:
+        import torch
+        if points is None:
+            points = torch.arange(H * W, dtype=torch.int32, device=f0.device)
+        n = int(points.numel())
+        flow = torch.zeros((n, 2), dtype=torch.float32, device=f0.device)
+        valid = torch.zeros(n, dtype=torch.uint8, device=f0.device)
+        pp, _, keep_p = _buffer(points, np.uint32, (n,))
+        fp = ctypes.c_void_p(flow.data_ptr())
+        vp = ctypes.c_void_p(valid.data_ptr())
+    else:
+        if points is None:
+            points = np.arange(H * W, dtype=np.uint32)
+        pts = np.ascontiguousarray(points, dtype=np.uint32)
+        n = pts.size
+        flow = np.zeros((n, 2), dtype=np.float32)
+        valid = np.zeros(n, dtype=np.uint8)
+        pp, keep_p = pts.ctypes.data_as(ctypes.c_void_p), pts
+        fp, vp = flow.ctypes.data_as(ctypes.c_void_p), valid.ctypes.data_as(ctypes.c_void_p)
+    if hip_stream is not None and hasattr(hip_stream, "cuda_stream"):
+        hip_stream = hip_stream.cuda_stream
+    st = ctypes.c_void_p(int(hip_stream)) if hip_stream else None
+    _check(lib.sim_lk_flow(a, b, W, H, pp, n, fp, vp, ctypes.byref(lk_params(**params)), ka, st),
+           "sim_lk_flow")
+    return flow, (valid != 0)
+
+
 def _check_flows(flows, needed: int, H: int, W: int) -> None:
     """The library reads `needed` flow fields of [H, W, 2] from `flows`: refuse anything smaller
     before it reaches the device."""
@@ -193,7 +251,8 @@ def make_config(width: int, height: int, method: Union[str, int] = "basic",
                 transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
                 log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
                 event_capacity: int = 0, hip_stream=None,
-                thresh_mode: Union[str, int] = "reference") -> SimConfig:
+                thresh_mode: Union[str, int] = "reference",
+                flow_source: Union[str, int] = "supplied") -> SimConfig:
     lib = load()
     cfg = SimConfig()
     lib.sim_config_init(ctypes.byref(cfg))
@@ -205,6 +264,8 @@ def make_config(width: int, height: int, method: Union[str, int] = "basic",
     cfg.event_capacity = int(event_capacity)
     cfg.thresh_mode = (THRESH_MODES[thresh_mode] if isinstance(thresh_mode, str)
                        else int(thresh_mode))
+    cfg.flow_source = (FLOW_SOURCES[flow_source] if isinstance(flow_source, str)
+                       else int(flow_source))
     if hip_stream == "torch":
         import torch
         hip_stream = torch.cuda.current_stream().cuda_stream
@@ -221,10 +282,11 @@ class Stream:
                  transform: Union[str, int] = "log", c_pos: float = 0.2, c_neg: float = 0.2,
                  log_eps: float = 1e-3, n_interp: int = 10, mask_threshold: float = -1.0,
                  event_capacity: int = 0, hip_stream=None,
-                 thresh_mode: Union[str, int] = "reference"):
+                 thresh_mode: Union[str, int] = "reference",
+                 flow_source: Union[str, int] = "supplied", lk: Optional[dict] = None):
         lib = load()
         cfg = make_config(width, height, method, transform, c_pos, c_neg, log_eps, n_interp,
-                          mask_threshold, event_capacity, hip_stream, thresh_mode)
+                          mask_threshold, event_capacity, hip_stream, thresh_mode, flow_source)
         h = ctypes.c_void_p()
         _check(lib.sim_create(ctypes.byref(cfg), ctypes.byref(h)), "sim_create")
         self._h = h
@@ -232,11 +294,15 @@ class Stream:
         self.width, self.height = int(width), int(height)
         self.method = cfg.method
         self.n_interp = cfg.n_interp
+        self.flow_source = cfg.flow_source
+        if lk:
+            _check(lib.sim_set_lk_params(self._h, ctypes.byref(lk_params(**lk))),
+                   "sim_set_lk_params", self._h)
 
     def _flows_needed(self, n_frames: int) -> int:
         """Flow fields a push of n_frames reads: one per simulated interval for the
         interpolating methods with S > 1 (the first frame of a stream only initialises it)."""
-        if self.method == BASIC or self.n_interp == 0:
+        if self.method == BASIC or self.n_interp == 0 or self.flow_source == FLOW_LK:
             return 0
         e = ctypes.c_int64()
         started = self._lib.sim_epoch(self._h, ctypes.byref(e)) == OK

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2209_04634_amd", "csrc")
 SOURCES = [os.path.join(CSRC, "evsim_kernels.hip"), os.path.join(CSRC, "evsim_runtime.hip"),
-           os.path.join(CSRC, "evsim_server.hip")]
+           os.path.join(CSRC, "evsim_server.hip"), os.path.join(CSRC, "evsim_lk.hip")]
 
 
 def lib_path(asan: bool = False) -> str:

@@ -105,3 +105,70 @@ def test_accumulated_frame_and_event_rate():
         assert sums == rsums and m == rm and sd == rsd
     assert s.pending() == len(ok)
     s.close()
+
+
+# ------------------------------------------------------------------------------------------
+# Pyramidal Lucas-Kanade flow estimation (NEXT-4)
+# ------------------------------------------------------------------------------------------
+
+def _lk_frames(H, W, seed, motion):
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    c = [(rng.uniform(0, W), rng.uniform(0, H), rng.uniform(3, 10), rng.uniform(60, 180))
+         for _ in range(40)]
+
+    def img(dx, dy):
+        v = np.full((H, W), 25.0)
+        for cx, cy, s, a in c:
+            v += a * np.exp(-((x - cx - dx) ** 2 + (y - cy - dy) ** 2) / (2 * s * s))
+        return np.clip(np.rint(v), 0, 255).astype(np.uint8)
+    return img(0, 0), img(*motion)
+
+
+@pytest.mark.parametrize("levels,radius", [(0, 3), (3, 7), (4, 10)])
+def test_lk_flow_equals_oracle(levels, radius):
+    """Host and device inputs, every 9th pixel of a 320x240 pair plus corners and indices
+    outside the image, bit for bit."""
+    import torch
+    from oracle.oracle import lk_flow as oracle_lk_flow
+    H, W = 240, 320
+    f0, f1 = _lk_frames(H, W, levels + radius, (4.5, -2.25))
+    pts = np.concatenate([np.arange(0, H * W, 9, dtype=np.uint32),
+                          np.array([W - 1, (H - 1) * W, H * W - 1, H * W, 1 << 30], np.uint32)])
+    ref, rvalid = oracle_lk_flow(f0, f1, pts, levels=levels, radius=radius)
+    flow, valid = sim.lk_flow(f0, f1, pts, levels=levels, radius=radius)
+    np.testing.assert_array_equal(valid, rvalid)
+    np.testing.assert_array_equal(flow.view(np.uint32), ref.view(np.uint32))
+    assert rvalid.sum() > 1000
+    torch.cuda.synchronize()
+    d0, d1 = torch.from_numpy(f0).cuda(), torch.from_numpy(f1).cuda()
+    dp = torch.from_numpy(pts.view(np.int32)).cuda()
+    torch.cuda.synchronize()
+    dflow, dvalid = sim.lk_flow(d0, d1, dp, levels=levels, radius=radius)
+    np.testing.assert_array_equal(dflow.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    np.testing.assert_array_equal(dvalid.cpu().numpy(), rvalid)
+
+
+@pytest.mark.parametrize("method,shape,frames", [(sim.SPARSE, (240, 320), 6),
+                                                 (sim.DENSE, (64, 96), 5)])
+def test_estimated_flow_simulation(method, shape, frames):
+    """Sparse and dense simulation with flow estimated on the device: one window, single
+    pushes; events and reference levels bit for bit."""
+    from oracle.oracle import FLOW_LK
+    H, W = shape
+    spec = synth.BlobVideoSpec(W, H, frames, 30.0, 24, seed=5, motion="random", speed_max=6.0)
+    v = synth.blob_video(spec)
+    ok, oref = oracle_keys(v.frames, None, v.t_us, method=method, c_pos=0.15, c_neg=0.15,
+                           n_interp=10, flow_source=FLOW_LK)
+    assert len(ok) > 100
+    for mode in ("window", "single"):
+        s = sim.Stream(W, H, method=method, c_pos=0.15, c_neg=0.15, n_interp=10,
+                       flow_source="lk")
+        if mode == "window":
+            s.push_frames(v.frames, None, v.t_us)
+        else:
+            for k in range(frames):
+                s.push(v.frames[k], None, int(v.t_us[k]))
+        np.testing.assert_array_equal(s.drain_keys(), ok, err_msg=mode)
+        np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32))
+        s.close()
