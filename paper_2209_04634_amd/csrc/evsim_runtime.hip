@@ -79,6 +79,7 @@ struct sim_stream {
     uint32_t* d_totals = nullptr;
     unsigned long long* d_counters = nullptr;
     unsigned long long* h_counters = nullptr;   // pinned
+    unsigned long long* h_stats = nullptr;      // pinned copy of d_stats (sim_get_stats)
     float* d_delta = nullptr;
     int64_t* d_tbase = nullptr;
     int* d_resume = nullptr;                     // per chain slot
@@ -180,6 +181,7 @@ void free_stream(sim_stream* s) {
     dfree(s->d_stage_flows);
     dfree(s->d_fifo);
     if (s->h_counters) (void)hipHostFree(s->h_counters);
+    if (s->h_stats) (void)hipHostFree(s->h_stats);
     if (s->h_delta) (void)hipHostFree(s->h_delta);
     if (s->h_tbase) (void)hipHostFree(s->h_tbase);
     for (hipEvent_t& e : s->ev)
@@ -727,6 +729,9 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     ok = ok && dev_alloc(&s->d_tbase, kMaxWindow) == hipSuccess;
     ok = ok && dev_alloc(&s->d_resume, slots) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->h_counters, 4 * sizeof(unsigned long long), 0) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&s->h_stats,
+                             (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
+                             0) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->h_delta, kMaxWindow * sizeof(float), 0) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&s->h_tbase, kMaxWindow * sizeof(int64_t), 0) == hipSuccess;
     if (!ok) {
@@ -1113,16 +1118,16 @@ int sim_get_stats(sim_stream* s, sim_stats* out) {
     if (!s || !out) return SIM_E_INVAL;
     *out = s->stats;
     if (!s->poisoned && s->cfg.method == SIM_SPARSE) {
-        unsigned long long sel[2 * kStatStripes];
-        HIP_TRY(s, hipMemcpy2DAsync(sel, 2 * sizeof(unsigned long long), s->d_stats,
-                                    kCounterStride * sizeof(unsigned long long),
-                                    2 * sizeof(unsigned long long), kStatStripes,
-                                    hipMemcpyDeviceToHost, s->stream));
+        // the whole striped block (16 KiB) in one plain copy to pinned memory
+        HIP_TRY(s, hipMemcpyAsync(s->h_stats, s->d_stats,
+                                  (size_t)kStatStripes * kCounterStride *
+                                      sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(s, hipStreamSynchronize(s->stream));
         uint64_t tot = 0, act = 0;
         for (int i = 0; i < kStatStripes; ++i) {
-            tot += sel[2 * i];
-            act += sel[2 * i + 1];
+            tot += s->h_stats[(size_t)i * kCounterStride];
+            act += s->h_stats[(size_t)i * kCounterStride + 1];
         }
         out->selected = tot;
         out->active = act;

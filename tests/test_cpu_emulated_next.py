@@ -252,3 +252,26 @@ def test_binding_refuses_short_flow_arrays(emu_sim):
     s = emu_sim.Stream(9, 6, method="basic")
     s.push_frames(frames, None, [0, 1, 2, 3])                    # basic reads no flow
     s.close()
+
+
+def test_emulated_selection_statistics(emu_sim):
+    """sim_get_stats of a sparse stream: selected pixel-intervals equal the oracle's per-interval
+    selection counts summed; active pixels are the pixels selected at least once in the window."""
+    from oracle.oracle import OracleSim, lut
+    spec = synth.BlobVideoSpec(64, 48, 9, 30.0, 6, seed=11, motion="random", speed_max=5.0)
+    v = synth.blob_video(spec)
+    o = OracleSim(64, 48, method=sim.SPARSE, c_pos=0.2, c_neg=0.2)
+    o.push(v.frames[0], None, int(v.t_us[0]))
+    sel = 0
+    for k in range(1, 9):
+        o.push(v.frames[k], v.flows[k - 1], int(v.t_us[k]))
+        sel += o.selected
+    L = lut()[v.frames].astype(np.float32)
+    active = int((np.abs(L[1:] - L[:-1]) >= np.float32(0.2)).any(axis=0).sum())
+    s = emu_sim.Stream(64, 48, method="sparse", c_pos=0.2, c_neg=0.2)
+    s.push_frames(v.frames, v.flows, v.t_us)
+    st = s.stats()
+    assert st["selected"] == sel > 0 and st["active"] == active > 0
+    s.clear_stats()
+    assert s.stats()["selected"] == 0
+    s.close()

@@ -172,3 +172,23 @@ def test_estimated_flow_simulation(method, shape, frames):
         np.testing.assert_array_equal(s.drain_keys(), ok, err_msg=mode)
         np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32))
         s.close()
+
+
+def test_selection_statistics():
+    """The device statistics of the sparse 1280x720 sequence: selected pixel-intervals equal the
+    oracle's per-interval counts summed, active pixels those selected at least once."""
+    from oracle.oracle import OracleSim, lut
+    v = synth.blob_video(synth.sparse_1280x720())
+    o = OracleSim(1280, 720, method=sim.SPARSE, c_pos=0.2, c_neg=0.2)
+    o.push(v.frames[0], None, int(v.t_us[0]))
+    sel = 0
+    for k in range(1, len(v.t_us)):
+        o.push(v.frames[k], v.flows[k - 1], int(v.t_us[k]))
+        sel += o.selected
+    L = lut()[v.frames].astype(np.float32)
+    active = int((np.abs(L[1:] - L[:-1]) >= np.float32(0.2)).any(axis=0).sum())
+    s = sim.Stream(1280, 720, method="sparse", c_pos=0.2, c_neg=0.2)
+    s.push_frames(v.frames, v.flows, v.t_us)
+    st = s.stats()
+    assert st["selected"] == sel > 0 and st["active"] == active > 0
+    s.close()
