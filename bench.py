@@ -11,7 +11,9 @@ Default workload: 1280x720 sparse-flow interpolation, 120 frames at 60 fps (119 
 
 Prints one JSON line (rank 0, N = 1).  Extra fields report the events/s rate, the per-frame
 latency of plain one-frame pushes (p50 / p99) next to the batched window push, and the dominant
-kernel against the HBM roofline.
+kernel against the HBM roofline.  Optional legs (off by default): --workload for the memoryless,
+difference-frame and estimated-flow variants; --batched STREAMS (mixed-resolution streams, one
+batched push per frame step against one push per stream); --serve SECONDS (the serving loop).
 """
 from __future__ import annotations
 
@@ -30,6 +32,12 @@ WORKLOADS = {
     "sparse_1280x720": dict(spec="sparse_1280x720", method="sparse", c=0.2, n_interp=10),
     "dense_346x260": dict(spec="dense_346x260", method="dense", c=0.15, n_interp=10),
     "basic_240x180": dict(spec="basic_240x180", method="basic", c=0.2, n_interp=0),
+    # the paper-literal thresholding, the difference-frame method and estimated flow
+    "memoryless_dense_346x260": dict(spec="dense_346x260", method="dense", c=0.03, n_interp=10,
+                                     thresh="memoryless"),
+    "difference_346x260": dict(spec="dense_346x260", method="difference", c=0.3, n_interp=10),
+    "lk_sparse_1280x720": dict(spec="sparse_1280x720", method="sparse", c=0.2, n_interp=10,
+                               flow="lk"),
 }
 
 
@@ -45,23 +53,149 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-frame-push latency leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--batched", type=int, default=0, metavar="STREAMS",
+                    help="also time STREAMS mixed-resolution streams (240x180, 346x260, "
+                         "640x480, 1920x1080; all three methods) pushed as one batch per frame "
+                         "step against one push per stream and step")
+    ap.add_argument("--serve", type=float, default=0.0, metavar="SECONDS",
+                    help="also run the serving loop for SECONDS: sparse cameras of 346x260, "
+                         "640x480 and 1280x720 with Poisson frame arrivals at 30-240 fps")
+    ap.add_argument("--cameras", type=int, default=32, help="cameras of the serving leg")
     return ap.parse_args()
 
 
-def chain_bytes(npix: int, K: int, active: int, selected: int, events: int, method: str) -> int:
+def chain_bytes(npix: int, K: int, active: int, selected: int, events: int, method: str,
+                memoryless: bool = False) -> int:
     """Minimum HBM bytes of one chain-kernel launch (the dominant kernel) over a window of K
     intervals.  Per chain (an active pixel for sparse, every pixel otherwise): its list slot and
-    selected-interval bitmask (sparse: 4 + 16 B), its reference level read and written (8 B).
-    Per interpolated pixel-interval: the two endpoint bytes and the flow vector (2 + 8 B; basic
-    reads no flow).  Per event: one 8-byte key written."""
+    selected-interval bitmask (sparse: 4 + 16 B), its reference level read and written (8 B; none
+    for the memoryless and difference thresholding).  Per interpolated pixel-interval: the
+    endpoint bytes (2; the difference method reads 3 frames) and the flow vector (8 B; basic
+    reads none).  Per event: one 8-byte key written."""
+    ref = 0 if (memoryless or method == "difference") else 8
     if method == "sparse":
-        per_chain = 4 + 16 + 8
+        per_chain = 4 + 16 + ref
         chains = active
     else:
-        per_chain, chains = 8, npix
+        per_chain, chains = ref, npix
         selected = npix * K
-    per_sel = 2 + (0 if method == "basic" else 8)
+    per_sel = (3 if method == "difference" else 2) + (0 if method == "basic" else 8)
     return chains * per_chain + selected * per_sel + 8 * events
+
+
+BATCH_SHAPES = [(240, 180), (346, 260), (640, 480), (1920, 1080)]
+SERVE_SHAPES = [(346, 260), (640, 480), (1280, 720)]
+
+
+def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
+    """Streams of mixed resolution and method (the batched configuration's recipe, scaled to
+    `args.batched` streams): per frame step, one sim_push_batch of every stream's frame against
+    one push per stream.  Inputs resident in HBM; events drained into device buffers."""
+    methods = ["dense", "sparse", "basic"]
+    streams, data = [], []
+    for i in range(args.batched):
+        W, H = shapes[i % 4]
+        method = methods[(i // 4) % 3]
+        v = synth.blob_video(synth.mixed_stream(W, H, seed=100 + i, n_frames=n_frames),
+                             with_flow=method != "basic")
+        fr = torch.from_numpy(v.frames).to(dev)
+        fl = torch.from_numpy(v.flows).to(dev) if method != "basic" else None
+        data.append((fr, fl, v.t_us, W * H))
+        streams.append(sim.Stream(W, H, method=method, c_pos=0.15, c_neg=0.15))
+    torch.cuda.synchronize()
+    px_per_step = sum(d[3] for d in data)
+
+    def run(batched):
+        for st in streams:
+            st.reset()
+        for k in range(n_frames):
+            if batched:
+                sim.push_batch([(st, fr[k:k + 1], None if (fl is None or k == 0)
+                                 else fl[k - 1:k], t[k:k + 1])
+                                for st, (fr, fl, t, _) in zip(streams, data)])
+            else:
+                for st, (fr, fl, t, _) in zip(streams, data):
+                    st.push(fr[k], None if (fl is None or k == 0) else fl[k - 1], int(t[k]))
+        ev = 0
+        for st in streams:
+            ev += st.pending()
+            out = torch.empty(max(1, st.pending()), dtype=torch.int64, device=dev)
+            st.drain_keys(out=out)
+        torch.cuda.synchronize()
+        return ev
+
+    res, secs = {}, {}
+    for name, batched in (("batched", True), ("plain", False)):
+        run(batched)                                   # warm-up: buffers reach their sizes
+        t0 = time.perf_counter()
+        ev = run(batched)
+        dt = time.perf_counter() - t0
+        secs[name] = dt
+        res[name] = {"mpix_frames_per_s": round(px_per_step * (n_frames - 1) / dt / 1e6, 1),
+                     "ms_per_frame_step": round(1e3 * dt / (n_frames - 1), 3),
+                     "events_per_s": round(ev / dt, 1)}
+    for st in streams:
+        st.close()
+    res["streams"] = args.batched
+    res["speedup"] = round(secs["plain"] / secs["batched"], 3)
+    return res
+
+
+def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES, pin=True):
+    """Serving loop: cameras of the serving configuration's resolutions, sparse method, frames
+    arriving as Poisson processes (rate U[30, 240] fps per camera) and copied from pinned host
+    memory on arrival; the loop steps the server whenever frames are queued.  Reports per-frame
+    latency (arrival to ordered events) and throughput."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    pools = {}
+    for W, H in res_opts:
+        v = synth.blob_video(synth.mixed_stream(W, H, seed=W, n_frames=16))
+        fr, fl = torch.from_numpy(v.frames), torch.from_numpy(v.flows)
+        pools[(W, H)] = (fr.pin_memory(), fl.pin_memory()) if pin else (fr, fl)
+    srv = sim.Server(hbm_budget_bytes=64 << 30, max_cameras=args.cameras, queue_depth=8)
+    cams = []
+    for c in range(args.cameras):
+        W, H = res_opts[int(rng.integers(3))]
+        try:
+            cid = srv.admit(width=W, height=H, method="sparse", c_pos=0.2, c_neg=0.2)
+        except sim.SimError:
+            continue
+        cams.append(dict(id=cid, W=W, H=H, rate=float(rng.uniform(30, 240)), k=0,
+                         next=0.0, t=0))
+    start = time.perf_counter()
+    for c in cams:
+        c["next"] = start + float(rng.exponential(1.0 / c["rate"]))
+    frames = 0
+    while time.perf_counter() - start < args.serve:
+        now = time.perf_counter()
+        queued = False
+        for c in cams:
+            while c["next"] <= now:
+                fr, fl = pools[(c["W"], c["H"])]
+                j = c["k"] % 16
+                flow = None if c["k"] == 0 else fl[(j - 1) % 15]
+                c["t"] += 1 + int(1e6 / c["rate"])
+                try:
+                    srv.submit(c["id"], fr[j], flow, c["t"],
+                               arrival_ns=int(srv.now_ns() - (now - c["next"]) * 1e9))
+                    c["k"] += 1
+                    queued = True
+                except sim.SimError:
+                    pass                                # queue full: the frame is dropped
+                c["next"] += float(rng.exponential(1.0 / c["rate"]))
+        if queued:
+            frames += srv.step()
+            for c in cams:
+                srv.drain_keys(c["id"])
+    st = srv.stats()
+    srv.close()
+    wall = time.perf_counter() - start
+    return {"cameras": len(cams), "seconds": round(wall, 2), "frames": frames,
+            "frames_per_s": round(frames / wall, 1), "events_per_s": round(st["events"] / wall, 1),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "max_ms": round(st["max_ms"], 3), "rejected_frames": st["rejected_frames"],
+            "rejected_admissions": st["rejected_admissions"], "steps": st["steps"]}
 
 
 def main():
@@ -78,6 +212,7 @@ def main():
 
     wl = WORKLOADS[args.workload]
     spec = getattr(synth, wl["spec"])()
+    supplied = wl["method"] != "basic" and wl.get("flow", "supplied") == "supplied"
     video = synth.blob_video(spec, with_flow=wl["method"] != "basic")
     T, H, W = video.frames.shape
     npix = H * W
@@ -85,12 +220,13 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     frames = torch.from_numpy(video.frames).to(dev)
-    flows = torch.from_numpy(video.flows).to(dev) if wl["method"] != "basic" else None
+    flows = torch.from_numpy(video.flows).to(dev) if supplied else None
     t_us = video.t_us
     torch.cuda.synchronize()
 
     s = sim.Stream(W, H, method=wl["method"], c_pos=wl["c"], c_neg=wl["c"],
-                   n_interp=wl["n_interp"], hip_stream="torch")
+                   n_interp=wl["n_interp"], hip_stream="torch",
+                   thresh_mode=wl.get("thresh", "reference"), flow_source=wl.get("flow", "supplied"))
     s.set_kernel_timing(True)
     out = torch.empty(max(1, 4 * npix * K // 10), dtype=torch.int64, device=dev)
 
@@ -128,7 +264,8 @@ def main():
     launch_ms = sim_ms / max(1, sim_launches)
     launches_per_step = sim_launches / args.steps
     act_per_step = st["active"] // args.steps
-    alg = chain_bytes(npix, K, act_per_step, sel_per_step, ev_per_step, wl["method"])
+    alg = chain_bytes(npix, K, act_per_step, sel_per_step, ev_per_step, wl["method"],
+                      memoryless=wl.get("thresh") == "memoryless")
     alg_per_launch = alg / launches_per_step
     achieved = alg_per_launch / (launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -165,7 +302,9 @@ def main():
         from oracle.oracle import OracleSim
         oracle.build(force=False)
         o = OracleSim(W, H, method=sim.METHODS[wl["method"]], c_pos=wl["c"], c_neg=wl["c"],
-                      n_interp=wl["n_interp"])
+                      n_interp=wl["n_interp"],
+                      thresh_mode=sim.THRESH_MODES[wl.get("thresh", "reference")],
+                      flow_source=sim.FLOW_SOURCES[wl.get("flow", "supplied")])
         o.push(video.frames[0], None, int(t_us[0]))
         a = time.perf_counter()
         done, oev = 0, 0
@@ -180,6 +319,9 @@ def main():
                "sample": f"first {done} of {K} intervals of the same {W}x{H} sequence, "
                          f"single-threaded C oracle ({ct:.1f} s, {oev} events, "
                          f"{oev / ct:.3g} events/s)"}
+
+    batched = batched_leg(args, sim, synth, torch, dev) if args.batched else None
+    served = serve_leg(args, sim, synth, torch, dev) if args.serve > 0 else None
 
     line = {
         "metric": "Mpixel-frames/s + events/s vs HBM roofline; p50/p99 frame latency, batched vs plain",
@@ -209,6 +351,15 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if wl.get("thresh"):
+        line["config"]["thresh_mode"] = wl["thresh"]
+    if wl.get("flow"):
+        line["config"]["flow_source"] = wl["flow"]
+        line["flow_estimation_note"] = "flow estimation runs inside select_ms_per_step"
+    if batched is not None:
+        line["batched_vs_plain_streams"] = batched
+    if served is not None:
+        line["serving"] = served
     print(json.dumps(line), flush=True)
 
 
