@@ -92,3 +92,112 @@ def test_server_interleaved_cameras_equal_cameras_alone():
     assert st["completed"] == 36 and st["failed_frames"] == 0
     assert 0 <= st["p50_ms"] <= st["p99_ms"]
     srv.close()
+
+
+def test_c4_batched_64_streams_full_size():
+    """The batched configuration at full size: 64 streams, 16 each of 240x180, 346x260, 640x480
+    and 1920x1080, all three methods, 30 frames, pushed as one batch per frame step (the launch
+    configuration of bench.py --batched).  Every stream equals the same stream pushed alone on
+    the GPU; sampled streams covering every resolution and method equal the oracle."""
+    import torch
+    vids = {}
+    for W, H in SHAPES:
+        v = synth.blob_video(synth.mixed_stream(W, H, seed=W + H, n_frames=30))
+        vids[(W, H)] = (v, torch.from_numpy(v.frames).cuda(), torch.from_numpy(v.flows).cuda())
+    torch.cuda.synchronize()
+    cfgs = []
+    for i in range(64):
+        W, H = SHAPES[i % 4]
+        method = [sim.DENSE, sim.SPARSE, sim.BASIC][(i // 4) % 3]
+        c = [0.12, 0.15, 0.2, 0.25][(i // 12) % 4]
+        cfgs.append(dict(W=W, H=H, method=method, c=c))
+    streams = [sim.Stream(d["W"], d["H"], method=d["method"], c_pos=d["c"], c_neg=d["c"])
+               for d in cfgs]
+    for k in range(30):
+        entries = []
+        for st, d in zip(streams, cfgs):
+            v, fr, fl = vids[(d["W"], d["H"])]
+            flow = None if (d["method"] == sim.BASIC or k == 0) else fl[k - 1:k]
+            entries.append((st, fr[k:k + 1], flow, v.t_us[k:k + 1]))
+        sim.push_batch(entries)
+    batched = [st.drain_keys() for st in streams]
+    for st in streams:
+        st.close()
+    for i, d in enumerate(cfgs):
+        v, fr, fl = vids[(d["W"], d["H"])]
+        s = sim.Stream(d["W"], d["H"], method=d["method"], c_pos=d["c"], c_neg=d["c"])
+        s.push_frames(fr, None if d["method"] == sim.BASIC else fl, v.t_us)
+        np.testing.assert_array_equal(batched[i], s.drain_keys(), err_msg=str(d))
+        s.close()
+    # sampled against the oracle: every resolution and every method
+    sampled = [0, 5, 10, 3, 7]
+    assert {(cfgs[i]["W"], cfgs[i]["method"]) for i in sampled} == {
+        (SHAPES[0][0], sim.DENSE), (SHAPES[1][0], sim.SPARSE), (SHAPES[2][0], sim.BASIC),
+        (SHAPES[3][0], sim.DENSE), (SHAPES[3][0], sim.SPARSE)}
+    for i in sampled:
+        d = cfgs[i]
+        v = vids[(d["W"], d["H"])][0]
+        ok, _ = oracle_keys(v.frames, None if d["method"] == sim.BASIC else v.flows, v.t_us,
+                            method=d["method"], c_pos=d["c"], c_neg=d["c"])
+        np.testing.assert_array_equal(batched[i], ok, err_msg=str(d))
+
+
+def test_c5_serving_256_cameras():
+    """The serving configuration's camera population: 256 sparse cameras (C = 0.2) with
+    resolutions drawn from 346x260, 640x480 and 1280x720, admitted by footprint, frames from
+    device-resident pools at per-camera phases and rates U[30, 240] fps, submitted in random
+    interleaving with steps at random points.  Every camera equals the same frames pushed alone
+    on the GPU; sampled cameras equal the oracle; latency percentiles are reported."""
+    import torch
+    rng = np.random.default_rng(11)
+    res = [(346, 260), (640, 480), (1280, 720)]
+    pools = {}
+    for W, H in res:
+        v = synth.blob_video(synth.mixed_stream(W, H, seed=3 * W, n_frames=16))
+        pools[(W, H)] = (v, torch.from_numpy(v.frames).cuda(), torch.from_numpy(v.flows).cuda())
+    torch.cuda.synchronize()
+    srv = sim.Server(hbm_budget_bytes=200 << 30, max_cameras=256, queue_depth=4)
+    cams = []
+    for c in range(256):
+        W, H = res[int(rng.integers(3))]
+        cid = srv.admit(width=W, height=H, method="sparse", c_pos=0.2, c_neg=0.2)
+        rate = float(rng.uniform(30, 240))
+        cams.append(dict(id=cid, W=W, H=H, phase=int(rng.integers(8)), step=int(1e6 / rate),
+                         k=0))
+    n_frames = 6
+    order = [c for c in range(256) for _ in range(n_frames)]
+    rng.shuffle(order)
+    for c in order:
+        cam = cams[c]
+        v, fr, fl = pools[(cam["W"], cam["H"])]
+        j = cam["phase"] + cam["k"]
+        flow = None if cam["k"] == 0 else fl[j - 1]
+        t = 1000 + cam["k"] * cam["step"]
+        while True:
+            try:
+                srv.submit(cam["id"], fr[j], flow, t)
+                break
+            except sim.SimError as e:
+                assert e.status == sim.E_BUSY
+                srv.step()
+        cam["k"] += 1
+        if rng.random() < 0.02:
+            srv.step()
+    srv.step()
+    st = srv.stats()
+    assert st["cameras"] == 256 and st["completed"] == 256 * n_frames
+    assert st["failed_frames"] == 0 and 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    for idx, cam in enumerate(cams):
+        v, fr, fl = pools[(cam["W"], cam["H"])]
+        a, b = cam["phase"], cam["phase"] + n_frames
+        t = [1000 + k * cam["step"] for k in range(n_frames)]
+        got = srv.drain_keys(cam["id"])
+        s = sim.Stream(cam["W"], cam["H"], method="sparse", c_pos=0.2, c_neg=0.2)
+        s.push_frames(fr[a:b].contiguous(), fl[a:b - 1].contiguous(), t)
+        np.testing.assert_array_equal(got, s.drain_keys(), err_msg=str(cam))
+        s.close()
+        if idx < 6:
+            ok, _ = oracle_keys(v.frames[a:b], v.flows[a:b - 1], t, method=sim.SPARSE,
+                                c_pos=0.2, c_neg=0.2)
+            np.testing.assert_array_equal(got, ok, err_msg=str(cam))
+    srv.close()
