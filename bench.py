@@ -11,9 +11,13 @@ Default workload: 1280x720 sparse-flow interpolation, 120 frames at 60 fps (119 
 
 Prints one JSON line (rank 0, N = 1).  Extra fields report the events/s rate, the per-frame
 latency of plain one-frame pushes (p50 / p99) next to the batched window push, and the dominant
-kernel against the HBM roofline.  Optional legs (off by default): --workload for the memoryless,
-difference-frame and estimated-flow variants; --batched STREAMS (mixed-resolution streams, one
-batched push per frame step against one push per stream); --serve SECONDS (the serving loop).
+kernel against the HBM roofline.  After the main measurement (and the CPU baseline), a child
+process times the extra legs and the line carries them under "extra_legs" (or an "error" entry if
+the child fails or exceeds --legs-timeout; the main figures are unaffected): the memoryless,
+difference-frame and estimated-flow workloads, 64 mixed-resolution streams pushed as one batch
+per frame step against one push per stream, and a 10 s serving run with 256 cameras.
+--no-legs skips them; --workload, --batched STREAMS and --serve SECONDS run single legs in
+process.
 """
 from __future__ import annotations
 
@@ -61,6 +65,12 @@ def parse():
                     help="also run the serving loop for SECONDS: sparse cameras of 346x260, "
                          "640x480 and 1280x720 with Poisson frame arrivals at 30-240 fps")
     ap.add_argument("--cameras", type=int, default=32, help="cameras of the serving leg")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the extra legs (memoryless, difference, estimated flow, 64 batched "
+                         "streams, 256-camera serving) that run in a child process after the "
+                         "main measurement")
+    ap.add_argument("--legs-timeout", type=float, default=300.0)
+    ap.add_argument("--legs-child", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -92,16 +102,19 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
     `args.batched` streams): per frame step, one sim_push_batch of every stream's frame against
     one push per stream.  Inputs resident in HBM; events drained into device buffers."""
     methods = ["dense", "sparse", "basic"]
+    videos = {}
+    for W, H in shapes:              # one device-resident video per resolution, shared
+        v = synth.blob_video(synth.mixed_stream(W, H, seed=W + H, n_frames=n_frames))
+        videos[(W, H)] = (torch.from_numpy(v.frames).to(dev), torch.from_numpy(v.flows).to(dev),
+                          v.t_us)
     streams, data = [], []
     for i in range(args.batched):
-        W, H = shapes[i % 4]
-        method = methods[(i // 4) % 3]
-        v = synth.blob_video(synth.mixed_stream(W, H, seed=100 + i, n_frames=n_frames),
-                             with_flow=method != "basic")
-        fr = torch.from_numpy(v.frames).to(dev)
-        fl = torch.from_numpy(v.flows).to(dev) if method != "basic" else None
-        data.append((fr, fl, v.t_us, W * H))
-        streams.append(sim.Stream(W, H, method=method, c_pos=0.15, c_neg=0.15))
+        W, H = shapes[i % len(shapes)]
+        method = methods[(i // len(shapes)) % 3]
+        c = [0.12, 0.15, 0.2, 0.25][(i // 12) % 4]
+        fr, fl, t = videos[(W, H)]
+        data.append((fr, None if method == "basic" else fl, t, W * H))
+        streams.append(sim.Stream(W, H, method=method, c_pos=c, c_neg=c))
     torch.cuda.synchronize()
     px_per_step = sum(d[3] for d in data)
 
@@ -198,27 +211,17 @@ def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES, pin=True):
             "rejected_admissions": st["rejected_admissions"], "steps": st["steps"]}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this simulator runs on one GPU; sharding across GPUs is "
-                          "designed but not implemented", "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
+    """Times `steps` whole-sequence steps of a workload (after `warmup`); returns the figures of
+    the bench line and the objects the CPU-baseline leg needs."""
     import numpy as np
-    import torch
-
-    from paper_2209_04634_amd import sim, synth
-
-    wl = WORKLOADS[args.workload]
+    wl = WORKLOADS[wl_name]
     spec = getattr(synth, wl["spec"])()
     supplied = wl["method"] != "basic" and wl.get("flow", "supplied") == "supplied"
     video = synth.blob_video(spec, with_flow=wl["method"] != "basic")
     T, H, W = video.frames.shape
     npix = H * W
     K = T - 1
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
     frames = torch.from_numpy(video.frames).to(dev)
     flows = torch.from_numpy(video.flows).to(dev) if supplied else None
     t_us = video.t_us
@@ -239,31 +242,28 @@ def main():
         assert got == n
         return n
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     s.clear_stats()
     events = 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         events += step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     st = s.stats()
     selected = st["selected"]
     sim_ms, sim_launches = st["simulate_ms"], st["simulate_launches"]
     sel_ms = st["select_ms"]
-    sort_ms, sort_launches = st["sort_ms"], st["sort_launches"]
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = npix * K * args.steps / elapsed / 1e6
-    ev_per_step = events // args.steps
-    sel_per_step = (selected // args.steps) if wl["method"] == "sparse" else npix * K
+    sort_ms = st["sort_ms"]
+    ev_per_step = events // steps
+    sel_per_step = (selected // steps) if wl["method"] == "sparse" else npix * K
 
     # dominant kernel: the per-pixel chain launch (one per step: the window holds every interval)
     launch_ms = sim_ms / max(1, sim_launches)
-    launches_per_step = sim_launches / args.steps
-    act_per_step = st["active"] // args.steps
+    launches_per_step = sim_launches / steps
+    act_per_step = st["active"] // steps
     alg = chain_bytes(npix, K, act_per_step, sel_per_step, ev_per_step, wl["method"],
                       memoryless=wl.get("thresh") == "memoryless")
     alg_per_launch = alg / launches_per_step
@@ -274,8 +274,8 @@ def main():
                 "algorithmic_bytes_per_launch": int(alg_per_launch)}
 
     # plain path: one push per frame, latency of each push until its events are ordered
-    plain = None
-    if not args.no_plain:
+    plain_res = None
+    if plain:
         s.reset()
         s.push(frames[0], None, int(t_us[0]))
         lat = []
@@ -285,9 +285,99 @@ def main():
             lat.append(time.perf_counter() - a)
         s.drain_keys(out=out)
         lat_ms = np.array(lat) * 1e3
-        plain = {"p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
-                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
-                 "mpix_frames_per_s": round(npix * K / lat_ms.sum() * 1e3 / 1e6, 1)}
+        plain_res = {"p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+                     "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+                     "mpix_frames_per_s": round(npix * K / lat_ms.sum() * 1e3 / 1e6, 1)}
+    s.close()
+    return {
+        "value": round(npix * K * steps / elapsed / 1e6, 1),
+        "ms_per_step": round(1e3 * elapsed / steps, 4),
+        "events_per_s": round(ev_per_step * steps / elapsed, 1),
+        "events_per_step": ev_per_step,
+        "selected_fraction": round(sel_per_step / (npix * K), 5),
+        "active_pixels_per_step": act_per_step,
+        "select_ms_per_step": round(sel_ms / steps, 4),
+        "simulate_ms_per_step": round(sim_ms / steps, 4),
+        "sort_ms_per_step": round(sort_ms / steps, 4),
+        "plain_one_frame_pushes": plain_res,
+        "roofline": roofline,
+        "_video": video, "_spec": spec, "_wl": wl, "_shape": (T, H, W),
+    }
+
+
+LEG_WORKLOADS = ["memoryless_dense_346x260", "difference_346x260", "lk_sparse_1280x720"]
+
+
+def legs_child(args):
+    """The optional legs, run in a child process of the default bench so that the main line is
+    measured and printed whatever happens here: the memoryless, difference-frame and
+    estimated-flow workloads; 64 mixed-resolution streams batched against plain pushes; the
+    serving loop with 256 cameras."""
+    import torch
+    from paper_2209_04634_amd import sim, synth
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    res = {}
+    for name in LEG_WORKLOADS:
+        t0 = time.perf_counter()
+        m = measure(name, 5, 2, sim, synth, torch, dev, plain=False)
+        wl = m["_wl"]
+        res[name] = {k: v for k, v in m.items() if not k.startswith("_") and v is not None}
+        res[name]["config"] = {"method": wl["method"], "c": wl["c"], "n_interp": wl["n_interp"],
+                               "thresh_mode": wl.get("thresh", "reference"),
+                               "flow_source": wl.get("flow", "supplied"),
+                               "width": m["_shape"][2], "height": m["_shape"][1],
+                               "frames": m["_shape"][0]}
+        res[name]["wall_s"] = round(time.perf_counter() - t0, 1)
+        print(f"leg {name} done", file=sys.stderr, flush=True)
+    args.batched = args.batched or 64
+    res["batched_vs_plain_streams"] = batched_leg(args, sim, synth, torch, dev)
+    print("leg batched done", file=sys.stderr, flush=True)
+    args.cameras = 256
+    args.serve = args.serve or 10.0
+    res["serving"] = serve_leg(args, sim, synth, torch, dev)
+    print("leg serving done", file=sys.stderr, flush=True)
+    print(json.dumps(res), flush=True)
+
+
+def run_legs(timeout_s):
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--legs-child"]
+    try:
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        return {"error": f"legs did not finish within {timeout_s} s"}
+    sys.stderr.write(r.stderr[-2000:])
+    if r.returncode != 0:
+        return {"error": f"legs exited with status {r.returncode}",
+                "stderr_tail": r.stderr[-600:]}
+    try:
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return {"error": "legs printed no result"}
+
+
+def main():
+    args = parse()
+    if args.legs_child:
+        legs_child(args)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this simulator runs on one GPU; sharding across GPUs is "
+                          "designed but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2209_04634_amd import sim, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    m = measure(args.workload, args.steps, args.warmup, sim, synth, torch, dev,
+                plain=not args.no_plain)
+    wl, spec, video = m["_wl"], m["_spec"], m["_video"]
+    T, H, W = m["_shape"]
+    npix, K, t_us = H * W, T - 1, video.t_us
 
     if args.copy_probe_mib:
         a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
@@ -305,11 +395,12 @@ def main():
                       n_interp=wl["n_interp"],
                       thresh_mode=sim.THRESH_MODES[wl.get("thresh", "reference")],
                       flow_source=sim.FLOW_SOURCES[wl.get("flow", "supplied")])
+        supplied = wl["method"] != "basic" and wl.get("flow", "supplied") == "supplied"
         o.push(video.frames[0], None, int(t_us[0]))
         a = time.perf_counter()
         done, oev = 0, 0
         while done < K and (time.perf_counter() - a) < args.cpu_seconds:
-            e = o.push(video.frames[done + 1], None if flows is None else video.flows[done],
+            e = o.push(video.frames[done + 1], video.flows[done] if supplied else None,
                        int(t_us[done + 1]))
             oev += len(e)
             done += 1
@@ -322,15 +413,18 @@ def main():
 
     batched = batched_leg(args, sim, synth, torch, dev) if args.batched else None
     served = serve_leg(args, sim, synth, torch, dev) if args.serve > 0 else None
+    legs = None
+    if not args.no_legs and not args.batched and args.serve <= 0:
+        legs = run_legs(args.legs_timeout)
 
     line = {
         "metric": "Mpixel-frames/s + events/s vs HBM roofline; p50/p99 frame latency, batched vs plain",
-        "value": round(value, 1),
+        "value": m["value"],
         "unit": "Mpixel-frames/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -340,17 +434,12 @@ def main():
                    "fps": spec.fps, "method": wl["method"], "c_pos": wl["c"],
                    "c_neg": wl["c"], "n_interp": wl["n_interp"], "blobs": spec.n_blobs,
                    "seed": spec.seed, "mode": "window push (one launch per sequence)"},
-        "events_per_s": round(ev_per_step * args.steps / elapsed, 1),
-        "events_per_step": ev_per_step,
-        "selected_fraction": round(sel_per_step / (npix * K), 5),
-        "active_pixels_per_step": act_per_step,
-        "select_ms_per_step": round(sel_ms / args.steps, 4),
-        "simulate_ms_per_step": round(sim_ms / args.steps, 4),
-        "sort_ms_per_step": round(sort_ms / args.steps, 4),
-        "plain_one_frame_pushes": plain,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
     }
+    for k in ("events_per_s", "events_per_step", "selected_fraction", "active_pixels_per_step",
+              "select_ms_per_step", "simulate_ms_per_step", "sort_ms_per_step",
+              "plain_one_frame_pushes", "roofline"):
+        line[k] = m[k]
+    line["cpu_baseline"] = cpu
     if wl.get("thresh"):
         line["config"]["thresh_mode"] = wl["thresh"]
     if wl.get("flow"):
@@ -360,6 +449,8 @@ def main():
         line["batched_vs_plain_streams"] = batched
     if served is not None:
         line["serving"] = served
+    if legs is not None:
+        line["extra_legs"] = legs
     print(json.dumps(line), flush=True)
 
 
