@@ -73,3 +73,51 @@ def test_product_path_does_not_use_the_oracle():
             for needle in ("import oracle", "from oracle", "liboracle", "oracle_", "oracle/"):
                 assert needle not in text, (path, needle)
     assert "liboracle" not in open(sim.LIB_PATH, "rb").read().decode("latin1")
+
+
+def test_host_only_entry_points_of_the_wider_rows():
+    """New configuration fields, the estimator's parameters and the server's admission are
+    validated on the host, before any device call."""
+    lib = sim.load()
+    cfg = sim.SimConfig()
+    lib.sim_config_init(ctypes.byref(cfg))
+    assert (cfg.thresh_mode, cfg.flow_source) == (sim.REFERENCE, sim.FLOW_SUPPLIED)
+    h = ctypes.c_void_p()
+    cfg.width = cfg.height = 16
+    for field, value in (("method", 4), ("thresh_mode", 2), ("flow_source", 2)):
+        bad = sim.SimConfig.from_buffer_copy(cfg)
+        setattr(bad, field, value)
+        assert lib.sim_create(ctypes.byref(bad), ctypes.byref(h)) == sim.E_INVAL, field
+    for method in (sim.BASIC, sim.DIFFERENCE):          # estimated flow: dense and sparse only
+        bad = sim.SimConfig.from_buffer_copy(cfg)
+        bad.method, bad.flow_source = method, sim.FLOW_LK
+        assert lib.sim_create(ctypes.byref(bad), ctypes.byref(h)) == sim.E_INVAL
+    p = sim.SimLkParams()
+    lib.sim_lk_params_init(ctypes.byref(p))
+    assert (p.levels, p.radius, p.iterations) == (3, 7, 10)
+    assert p.eps == pytest.approx(1e-4) and p.min_ratio == pytest.approx(1e-3)
+    f = (ctypes.c_uint8 * 64)()
+    pts = (ctypes.c_uint32 * 1)()
+    fl = (ctypes.c_float * 2)()
+    for field, value in (("levels", 5), ("radius", 0), ("radius", 16), ("iterations", 0),
+                         ("eps", -1.0)):
+        bad = sim.SimLkParams.from_buffer_copy(p)
+        setattr(bad, field, value)
+        assert lib.sim_lk_flow(f, f, 8, 8, pts, 1, fl, None, ctypes.byref(bad), sim.MEM_HOST,
+                               None) == sim.E_INVAL, field
+    assert lib.sim_lk_flow(f, f, 0, 8, pts, 1, fl, None, None, sim.MEM_HOST, None) == sim.E_INVAL
+    assert lib.sim_lk_flow(f, f, 8, 8, None, 1, fl, None, None, sim.MEM_HOST, None) == sim.E_INVAL
+    assert lib.sim_lk_flow(f, f, 8, 8, pts, 0, fl, None, None, sim.MEM_HOST, None) == sim.OK
+    # server admission arithmetic and creation are host-side
+    out = ctypes.c_uint64()
+    small = sim.SimConfig.from_buffer_copy(cfg)
+    small.method = sim.SPARSE
+    assert lib.srv_footprint(ctypes.byref(small), 4, ctypes.byref(out)) == sim.OK
+    sparse_fp = out.value
+    small.method = sim.BASIC
+    assert lib.srv_footprint(ctypes.byref(small), 4, ctypes.byref(out)) == sim.OK
+    assert out.value < sparse_fp and out.value >= 256 * (4 + 2 + 4 + 16 + 32 + 16 + 4)
+    srv = ctypes.c_void_p()
+    assert lib.srv_create(1 << 30, 0, 4, ctypes.byref(srv)) == sim.E_INVAL
+    assert lib.srv_create(1 << 30, 4, 4, ctypes.byref(srv)) == sim.OK
+    assert lib.srv_destroy(srv) == sim.OK
