@@ -125,6 +125,53 @@ hipError_t launch_moments(const uint32_t* counts, uint64_t plane, unsigned long 
                           hipStream_t stream);
 
 // ------------------------------------------------------------------------------------------
+// Fused batch: one launch per phase over every stream of a batched push.  Each stream of the
+// launch is one BatchEntry in device memory; a block finds its entry by binary search over the
+// launch's block offsets (entry e owns blocks [start[e], start[e + 1])) and runs the same block
+// body as the stream's own kernel with its block index inside the stream.
+// ------------------------------------------------------------------------------------------
+struct BatchEntry {
+    int sparse;                      // 1: selection pass; 0: frame copies
+    int vec;                         // selection: 4-byte aligned frames (vector loads)
+    SelectArgs sel;
+    const uint8_t* copy_src;         // non-sparse: the window's last frame -> prev_out
+    uint8_t* copy_dst;
+    const uint8_t* copy2_src;        // difference method: the frame before it -> prev2 out
+    uint8_t* copy2_dst;
+    int64_t npix;
+    unsigned long long* counters;    // [0] failed reservations [1] sentinels [2] gathered
+    ChainArgs chain;
+    uint64_t clamp_cap;              // re-run: clamp reservations to this (old) stripe capacity
+    uint64_t* gathered;              // gather output = sort input
+    uint64_t* sort_alt;              // sort ping-pong buffer
+    uint32_t* hist;
+    uint32_t* totals;
+    uint64_t* out;                   // the stream's FIFO tail
+    ConvertArgs cv;
+    int sort_blocks;                 // 0: nothing to sort
+};
+
+// Block offsets of each fused launch live in device memory as n + 1 ints.
+hipError_t launch_batch_prep(const BatchEntry* e, int n, hipStream_t stream);
+hipError_t launch_batch_select(const BatchEntry* e, const int* start, int n, int blocks,
+                               hipStream_t stream);
+hipError_t launch_batch_chain(const BatchEntry* e, const int* start, int n, int blocks, int mode,
+                              int max_stash, hipStream_t stream);
+// out[e] = failed reservations of entry e (counters[0]).
+hipError_t launch_batch_fails(const BatchEntry* e, int n, unsigned long long* out,
+                              hipStream_t stream);
+// For every entry with a nonzero clamp_cap: clamp its reservations, clear its failure count.
+hipError_t launch_batch_clamp(const BatchEntry* e, int n, hipStream_t stream);
+hipError_t launch_batch_gather(const BatchEntry* e, const int* start, int n, int blocks,
+                               hipStream_t stream);
+// out[2e] = sentinels, out[2e + 1] = gathered keys of entry e.
+hipError_t launch_batch_counts(const BatchEntry* e, int n, unsigned long long* out,
+                               hipStream_t stream);
+// Every pass of the sort of every entry (`passes` passes; the last converts into `out`).
+hipError_t launch_batch_sort(const BatchEntry* e, const int* start, int n, int blocks, int passes,
+                             hipStream_t stream);
+
+// ------------------------------------------------------------------------------------------
 // Pyramidal Lucas-Kanade flow (evsim_lk.hip).
 // ------------------------------------------------------------------------------------------
 constexpr int kLkMaxLevels = 4;      // pyramid levels above full resolution

@@ -265,13 +265,13 @@ __device__ __forceinline__ int next_selected(bool all, uint32_t m0, uint32_t m1,
 // list (wave-aggregated reservation).
 // ------------------------------------------------------------------------------------------
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_select(SelectArgs a) {
+__device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
     __shared__ float lut[256];
     const int tid = threadIdx.x;
     lut[tid] = a.lut[tid];
     __syncthreads();
     const int lane = tid & 63;
-    const int base = (blockIdx.x * 256 + tid) * 4;
+    const int base = (bid * 256 + tid) * 4;
     const int cnt = max(0, min(4, a.npix - base));
 
     uint32_t last = 0;
@@ -331,11 +331,11 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     __syncthreads();
     int sel_total;
     block_scan_256(nsel, s_wsum, &sel_total);
-    const int stripe = blockIdx.x % kActStripes;
+    const int stripe = bid % kActStripes;
     if (tid == 0) {
         s_slot0 = total > 0 ? atomicAdd(a.n_active + stripe * kCounterStride, (unsigned int)total)
                             : 0u;
-        unsigned long long* st = a.stats + (blockIdx.x % kStatStripes) * kCounterStride;
+        unsigned long long* st = a.stats + (bid % kStatStripes) * kCounterStride;
         if (sel_total > 0) atomicAdd(st, (unsigned long long)sel_total);
         if (total > 0) atomicAdd(st + 1, (unsigned long long)total);
     }
@@ -352,6 +352,11 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
     (void)lane;
 }
 
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_select(SelectArgs a) {
+    select_block<VEC>(a, blockIdx.x);
+}
+
 // ------------------------------------------------------------------------------------------
 // Chain pass.  One lane per pixel (per active pixel for the sparse method) walks that pixel's
 // selected intervals in order, carrying its reference level in a register: the only temporal
@@ -365,14 +370,14 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
 // frames (no reference level, which is then neither read nor written).
 // ------------------------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
+__device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
     extern __shared__ float smem[];
     float* lut = smem;
     const int tid = threadIdx.x, lane = tid & 63;
     lut[tid] = a.lut[tid];
     __syncthreads();
 
-    const int slot = blockIdx.x * kSimThreads + tid;
+    const int slot = bid * kSimThreads + tid;
     bool valid;
     if (a.act_px) {
         const int stripe = slot / a.act_cap;
@@ -491,6 +496,11 @@ __global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
     }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
+    chain_block<MODE>(a, blockIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_copy_u8(const uint8_t* __restrict__ src,
                                                  uint8_t* __restrict__ dst, int64_t n) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
@@ -500,11 +510,11 @@ __global__ __launch_bounds__(256) void k_copy_u8(const uint8_t* __restrict__ src
 
 // Concatenation of the sub-arenas.  Block b copies chunk b / kArenaStripes of stripe
 // b % kArenaStripes; its destination offset is the exclusive prefix of the stripe lengths.
-__global__ __launch_bounds__(kArenaStripes) void k_gather(const uint64_t* __restrict__ arena,
-                                                          uint64_t stripe_cap,
-                                                          const unsigned long long* reserve,
-                                                          uint64_t* __restrict__ out,
-                                                          unsigned long long* n_total) {
+__device__ __forceinline__ void gather_block(const uint64_t* __restrict__ arena,
+                                             uint64_t stripe_cap,
+                                             const unsigned long long* reserve,
+                                             uint64_t* __restrict__ out,
+                                             unsigned long long* n_total, unsigned bid) {
     static_assert(kArenaStripes == 256, "one thread per stripe");
     __shared__ int s_wsum[4];
     __shared__ unsigned long long s_len[kArenaStripes];
@@ -518,9 +528,9 @@ __global__ __launch_bounds__(kArenaStripes) void k_gather(const uint64_t* __rest
     __shared__ unsigned long long s_off[kArenaStripes];
     s_off[tid] = (unsigned long long)ex;
     __syncthreads();
-    const int stripe = blockIdx.x % kArenaStripes;
-    const uint64_t chunk = blockIdx.x / kArenaStripes;
-    if (blockIdx.x == 0 && tid == 0) *n_total = (unsigned long long)tot;
+    const int stripe = bid % kArenaStripes;
+    const uint64_t chunk = bid / kArenaStripes;
+    if (bid == 0 && tid == 0) *n_total = (unsigned long long)tot;
     const uint64_t n = s_len[stripe];
     const uint64_t b0 = chunk * kSortTile;
     if (b0 >= n) return;
@@ -528,6 +538,14 @@ __global__ __launch_bounds__(kArenaStripes) void k_gather(const uint64_t* __rest
     uint64_t* dst = out + s_off[stripe];
     const uint64_t e = min(b0 + (uint64_t)kSortTile, n);
     for (uint64_t j = b0 + tid; j < e; j += kArenaStripes) dst[j] = src[j];
+}
+
+__global__ __launch_bounds__(kArenaStripes) void k_gather(const uint64_t* __restrict__ arena,
+                                                          uint64_t stripe_cap,
+                                                          const unsigned long long* reserve,
+                                                          uint64_t* __restrict__ out,
+                                                          unsigned long long* n_total) {
+    gather_block(arena, stripe_cap, reserve, out, n_total, blockIdx.x);
 }
 
 __global__ void k_clamp(unsigned long long* reserve, uint64_t cap) {
@@ -591,32 +609,37 @@ __global__ __launch_bounds__(256) void k_moments(const uint32_t* __restrict__ co
 // ------------------------------------------------------------------------------------------
 // Stable LSD radix sort, 8-bit digits, three kernels per pass.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
-                                                             const unsigned long long* n_dev,
-                                                             int shift,
-                                                             uint32_t* __restrict__ hist,
-                                                             int nblocks) {
+__device__ __forceinline__ void hist_block(const uint64_t* __restrict__ keys,
+                                           const unsigned long long* n_dev, int shift,
+                                           uint32_t* __restrict__ hist, int nblocks, unsigned bid) {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
     const uint64_t n = *n_dev;
     h[tid] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)bid * kSortTile;
 #pragma unroll 4
     for (int j = 0; j < kSortItems; ++j) {
         const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
         if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
+    hist[(size_t)tid * nblocks + bid] = h[tid];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
+                                                             const unsigned long long* n_dev,
+                                                             int shift,
+                                                             uint32_t* __restrict__ hist,
+                                                             int nblocks) {
+    hist_block(keys, n_dev, shift, hist, nblocks, blockIdx.x);
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts; row total to totals[d].
-__global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __restrict__ hist,
-                                                                int nblocks,
-                                                                uint32_t* __restrict__ totals) {
+__device__ __forceinline__ void rowscan_block(uint32_t* __restrict__ hist, int nblocks,
+                                              uint32_t* __restrict__ totals, unsigned digit) {
     __shared__ int s_wsum[4];
-    uint32_t* row = hist + (size_t)blockIdx.x * nblocks;
+    uint32_t* row = hist + (size_t)digit * nblocks;
     uint32_t carry = 0;
     for (int b = 0; b < nblocks; b += kSortThreads) {
         const int j = b + threadIdx.x;
@@ -627,7 +650,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __rest
         carry += (uint32_t)tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) totals[digit] = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* __restrict__ hist,
+                                                                int nblocks,
+                                                                uint32_t* __restrict__ totals) {
+    rowscan_block(hist, nblocks, totals, blockIdx.x);
 }
 
 __device__ __forceinline__ uint64_t convert_key(uint64_t k, const ConvertArgs& cv) {
@@ -643,22 +672,22 @@ __device__ __forceinline__ uint64_t convert_key(uint64_t k, const ConvertArgs& c
     return (t << 25) | (y << 13) | (x << 1) | (pix & 1ull);
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+__device__ __forceinline__ void scatter_block(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
     const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv) {
+    const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv, unsigned bid) {
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_wcnt[4][256];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t n = *n_dev;
-    if ((uint64_t)blockIdx.x * kSortTile >= n) return;
+    if ((uint64_t)bid * kSortTile >= n) return;
     const uint64_t n_valid = cv.enabled ? n - *cv.n_sentinel : n;
     int tot;
     const int dex = block_scan_256((int)totals[tid], s_wsum, &tot);
-    s_base[tid] = (uint32_t)dex + hist[(size_t)tid * nblocks + blockIdx.x];
+    s_base[tid] = (uint32_t)dex + hist[(size_t)tid * nblocks + bid];
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)bid * kSortTile;
     for (int j = 0; j < kSortItems; ++j) {
         s_wcnt[0][tid] = 0;
         s_wcnt[1][tid] = 0;
@@ -691,6 +720,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         __syncthreads();
         s_base[tid] += s_wcnt[0][tid] + s_wcnt[1][tid] + s_wcnt[2][tid] + s_wcnt[3][tid];
     }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+    const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv) {
+    scatter_block(in, out, n_dev, shift, hist, totals, nblocks, cv, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -807,6 +843,209 @@ hipError_t launch_moments(const uint32_t* counts, uint64_t plane, unsigned long 
                           hipStream_t stream) {
     hipLaunchKernelGGL(k_moments, dim3((unsigned)moments_blocks(plane)), dim3(256), 0, stream,
                        counts, plane, part);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused batch: one launch per phase over the streams of a batched push.  A block finds its
+// stream's entry by binary search over the launch's block offsets and runs that stream's block
+// body with its block index inside the stream.
+// ------------------------------------------------------------------------------------------
+// Largest e with start[e] <= b: the entry owning block b (entries owning no block share their
+// offset with the next owner, which has the larger index).
+__device__ __forceinline__ int batch_entry(const int* __restrict__ start, int n, unsigned b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((unsigned)start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Per entry: clear the reservation counters, the window counters and (sparse) the active-list
+// lengths.
+__global__ __launch_bounds__(256) void k_batch_prep(const BatchEntry* __restrict__ entries) {
+    const BatchEntry* e = entries + blockIdx.x;
+    const int tid = threadIdx.x;
+    unsigned long long* reserve = e->chain.reserve;
+    for (int i = tid; i < kArenaStripes * kCounterStride; i += 256) reserve[i] = 0ull;
+    if (tid < 4) e->counters[tid] = 0ull;
+    if (e->sparse)
+        for (int i = tid; i < kActStripes * kCounterStride; i += 256) e->sel.n_active[i] = 0u;
+}
+
+// Selection pass of sparse entries; frame copies and chain resets of the others (kSelectPx
+// pixels per block either way).
+__global__ __launch_bounds__(256) void k_batch_select(const BatchEntry* __restrict__ entries,
+                                                      const int* __restrict__ start, int n) {
+    const int ei = batch_entry(start, n, blockIdx.x);
+    const unsigned lb = blockIdx.x - (unsigned)start[ei];
+    const BatchEntry* e = entries + ei;
+    if (e->sparse) {
+        if (e->vec)
+            select_block<true>(e->sel, lb);
+        else
+            select_block<false>(e->sel, lb);
+        return;
+    }
+    const int64_t base = (int64_t)lb * kSelectPx;
+    const int64_t end = min(base + (int64_t)kSelectPx, e->npix);
+    for (int64_t p = base + threadIdx.x; p < end; p += 256) {
+        e->copy_dst[p] = e->copy_src[p];
+        if (e->copy2_dst) e->copy2_dst[p] = e->copy2_src[p];
+        e->chain.resume[p] = 0;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kSimThreads) void k_batch_chain(const BatchEntry* __restrict__ entries,
+                                                             const int* __restrict__ start,
+                                                             int n) {
+    const int ei = batch_entry(start, n, blockIdx.x);
+    chain_block<MODE>(entries[ei].chain, blockIdx.x - (unsigned)start[ei]);
+}
+
+__global__ void k_batch_fails(const BatchEntry* __restrict__ entries, int n,
+                              unsigned long long* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) out[e] = entries[e].counters[0];
+}
+
+__global__ void k_batch_clamp(const BatchEntry* __restrict__ entries) {
+    const BatchEntry* e = entries + blockIdx.x;
+    if (e->clamp_cap == 0) return;
+    unsigned long long* r = e->chain.reserve + threadIdx.x * kCounterStride;
+    if (*r > e->clamp_cap) *r = e->clamp_cap;
+    if (threadIdx.x == 0) e->counters[0] = 0ull;
+}
+
+__global__ __launch_bounds__(kArenaStripes) void k_batch_gather(
+    const BatchEntry* __restrict__ entries, const int* __restrict__ start, int n) {
+    const int ei = batch_entry(start, n, blockIdx.x);
+    const BatchEntry* e = entries + ei;
+    gather_block(e->chain.arena, e->chain.stripe_cap, e->chain.reserve, e->gathered,
+                 e->counters + 2, blockIdx.x - (unsigned)start[ei]);
+}
+
+__global__ void k_batch_counts(const BatchEntry* __restrict__ entries, int n,
+                               unsigned long long* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) {
+        out[2 * e] = entries[e].counters[1];
+        out[2 * e + 1] = entries[e].counters[2];
+    }
+}
+
+// One pass of every entry's sort: pass p reads the gathered keys (p even) or the ping-pong
+// buffer (p odd) and writes the other one, or the FIFO on the last pass.
+__global__ __launch_bounds__(kSortThreads) void k_batch_hist(const BatchEntry* __restrict__ entries,
+                                                             const int* __restrict__ start, int n,
+                                                             int pass) {
+    const int ei = batch_entry(start, n, blockIdx.x);
+    const BatchEntry* e = entries + ei;
+    const uint64_t* src = (pass & 1) ? e->sort_alt : e->gathered;
+    hist_block(src, e->counters + 2, 8 * pass, e->hist, e->sort_blocks,
+               blockIdx.x - (unsigned)start[ei]);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_batch_rowscan(
+    const BatchEntry* __restrict__ entries) {
+    const BatchEntry* e = entries + blockIdx.x / 256;
+    if (e->sort_blocks == 0) return;
+    rowscan_block(e->hist, e->sort_blocks, e->totals, blockIdx.x % 256);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_batch_scatter(
+    const BatchEntry* __restrict__ entries, const int* __restrict__ start, int n, int pass,
+    int last) {
+    const int ei = batch_entry(start, n, blockIdx.x);
+    const BatchEntry* e = entries + ei;
+    const uint64_t* src = (pass & 1) ? e->sort_alt : e->gathered;
+    uint64_t* dst = last ? e->out : ((pass & 1) ? e->gathered : e->sort_alt);
+    ConvertArgs c = e->cv;
+    if (!last) c.enabled = 0;
+    scatter_block(src, dst, e->counters + 2, 8 * pass, e->hist, e->totals, e->sort_blocks, c,
+                  blockIdx.x - (unsigned)start[ei]);
+}
+
+hipError_t launch_batch_prep(const BatchEntry* e, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_prep, dim3(n), dim3(256), 0, stream, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_select(const BatchEntry* e, const int* start, int n, int blocks,
+                               hipStream_t stream) {
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_select, dim3(blocks), dim3(256), 0, stream, e, start, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_chain(const BatchEntry* e, const int* start, int n, int blocks, int mode,
+                              int max_stash, hipStream_t stream) {
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    const size_t shmem = (size_t)(256 + max_stash * kSimThreads) * sizeof(float);
+    switch (mode) {
+        case kModeReference:
+            hipLaunchKernelGGL(k_batch_chain<kModeReference>, dim3(blocks), dim3(kSimThreads),
+                               shmem, stream, e, start, n);
+            break;
+        case kModeMemoryless:
+            hipLaunchKernelGGL(k_batch_chain<kModeMemoryless>, dim3(blocks), dim3(kSimThreads),
+                               shmem, stream, e, start, n);
+            break;
+        case kModeDifference:
+            hipLaunchKernelGGL(k_batch_chain<kModeDifference>, dim3(blocks), dim3(kSimThreads),
+                               shmem, stream, e, start, n);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_fails(const BatchEntry* e, int n, unsigned long long* out,
+                              hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_fails, dim3((n + 255) / 256), dim3(256), 0, stream, e, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_clamp(const BatchEntry* e, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_clamp, dim3(n), dim3(kArenaStripes), 0, stream, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(const BatchEntry* e, const int* start, int n, int blocks,
+                               hipStream_t stream) {
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_gather, dim3(blocks), dim3(kArenaStripes), 0, stream, e, start,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_counts(const BatchEntry* e, int n, unsigned long long* out,
+                               hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_counts, dim3((n + 255) / 256), dim3(256), 0, stream, e, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sort(const BatchEntry* e, const int* start, int n, int blocks, int passes,
+                             hipStream_t stream) {
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int last = pass == passes - 1;
+        hipLaunchKernelGGL(k_batch_hist, dim3(blocks), dim3(kSortThreads), 0, stream, e, start, n,
+                           pass);
+        hipLaunchKernelGGL(k_batch_rowscan, dim3(256 * n), dim3(kSortThreads), 0, stream, e);
+        hipLaunchKernelGGL(k_batch_scatter, dim3(blocks), dim3(kSortThreads), 0, stream, e, start,
+                           n, pass, last);
+    }
     return hipGetLastError();
 }
 

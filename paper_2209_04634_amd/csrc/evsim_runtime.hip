@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -290,16 +291,19 @@ LkParams lk_from(const sim_lk_params& p) {
 //   check:  wait for the counters; re-run overflowed chains after growing the arena until none
 //           overflows; concatenate the sub-arenas and read the event count asynchronously;
 //   order:  wait for the count; sort into the FIFO; advance the stream's state.
-int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
-               int K) {
+// Host side of a window (no device work): per-interval tables into h_delta / h_tbase, the key
+// layout, and the selection and chain arguments, whose table pointers are d_delta / d_tbase.
+int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
+                int K, float* h_delta, int64_t* h_tbase, const float* d_delta, KeyLayout* lay_out,
+                int* nbits_out, SelectArgs* sa, ChainArgs* a) {
     const int W = s->cfg.width, H = s->cfg.height;
     uint64_t max_delta = 0;
     for (int i = 0; i < K; ++i) {
         const int64_t t0 = i == 0 ? s->t_prev : t_us[i - 1];
         const int64_t d = t_us[i] - t0;
-        s->h_delta[i] = (float)d;
-        s->h_tbase[i] = t0 - s->epoch;
-        const uint64_t dr = (uint64_t)ceil((double)s->h_delta[i]);
+        h_delta[i] = (float)d;
+        h_tbase[i] = t0 - s->epoch;
+        const uint64_t dr = (uint64_t)ceil((double)h_delta[i]);
         max_delta = std::max(max_delta, dr);
     }
     KeyLayout lay;
@@ -309,6 +313,114 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
     lay.ib = K > 1 ? bits_for((uint64_t)(K - 1)) : 0;
     const int nbits = lay.total_bits() + 1;   // + sentinel bit
     if (nbits > 64) return SIM_E_RANGE;
+    *lay_out = lay;
+    *nbits_out = nbits;
+
+    const bool sparse = s->cfg.method == SIM_SPARSE;
+    sa->prev = s->d_prev[s->cur];
+    sa->frames = frames;
+    sa->fstride = s->npix;
+    sa->lut = s->d_lut;
+    sa->prev_out = s->d_prev[1 - s->cur];
+    sa->mask = s->d_mask;
+    sa->act_px = s->d_act;
+    sa->resume = s->d_resume;
+    sa->n_active = s->d_nact;
+    sa->stats = s->d_stats;
+    sa->npix = (int)s->npix;
+    sa->K = K;
+    sa->act_cap = s->act_cap;
+    sa->m = s->m;
+
+    const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
+    a->prev = s->d_prev[s->cur];
+    a->frames = frames;
+    a->fstride = s->npix;
+    a->flows = estimate ? s->d_lkflow : flows;
+    a->flstride = 2 * s->npix;
+    a->lut = s->d_lut;
+    a->delta = d_delta;
+    a->lref = s->d_lref;
+    a->mask = sparse ? s->d_mask : nullptr;
+    a->act_px = sparse ? s->d_act : nullptr;
+    a->n_active = sparse ? s->d_nact : nullptr;
+    a->act_cap = s->act_cap;
+    a->resume = s->d_resume;
+    a->reserve = s->d_reserve;
+    a->fails = s->d_counters;          // [0] failed reservations, [1] sentinels, [2] gathered
+    a->W = W;
+    a->H = H;
+    a->S = s->S;
+    a->K = K;
+    a->npix = (int)s->npix;
+    a->cpos = s->cfg.c_pos;
+    a->cneg = s->cfg.c_neg;
+    a->lay = lay;
+    if (s->cfg.method == SIM_DIFFERENCE)
+        a->mode = kModeDifference;
+    else
+        a->mode = s->cfg.thresh_mode == SIM_THRESH_MEMORYLESS ? kModeMemoryless : kModeReference;
+    a->prev2 = s->d_prev2[s->cur];
+    a->first_emit = s->n_int == 0 ? 1 : 0;   // difference method: three frames are needed
+    a->arena = s->d_arena;
+    a->stripe_cap = s->stripe_cap;
+    return SIM_OK;
+}
+
+int chain_slots(const sim_stream* s) {
+    return s->cfg.method == SIM_SPARSE ? kActStripes * s->act_cap : (int)s->npix;
+}
+
+// Estimated flow (SIM_FLOW_LK): buffers for a window of K intervals.
+int ensure_lk_buffers(sim_stream* s, int K) {
+    const PyrLayout pl = pyr_layout(s->cfg.width, s->cfg.height, s->lk.levels);
+    uint64_t cap = s->pyr_cap;
+    int rc = grow(s, &s->d_pyr, &cap, (uint64_t)(K + 1) * pl.total, 0);
+    s->pyr_cap = cap;
+    if (!rc) {
+        cap = s->lkflow_cap;
+        rc = grow(s, &s->d_lkflow, &cap, (uint64_t)K * 2 * (uint64_t)s->npix, 0);
+        s->lkflow_cap = cap;
+    }
+    return rc;
+}
+
+// Flow of every selected pixel-interval of the window, from the pyramids of the previous frame
+// and the window's frames, into the layout of supplied flows (after the selection pass).
+hipError_t launch_lk(sim_stream* s, const uint8_t* frames, int K, hipStream_t stream) {
+    const bool sparse = s->cfg.method == SIM_SPARSE;
+    const PyrLayout pl = pyr_layout(s->cfg.width, s->cfg.height, s->lk.levels);
+    hipError_t e = launch_pyramids(s->d_prev[s->cur], frames, s->npix, K + 1, pl, s->d_pyr, stream);
+    if (e != hipSuccess) return e;
+    LkWindowArgs la;
+    la.pyr = s->d_pyr;
+    la.lay = pl;
+    la.P = s->lk;
+    la.mask = sparse ? s->d_mask : nullptr;
+    la.act_px = sparse ? s->d_act : nullptr;
+    la.n_active = sparse ? s->d_nact : nullptr;
+    la.act_cap = s->act_cap;
+    la.npix = (int)s->npix;
+    la.W = s->cfg.width;
+    la.K = K;
+    la.flow = s->d_lkflow;
+    return launch_lk_window(la, chain_slots(s), stream);
+}
+
+int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
+               int K) {
+    const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
+    if (estimate) {
+        int rc = ensure_lk_buffers(s, K);
+        if (rc) return rc;
+    }
+    KeyLayout lay;
+    int nbits = 0;
+    SelectArgs sa;
+    ChainArgs a;
+    int rc = plan_window(s, frames, flows, t_us, K, s->h_delta, s->h_tbase, s->d_delta, &lay,
+                         &nbits, &sa, &a);
+    if (rc) return rc;
 
     HIP_TRY(s, hipMemcpyAsync(s->d_delta, s->h_delta, K * sizeof(float), hipMemcpyHostToDevice,
                               s->stream));
@@ -319,31 +431,15 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
                               (size_t)kArenaStripes * kCounterStride * sizeof(unsigned long long),
                               s->stream));
     const bool sparse = s->cfg.method == SIM_SPARSE;
-    uint8_t* prev_out = s->d_prev[1 - s->cur];
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[0], s->stream));
     if (sparse) {
         HIP_TRY(s, hipMemsetAsync(s->d_nact, 0,
                                   (size_t)kActStripes * kCounterStride * sizeof(unsigned int),
                                   s->stream));
-        SelectArgs sa;
-        sa.prev = s->d_prev[s->cur];
-        sa.frames = frames;
-        sa.fstride = s->npix;
-        sa.lut = s->d_lut;
-        sa.prev_out = prev_out;
-        sa.mask = s->d_mask;
-        sa.act_px = s->d_act;
-        sa.resume = s->d_resume;
-        sa.n_active = s->d_nact;
-        sa.stats = s->d_stats;
-        sa.npix = (int)s->npix;
-        sa.K = K;
-        sa.act_cap = s->act_cap;
-        sa.m = s->m;
         HIP_TRY(s, launch_select(sa, s->stream));
     } else {
         HIP_TRY(s, hipMemsetAsync(s->d_resume, 0, (size_t)s->npix * sizeof(int), s->stream));
-        HIP_TRY(s, launch_copy_u8(frames + (size_t)(K - 1) * s->npix, prev_out, s->npix,
+        HIP_TRY(s, launch_copy_u8(frames + (size_t)(K - 1) * s->npix, sa.prev_out, s->npix,
                                   s->stream));
         if (s->cfg.method == SIM_DIFFERENCE) {
             // the frame before the window's last one becomes the next window's second-to-last
@@ -351,80 +447,16 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
             HIP_TRY(s, launch_copy_u8(src, s->d_prev2[1 - s->cur], s->npix, s->stream));
         }
     }
-    const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
-    if (estimate) {
-        // flow of every selected pixel-interval, from the pyramids of the previous frame and the
-        // window's frames, into the layout of supplied flows
-        const PyrLayout pl = pyr_layout(W, H, s->lk.levels);
-        uint64_t cap = s->pyr_cap;
-        int rc = grow(s, &s->d_pyr, &cap, (uint64_t)(K + 1) * pl.total, 0);
-        s->pyr_cap = cap;
-        if (!rc) {
-            cap = s->lkflow_cap;
-            rc = grow(s, &s->d_lkflow, &cap, (uint64_t)K * 2 * (uint64_t)s->npix, 0);
-            s->lkflow_cap = cap;
-        }
-        if (rc) return rc;
-        HIP_TRY(s, launch_pyramids(s->d_prev[s->cur], frames, s->npix, K + 1, pl, s->d_pyr,
-                                   s->stream));
-        LkWindowArgs la;
-        la.pyr = s->d_pyr;
-        la.lay = pl;
-        la.P = s->lk;
-        la.mask = sparse ? s->d_mask : nullptr;
-        la.act_px = sparse ? s->d_act : nullptr;
-        la.n_active = sparse ? s->d_nact : nullptr;
-        la.act_cap = s->act_cap;
-        la.npix = (int)s->npix;
-        la.W = W;
-        la.K = K;
-        la.flow = s->d_lkflow;
-        HIP_TRY(s, launch_lk_window(la, sparse ? kActStripes * s->act_cap : (int)s->npix,
-                                    s->stream));
-        flows = s->d_lkflow;
-    }
+    if (estimate) HIP_TRY(s, launch_lk(s, frames, K, s->stream));
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
 
-    ChainArgs a;
-    a.prev = s->d_prev[s->cur];
-    a.frames = frames;
-    a.fstride = s->npix;
-    a.flows = flows;
-    a.flstride = 2 * s->npix;
-    a.lut = s->d_lut;
-    a.delta = s->d_delta;
-    a.lref = s->d_lref;
-    a.mask = sparse ? s->d_mask : nullptr;
-    a.act_px = sparse ? s->d_act : nullptr;
-    a.n_active = sparse ? s->d_nact : nullptr;
-    a.act_cap = s->act_cap;
-    a.resume = s->d_resume;
-    a.reserve = s->d_reserve;
-    a.fails = s->d_counters;          // [0] failed reservations, [1] sentinels, [2] gathered
-    a.W = W;
-    a.H = H;
-    a.S = s->S;
-    a.K = K;
-    a.npix = (int)s->npix;
-    a.cpos = s->cfg.c_pos;
-    a.cneg = s->cfg.c_neg;
-    a.lay = lay;
-    if (s->cfg.method == SIM_DIFFERENCE)
-        a.mode = kModeDifference;
-    else
-        a.mode = s->cfg.thresh_mode == SIM_THRESH_MEMORYLESS ? kModeMemoryless : kModeReference;
-    a.prev2 = s->d_prev2[s->cur];
-    a.first_emit = s->n_int == 0 ? 1 : 0;   // difference method: three frames are needed
-    const int max_slots = sparse ? kActStripes * s->act_cap : (int)s->npix;
-
+    const int max_slots = chain_slots(s);
     s->job.active = true;
     s->job.K = K;
     s->job.nbits = nbits;
     s->job.max_slots = max_slots;
     s->job.lay = lay;
     s->job.t_last = t_us[K - 1];
-    a.arena = s->d_arena;
-    a.stripe_cap = s->stripe_cap;
     HIP_TRY(s, launch_chain(a, max_slots, s->stream));
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
@@ -610,6 +642,285 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
     if (!rc) rc = win_order(s, n_new);
     if (rc) s->job.active = false;
     return rc;
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused batched push: the streams of a sim_push_batch call share one launch per phase (clear,
+// selection or frame copies, chains per thresholding mode, overflow readback, gather, counts,
+// and every pass of the sort), on one library stream, with one host wait per phase instead of
+// one per stream.  Per stream the kernels run the same block bodies on the same data as its
+// own launches, so every stream's result is that of the stream pushed alone.
+// ------------------------------------------------------------------------------------------
+struct BatchCtx {
+    std::mutex mu;                   // one fused batch at a time (shared buffers below)
+    hipStream_t stream = nullptr;
+    char* h_blob = nullptr;          // pinned: entries, block offsets, per-interval tables
+    size_t h_cap = 0;
+    char* d_blob = nullptr;
+    size_t d_cap = 0;
+    unsigned long long* h_out = nullptr;   // pinned readback of per-entry counters
+    unsigned long long* d_out = nullptr;
+    size_t out_cap = 0;
+};
+
+BatchCtx& batch_ctx() {
+    static BatchCtx* ctx = new BatchCtx();   // lives until the process ends
+    return *ctx;
+}
+
+size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
+
+// Grows the context's buffers; returns false on allocation failure.
+bool batch_reserve(BatchCtx& c, size_t blob, size_t outs) {
+    if (!c.stream && hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
+        return false;
+    if (blob > c.h_cap || blob > c.d_cap) {
+        if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
+        if (c.h_blob) (void)hipHostFree(c.h_blob);
+        if (c.d_blob) (void)hipFree(c.d_blob);
+        c.h_blob = nullptr;
+        c.d_blob = nullptr;
+        c.h_cap = c.d_cap = 0;
+        const size_t cap = std::max(blob, (size_t)1 << 16);
+        if (hipHostMalloc((void**)&c.h_blob, cap, 0) != hipSuccess) return false;
+        if (hipMalloc((void**)&c.d_blob, cap) != hipSuccess) return false;
+        c.h_cap = c.d_cap = cap;
+    }
+    if (outs > c.out_cap) {
+        if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
+        if (c.h_out) (void)hipHostFree(c.h_out);
+        if (c.d_out) (void)hipFree(c.d_out);
+        c.h_out = nullptr;
+        c.d_out = nullptr;
+        c.out_cap = 0;
+        const size_t cap = std::max(outs, (size_t)256);
+        if (hipHostMalloc((void**)&c.h_out, cap * sizeof(unsigned long long), 0) != hipSuccess)
+            return false;
+        if (hipMalloc((void**)&c.d_out, cap * sizeof(unsigned long long)) != hipSuccess)
+            return false;
+        c.out_cap = cap;
+    }
+    return true;
+}
+
+struct FusedItem {
+    sim_stream* s;
+    sim_frames* it;
+    const uint8_t* frames;           // the window's frames on the device
+    const float* flows;              // its supplied flows (or null)
+    const int64_t* t_us;
+    int K;
+    KeyLayout lay;
+    int nbits;
+    size_t tab_off;                  // offset of its tables in the blob
+    uint64_t n_valid;
+};
+
+// Block offsets of one launch: start[e] = blocks of entries before e; returns the total.
+int fill_starts(int* start, const std::vector<int>& blocks) {
+    int acc = 0;
+    for (size_t e = 0; e < blocks.size(); ++e) {
+        start[e] = acc;
+        acc += blocks[e];
+    }
+    start[blocks.size()] = acc;
+    return acc;
+}
+
+// One window chunk of a batch: the streams in `items` (each with K >= 1 intervals).  Returns
+// SIM_OK or the status every participating item gets.
+int fused_window(std::vector<FusedItem>& items) {
+    BatchCtx& c = batch_ctx();
+    const int n = (int)items.size();
+    // blob: entries | 8 offset arrays of n + 1 ints | per-item delta (K floats) + tbase (K int64)
+    const size_t ent_bytes = align8((size_t)n * sizeof(BatchEntry));
+    const size_t starts_bytes = align8((size_t)8 * (n + 1) * sizeof(int));
+    size_t tab = ent_bytes + starts_bytes;
+    for (FusedItem& f : items) {
+        f.tab_off = tab;
+        tab += align8((size_t)f.K * sizeof(float)) + (size_t)f.K * sizeof(int64_t);
+    }
+    if (!batch_reserve(c, tab, 2 * (size_t)n)) {
+        (void)hipGetLastError();
+        return SIM_E_NOMEM;
+    }
+    BatchEntry* he = (BatchEntry*)c.h_blob;
+    BatchEntry* de = (BatchEntry*)c.d_blob;
+    int* hs = (int*)(c.h_blob + ent_bytes);
+    int* ds = (int*)(c.d_blob + ent_bytes);
+    auto hstart = [&](int k) { return hs + (size_t)k * (n + 1); };
+    auto dstart = [&](int k) { return ds + (size_t)k * (n + 1); };
+    enum { kSel = 0, kChain0 = 1, kGather = 4, kSort = 5 };
+
+    // every stream's staged inputs and earlier work are complete before the batch stream reads
+    for (FusedItem& f : items)
+        if (hipStreamSynchronize(f.s->stream) != hipSuccess) return SIM_E_HIP;
+
+    std::vector<int> sel_blocks(n), chain_blocks[3], blocks(n);
+    for (int m = 0; m < 3; ++m) chain_blocks[m].assign(n, 0);
+    int max_stash[3] = {0, 0, 0};
+    for (int e = 0; e < n; ++e) {
+        FusedItem& f = items[e];
+        sim_stream* s = f.s;
+        if (s->cfg.flow_source == SIM_FLOW_LK && s->S > 1) {
+            int rc = ensure_lk_buffers(s, f.K);
+            if (rc) return rc;
+        }
+        float* h_delta = (float*)(c.h_blob + f.tab_off);
+        int64_t* h_tbase = (int64_t*)(c.h_blob + f.tab_off + align8((size_t)f.K * sizeof(float)));
+        const float* d_delta = (const float*)(c.d_blob + f.tab_off);
+        const int64_t* d_tbase =
+            (const int64_t*)(c.d_blob + f.tab_off + align8((size_t)f.K * sizeof(float)));
+        BatchEntry& b = he[e];
+        memset(&b, 0, sizeof(b));
+        int rc = plan_window(s, f.frames, f.flows, f.t_us, f.K, h_delta, h_tbase,
+                             d_delta, &f.lay, &f.nbits, &b.sel, &b.chain);
+        if (rc) return rc;
+        b.sparse = s->cfg.method == SIM_SPARSE ? 1 : 0;
+        b.vec = (b.sel.fstride % 4) == 0 && ((uintptr_t)b.sel.frames % 4) == 0 &&
+                ((uintptr_t)b.sel.prev % 4) == 0 && ((uintptr_t)b.sel.prev_out % 4) == 0;
+        b.copy_src = f.frames + (size_t)(f.K - 1) * s->npix;
+        b.copy_dst = b.sel.prev_out;
+        if (s->cfg.method == SIM_DIFFERENCE) {
+            b.copy2_src = f.K >= 2 ? f.frames + (size_t)(f.K - 2) * s->npix : s->d_prev[s->cur];
+            b.copy2_dst = s->d_prev2[1 - s->cur];
+        }
+        b.npix = s->npix;
+        b.counters = s->d_counters;
+        b.cv.tbase = d_tbase;
+        sel_blocks[e] = (int)((s->npix + kSelectPx - 1) / kSelectPx);
+        const int m = b.chain.mode;
+        chain_blocks[m][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
+        max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
+    }
+    const int sel_total = fill_starts(hstart(kSel), sel_blocks);
+    int chain_total[3];
+    for (int m = 0; m < 3; ++m) chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
+    hipStream_t st = c.stream;
+    const size_t head = ent_bytes + starts_bytes;
+#define BATCH_TRY(expr)                       \
+    do {                                      \
+        if ((expr) != hipSuccess) {           \
+            (void)hipGetLastError();          \
+            return SIM_E_HIP;                 \
+        }                                     \
+    } while (0)
+    BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, tab, hipMemcpyHostToDevice, st));
+    BATCH_TRY(launch_batch_prep(de, n, st));
+    BATCH_TRY(launch_batch_select(de, dstart(kSel), n, sel_total, st));
+    for (FusedItem& f : items)
+        if (f.s->cfg.flow_source == SIM_FLOW_LK && f.s->S > 1)
+            BATCH_TRY(launch_lk(f.s, f.frames, f.K, st));
+    for (int m = 0; m < 3; ++m)
+        BATCH_TRY(launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m, max_stash[m],
+                                     st));
+    BATCH_TRY(launch_batch_fails(de, n, c.d_out, st));
+    BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, (size_t)n * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, st));
+    BATCH_TRY(hipStreamSynchronize(st));
+
+    // chains that ran out of event-buffer space: grow those buffers, re-run only them
+    for (;;) {
+        bool any = false;
+        for (int m = 0; m < 3; ++m) std::fill(chain_blocks[m].begin(), chain_blocks[m].end(), 0);
+        for (int e = 0; e < n; ++e) {
+            he[e].clamp_cap = 0;
+            if (c.h_out[e] == 0) continue;
+            any = true;
+            sim_stream* s = items[e].s;
+            const uint64_t old = s->stripe_cap;
+            int rc = grow_arena(s, 2 * old);
+            if (rc) {
+                s->poisoned = true;   // finished chains have advanced their levels
+                return rc;
+            }
+            s->stats.retries++;
+            he[e].clamp_cap = old;
+            he[e].chain.arena = s->d_arena;
+            he[e].chain.stripe_cap = s->stripe_cap;
+            chain_blocks[he[e].chain.mode][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
+        }
+        if (!any) break;
+        for (int m = 0; m < 3; ++m)
+            chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
+        BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
+        BATCH_TRY(launch_batch_clamp(de, n, st));
+        for (int m = 0; m < 3; ++m)
+            BATCH_TRY(launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m,
+                                         max_stash[m], st));
+        BATCH_TRY(launch_batch_fails(de, n, c.d_out, st));
+        BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, (size_t)n * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, st));
+        BATCH_TRY(hipStreamSynchronize(st));
+    }
+
+    // every chain has finished: concatenate each stream's sub-arenas
+    for (int e = 0; e < n; ++e) {
+        sim_stream* s = items[e].s;
+        int rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
+        if (rc) return rc;
+        he[e].clamp_cap = 0;
+        he[e].gathered = s->d_alt;
+        he[e].sort_alt = s->d_alt2;
+        blocks[e] = (int)(std::max<uint64_t>(1, (s->stripe_cap + kSortTile - 1) / kSortTile) *
+                          kArenaStripes);
+    }
+    const int gather_total = fill_starts(hstart(kGather), blocks);
+    BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
+    BATCH_TRY(launch_batch_gather(de, dstart(kGather), n, gather_total, st));
+    BATCH_TRY(launch_batch_counts(de, n, c.d_out, st));
+    BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, 2 * (size_t)n * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, st));
+    BATCH_TRY(hipStreamSynchronize(st));
+
+    // order: every stream's keys sorted into its FIFO
+    int passes = 0;
+    for (int e = 0; e < n; ++e) {
+        FusedItem& f = items[e];
+        sim_stream* s = f.s;
+        const uint64_t n_total = c.h_out[2 * e + 1];
+        f.n_valid = n_total - c.h_out[2 * e];
+        blocks[e] = 0;
+        if (f.n_valid == 0) continue;
+        int rc = ensure_sort_scratch(s, n_total);
+        if (!rc && s->fifo_tail + f.n_valid > s->fifo_cap)
+            rc = grow(s, &s->d_fifo, &s->fifo_cap,
+                      std::max<uint64_t>(s->fifo_tail + f.n_valid, 2 * s->fifo_cap),
+                      s->fifo_tail);
+        if (rc) return rc;
+        BatchEntry& b = he[e];
+        b.hist = s->d_hist;
+        b.totals = s->d_totals;
+        b.out = s->d_fifo + s->fifo_tail;
+        b.cv.enabled = 1;
+        b.cv.n_sentinel = s->d_counters + 1;
+        b.cv.K = f.K;
+        b.cv.lay = f.lay;
+        b.sort_blocks = (int)std::max<uint64_t>(1, (n_total + kSortTile - 1) / kSortTile);
+        blocks[e] = b.sort_blocks;
+        passes = std::max(passes, (f.nbits + 7) / 8);
+    }
+    const int sort_total = fill_starts(hstart(kSort), blocks);
+    if (sort_total > 0) {
+        // entries needing fewer passes get more: their keys are zero (sentinels all ones) in
+        // the extra digits, which a stable pass leaves in place
+        BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
+        BATCH_TRY(launch_batch_sort(de, dstart(kSort), n, sort_total, passes, st));
+        BATCH_TRY(hipStreamSynchronize(st));
+    }
+#undef BATCH_TRY
+    for (FusedItem& f : items) {
+        sim_stream* s = f.s;
+        s->fifo_tail += f.n_valid;
+        s->cur = 1 - s->cur;
+        s->t_prev = f.t_us[f.K - 1];
+        s->n_int += (uint64_t)f.K;
+        s->stats.intervals += (uint64_t)f.K;
+        s->stats.frames += (uint64_t)f.K;
+        s->stats.events += f.n_valid;
+        f.it->n_new_events += f.n_valid;
+    }
+    return SIM_OK;
 }
 
 }  // namespace
@@ -823,27 +1134,34 @@ int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
         if (it.status && !first_err) first_err = it.status;
         if (!it.status) max_int = std::max(max_int, st[i].n_int);
     }
-    // window by window, each phase across every stream before the next phase: the launches of
-    // all streams are queued on their HIP streams before the host waits on any of them
+    // window by window: every stream's window of a chunk runs in the fused launches
+    std::lock_guard<std::mutex> lock(batch_ctx().mu);
     for (int j = 0; j < max_int; j += kMaxWindow) {
+        std::vector<FusedItem> fi;
         for (int i = 0; i < n; ++i) {
             sim_frames& it = items[i];
             if (it.status || j >= st[i].n_int) continue;
-            const int K = std::min(kMaxWindow, st[i].n_int - j);
-            it.status = win_launch(streams[i], window_frames(streams[i], st[i], j),
-                                   window_flows(streams[i], st[i], j), it.t_us + st[i].first + j,
-                                   K);
+            FusedItem f;
+            memset(&f, 0, sizeof(f));
+            f.s = streams[i];
+            f.it = &it;
+            f.K = std::min(kMaxWindow, st[i].n_int - j);
+            f.frames = window_frames(streams[i], st[i], j);
+            f.flows = window_flows(streams[i], st[i], j);
+            f.t_us = it.t_us + st[i].first + j;
+            fi.push_back(f);
         }
-        for (int i = 0; i < n; ++i) {
-            sim_frames& it = items[i];
-            if (it.status || !streams[i]->job.active) continue;
-            it.status = win_check(streams[i]);
-        }
-        for (int i = 0; i < n; ++i) {
-            sim_frames& it = items[i];
-            if (!streams[i]->job.active) continue;
-            if (!it.status) it.status = win_order(streams[i], &it.n_new_events);
-            streams[i]->job.active = false;
+        if (fi.empty()) continue;
+        const int rc = fused_window(fi);
+        if (rc) {
+            // device state of the chunk's streams may have advanced: they cannot continue
+            for (FusedItem& f : fi) {
+                f.it->status = rc;
+                f.s->poisoned = true;
+                if (!f.s->last_error[0])
+                    snprintf(f.s->last_error, sizeof(f.s->last_error),
+                             "batched push failed (%s)", sim_strerror(rc));
+            }
         }
     }
     for (int i = 0; i < n; ++i)
