@@ -1,10 +1,14 @@
 // Host runtime of the event simulator: the C ABI declared in include/sim.h.
 //
 // Per stream the device holds the 256-entry transform table, the per-pixel reference levels
-// (updated in place), two previous-frame buffers (ping-pong), an unsorted event arena with its
-// sort scratch, and a FIFO of sorted packed keys awaiting drain.  A push of K frames is one
-// simulation launch over all tiles, a read of four counters, an optional re-run of the tiles that
-// ran out of arena space (after growing it), and one sort whose last pass appends to the FIFO.
+// (updated in place), two previous-frame buffers (ping-pong; two more for the difference
+// method), the sparse method's selection masks and active list, an event arena of 256 striped
+// sub-arenas, sort buffers, and a FIFO of sorted packed keys awaiting drain.  A push runs in
+// windows of up to 128 intervals: the selection pass (or the frame copies), flow estimation when
+// it is on, one chain launch, a read of the overflow counters, re-runs of the chains that ran out
+// of arena space after growing it, the gather of the sub-arenas, and the sort whose last pass
+// appends to the FIFO.  A batched push runs each phase of every stream's window in one fused
+// launch (fused_window).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -54,7 +58,6 @@ struct sim_stream {
     bool poisoned = false;
 
     int64_t npix = 0;
-    int ntiles = 0;
     float* d_lut = nullptr;
     float* d_lref = nullptr;
     uint8_t* d_prev[2] = {nullptr, nullptr};
@@ -125,7 +128,6 @@ struct sim_stream {
         KeyLayout lay;
         ChainArgs a;
         int64_t t_last = 0;
-        uint64_t n_total = 0, n_valid = 0;
     } job;
 
     // kernel timing (sim_set_kernel_timing)
@@ -994,7 +996,6 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     s->S = cfg->method == SIM_BASIC ? 1 : cfg->n_interp + 1;
     s->m = cfg->mask_threshold < 0.0f ? std::min(cfg->c_pos, cfg->c_neg) : cfg->mask_threshold;
     s->npix = (int64_t)cfg->width * cfg->height;
-    s->ntiles = (int)((s->npix + kSimThreads - 1) / kSimThreads);
     {
         sim_lk_params d;
         sim_lk_params_init(&d);
