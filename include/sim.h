@@ -45,9 +45,10 @@
  *
  * Conventions for every call: the return value is SIM_OK (0) or a negative status.  No C++
  * exception crosses the ABI.  SIM_E_INVAL, SIM_E_ORDER, SIM_E_RANGE and SIM_E_NOMEM leave the
- * stream exactly as it was before the call, with one exception: when the device event buffer
- * has to grow in the middle of a push and that allocation fails, part of the image has already
- * advanced, so the push returns SIM_E_NOMEM and poisons the handle.  SIM_E_HIP poisons the
+ * stream exactly as it was before the call, with one exception: when a device buffer sized by
+ * the number of events (the event arena, the sort buffers, the event FIFO) has to grow in the
+ * middle of a push and that allocation fails, part of the image has already advanced, so the
+ * push returns SIM_E_NOMEM and poisons the handle.  SIM_E_HIP poisons the
  * handle: every later call except sim_destroy, sim_get_stats and sim_strerror returns
  * SIM_E_POISONED.  A handle is not thread-safe; distinct handles are independent.
  */
@@ -189,12 +190,15 @@ typedef struct sim_frames {
 } sim_frames;
 
 /* Pushes frames to n distinct streams at once, with exactly the result of n sim_push_frames
- * calls.  Every stream's selection and chain kernels are queued on its own HIP stream before the
- * host waits on any of them, and so are the orderings, so the streams' work overlaps on the GPU
- * (streams of mixed resolution and method may be combined).  Validation of every entry (and a
- * handle listed twice, SIM_E_INVAL) happens before any work is queued; on a validation error
- * nothing changes.  Errors after that are reported per entry in `status` and affect only that
- * stream.  Returns SIM_OK or the first error. */
+ * calls.  Streams of any resolution, method, thresholding mode and flow source may be combined:
+ * each window of all streams runs as one launch per phase (clearing, selection, chains, overflow
+ * re-runs, gather, every sort pass) on a library stream, with one host wait per phase.  The
+ * streams' earlier work is completed first; their events are ordered when the call returns.
+ * Validation of every entry (and a handle listed twice, SIM_E_INVAL) happens before any work is
+ * queued; on a validation error nothing changes.  Staging and buffer reservation follow per
+ * entry (an entry failing there stays untouched while the others proceed).  A failure inside the
+ * fused launches poisons every stream of that window.  Errors are reported per entry in `status`;
+ * returns SIM_OK or the first error.  One batched push runs at a time per process. */
 int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n);
 
 /* Number of events produced and not yet drained. */

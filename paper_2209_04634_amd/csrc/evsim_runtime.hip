@@ -147,6 +147,15 @@ int hip_fail_at(sim_stream* s, hipError_t e, const char* what, int line) {
 
 int hip_fail(sim_stream* s) { return hip_fail_at(s, hipGetLastError(), "HIP call", 0); }
 
+// A failure after a window's chains have run: the reference levels and the previous frame have
+// advanced on the device while the host state has not, so the stream cannot continue.
+int fail_mid_push(sim_stream* s, int rc, const char* what) {
+    s->poisoned = true;
+    snprintf(s->last_error, sizeof(s->last_error), "%s failed in the middle of a push (%s)",
+             what, rc == SIM_E_NOMEM ? "out of memory" : "error");
+    return rc;
+}
+
 #define HIP_TRY(s, expr)                                                 \
     do {                                                                 \
         hipError_t e_ = (expr);                                          \
@@ -490,12 +499,8 @@ int win_check(sim_stream* s) {
         // unfinished pixel chains.  Nothing else reads or writes the arena in between.
         const uint64_t old = s->stripe_cap;
         int rc = grow_arena(s, 2 * old);
-        if (rc) {
-            // Finished chains have already advanced their reference levels: the stream can no
-            // longer be rolled back, so an allocation failure here poisons the handle.
-            s->poisoned = true;
-            return rc;
-        }
+        // finished chains have already advanced their reference levels: no roll-back
+        if (rc) return fail_mid_push(s, rc, "event arena growth");
         HIP_TRY(s, launch_clamp(s->d_reserve, old, s->stream));
         HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, sizeof(unsigned long long), s->stream));
         s->stats.retries++;
@@ -510,7 +515,7 @@ int win_check(sim_stream* s) {
     // every chain has finished: concatenate the sub-arenas, then order the events
     {
         int rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
-        if (rc) return rc;
+        if (rc) return fail_mid_push(s, rc, "sort buffer growth");
     }
     HIP_TRY(s, launch_gather(s->d_arena, s->stripe_cap, s->d_reserve, s->d_alt,
                              s->d_counters + 2, s->stream));
@@ -529,7 +534,7 @@ int win_order(sim_stream* s, uint64_t* n_new) {
             rc = grow(s, &s->d_fifo, &s->fifo_cap,
                       std::max<uint64_t>(s->fifo_tail + n_valid, 2 * s->fifo_cap),
                       s->fifo_tail);
-        if (rc) return rc;
+        if (rc) return fail_mid_push(s, rc, "event buffer growth");
         ConvertArgs cv;
         cv.enabled = 1;
         cv.n_sentinel = s->d_counters + 1;
@@ -615,6 +620,16 @@ int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const flo
                                       s->stream));
             out->flows = s->d_stage_flows;
         }
+    }
+    if (out->n_int > 0) {
+        // every buffer whose size is known now, before anything changes: a failure here leaves
+        // the stream as it was (later growth with the event count fails mid-push and poisons)
+        int rc = SIM_OK;
+        if (s->cfg.flow_source == SIM_FLOW_LK && s->S > 1)
+            rc = ensure_lk_buffers(s, std::min(kMaxWindow, out->n_int));
+        if (!rc) rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
+        if (!rc) rc = ensure_sort_scratch(s, kArenaStripes * s->stripe_cap);
+        if (rc) return rc;
     }
     if (!s->started) {
         HIP_TRY(s, launch_init(out->frames, s->d_lut, s->d_lref, s->d_prev[s->cur], s->npix,
@@ -832,10 +847,7 @@ int fused_window(std::vector<FusedItem>& items) {
             sim_stream* s = items[e].s;
             const uint64_t old = s->stripe_cap;
             int rc = grow_arena(s, 2 * old);
-            if (rc) {
-                s->poisoned = true;   // finished chains have advanced their levels
-                return rc;
-            }
+            if (rc) return fail_mid_push(s, rc, "event arena growth");
             s->stats.retries++;
             he[e].clamp_cap = old;
             he[e].chain.arena = s->d_arena;
@@ -1227,7 +1239,9 @@ int sim_drain_events(sim_stream* s, sim_event* dst, uint64_t max_events, uint64_
 }
 
 int sim_epoch(sim_stream* s, int64_t* epoch) {
-    if (!s || !epoch || !s->started) return SIM_E_INVAL;
+    if (!s || !epoch) return SIM_E_INVAL;
+    if (s->poisoned) return SIM_E_POISONED;
+    if (!s->started) return SIM_E_INVAL;
     *epoch = s->epoch;
     return SIM_OK;
 }

@@ -306,10 +306,24 @@ struct emu_event_t {
     std::chrono::steady_clock::time_point t;
 };
 
+// Failure injection for tests of error handling: once armed with emu_fail_alloc_after(k), the
+// device allocation after k more successful ones fails (then the countdown is off again).
+static long g_fail_countdown = -1;
+static long g_allocs = 0;
+extern "C" void emu_fail_alloc_after(long k) { g_fail_countdown = k; }
+extern "C" long emu_alloc_count(void) { return g_allocs; }
+
 hipError_t emu_hipMalloc(void** p, size_t n) {
+    if (g_fail_countdown == 0) {
+        g_fail_countdown = -1;
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    if (g_fail_countdown > 0) --g_fail_countdown;
     *p = malloc(n ? n : 1);
     if (!*p) return hipErrorOutOfMemory;
     memset(*p, 0xA5, n);   // device memory starts as garbage
+    ++g_allocs;
     return hipSuccess;
 }
 hipError_t emu_hipFree(void* p) {
