@@ -200,6 +200,7 @@ def test_device_drain_into_torch_tensor():
     v = synth.blob_video(synth.basic_240x180())
     s = sim.Stream(240, 180, method="basic", hip_stream="torch")
     fr = torch.from_numpy(v.frames).cuda()
+    torch.cuda.synchronize()            # the copy runs on torch's stream, the library on its own
     s.push_frames(fr, None, v.t_us)
     out = torch.empty(s.pending(), dtype=torch.int64, device="cuda")
     n = s.drain_keys(out=out)
