@@ -24,6 +24,8 @@
  *     (Sec. III-A threshold equations, taken literally).
  *   - Difference-frame interpolation: from three consecutive frames, two difference frames; the
  *     flow between them interpolates further difference frames, each thresholded (Sec. III-C).
+ *   - Flow at the selected pixels estimated with Lucas-Kanade (Sec. III-B, IV-A), here the
+ *     published pyramidal form of Lucas and Kanade's window least-squares fit (oracle_lk_flow).
  *
  * Readings where the paper is silent:
  *   log transform ln(v/255 + eps) via a 256-entry table; interpolation of the transformed frames;
@@ -46,10 +48,16 @@
  * logarithm, zero-event invariants, the closed-form per-pixel count floor(|dL|/C) of the basic
  * method, endpoint exactness (dense with S = 1 equals basic), zero-flow and translating-edge
  * closed forms, time reversal, reference bookkeeping, hand-worked fixtures under tests/golden/ and
- * an independent float64 brute-force solver on 8x8 inputs.  The exact interpolation formula has
+ * an independent float64 brute-force solver on 8x8 inputs; for the memoryless mode and the
+ * difference method by hand-worked fixtures, the float64 solver, a translating-edge closed form
+ * and invariants; for the accumulated frame and the event rate by hand-worked examples and exact
+ * rational arithmetic; for Lucas-Kanade by recovered known translations, rejection of flat and
+ * edge windows and an independent float64 implementation (tests/lk64.py).  Planted one-token
+ * mistakes each fail a pin (tests/test_oracle_mutants*.py).  The exact interpolation formula has
  * no anchor in the paper beyond those properties ("parity unpinned" against the paper itself for
  * that formula; pinned through endpoint exactness, the zero-flow and translating-edge closed forms
- * and the brute-force solver).
+ * and the brute-force solver), and the estimator's quality on real scenes is unpinned (no data
+ * or reference implementation here).
  */
 #include <math.h>
 #include <stdint.h>
