@@ -247,11 +247,14 @@ def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
     torch.cuda.synchronize()
     s.clear_stats()
     events = 0
+    marks = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        events += step()
+        events += step()                 # each step ends with a synchronising drain
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    per_step = np.diff(np.array([t0] + marks)) * 1e3
     st = s.stats()
     selected = st["selected"]
     sim_ms, sim_launches = st["simulate_ms"], st["simulate_launches"]
@@ -292,6 +295,7 @@ def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
     return {
         "value": round(npix * K * steps / elapsed / 1e6, 1),
         "ms_per_step": round(1e3 * elapsed / steps, 4),
+        "ms_per_step_std": round(float(per_step.std()), 4),
         "events_per_s": round(ev_per_step * steps / elapsed, 1),
         "events_per_step": ev_per_step,
         "selected_fraction": round(sel_per_step / (npix * K), 5),
@@ -425,6 +429,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": m["ms_per_step"],
+        "ms_per_step_std": m["ms_per_step_std"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
