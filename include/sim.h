@@ -48,7 +48,11 @@
  * stream exactly as it was before the call, with one exception: when a device buffer sized by
  * the number of events (the event arena, the sort buffers, the event FIFO) has to grow in the
  * middle of a push and that allocation fails, part of the image has already advanced, so the
- * push returns SIM_E_NOMEM and poisons the handle.  SIM_E_HIP poisons the
+ * push returns SIM_E_NOMEM and poisons the handle.  The same holds when the events of one window
+ * (the up to 128 intervals a push simulates in one launch) exceed what that buffer can hold:
+ * fewer than 2^31 events, in 256 equal parts of at most 2^23 - 1 events; the pixels are taken in
+ * groups of 64 consecutive ones (consecutive selected pixels for SPARSE) and group g writes into
+ * part g mod 256.  Pushing fewer frames per call makes windows smaller.  SIM_E_HIP poisons the
  * handle: every later call except sim_destroy, sim_get_stats and sim_strerror returns
  * SIM_E_POISONED.  A handle is not thread-safe; distinct handles are independent.
  */
@@ -86,7 +90,8 @@ typedef struct sim_config {
     int32_t n_interp;           /* N >= 0 interpolated frames per interval, S = N + 1 (<= 255);     */
                                 /* ignored by SIM_BASIC (S = 1)                                     */
     float mask_threshold;       /* SIM_SPARSE selection m: < 0 -> min(c_pos, c_neg); 0 -> all px   */
-    uint64_t event_capacity;    /* initial device event buffer (events); grows on demand; 0 = auto */
+    uint64_t event_capacity;    /* initial device event buffer (events, < 2^31 - 255); grows on    */
+                                /* demand; 0 = auto (2 per pixel)                                  */
     void* hip_stream;           /* hipStream_t to order all work on; NULL -> library-owned stream   */
     int32_t thresh_mode;        /* SIM_THRESH_REFERENCE (default: reference level, event pixel) |   */
                                 /* SIM_THRESH_MEMORYLESS (paper's equations); DIFFERENCE: ignored   */
@@ -142,7 +147,10 @@ void sim_config_init(sim_config* cfg);
  * cfg is copied.  On success *out owns the handle until sim_destroy.  Errors: SIM_E_INVAL
  * (dimension out of 1..4096, method/transform/thresh_mode/flow_source unknown, SIM_FLOW_LK
  * with a method other than DENSE or SPARSE, thresholds not > 0 or so small that R + C == R for
- * some reachable R, n_interp outside 0..255, log_eps not > 0), SIM_E_NOMEM. */
+ * some reachable R, n_interp outside 0..255, log_eps not > 0, event_capacity >= 2^31 - 255, and,
+ * with a reference level (SIM_THRESH_REFERENCE, methods other than DIFFERENCE), thresholds so
+ * small that one pixel could fire more than 2^24 events in one interval:
+ * S * (2 * (max T - min T) / min(c_pos, c_neg) + 3) > 2^24), SIM_E_NOMEM. */
 int sim_create(const sim_config* cfg, sim_stream** out);
 
 /* Releases every resource of the handle after the work queued on its stream completes. */

@@ -22,6 +22,15 @@ constexpr int kArenaStripes = 256;   // event sub-arenas, one reservation counte
 constexpr int kActStripes = 8;       // active-pixel sub-lists (one per group of select blocks)
 constexpr int kStatStripes = 64;     // statistics counters
 constexpr int kSelectPx = 1024;      // pixels per selection block (4 per thread)
+// The event arena of one window holds fewer than kArenaKeyLimit keys (so every count, offset and
+// prefix sum over it fits 32 bits), hence each sub-arena fewer than kArenaKeyLimit / kArenaStripes.
+constexpr uint64_t kArenaKeyLimit = 1ull << 31;
+// Most events one pixel may fire in one frame interval with a reference level (the stream's
+// configuration is refused otherwise): the chain kernel sums 64 lanes' counts in an int, and each
+// lane's crossing loop runs at most this many steps per pass.  (Memoryless thresholding fires at
+// most S <= 256 events per pixel and interval.)
+constexpr int kMaxLaneCount = 1 << 24;
+static_assert(64ull * kMaxLaneCount < (1ull << 31), "wave totals fit an int");
 
 enum Method { kBasic = 0, kDense = 1, kSparse = 2, kDifference = 3 };
 

@@ -246,7 +246,7 @@ int ensure_sort_scratch(sim_stream* s, uint64_t n) {
 // Grows every sub-arena to new_stripe_cap keys, keeping the first stripe_cap keys of each.
 int grow_arena(sim_stream* s, uint64_t new_stripe_cap) {
     if (new_stripe_cap <= s->stripe_cap) return SIM_OK;
-    if (new_stripe_cap * kArenaStripes >= (1ull << 31)) return SIM_E_NOMEM;
+    if (new_stripe_cap * kArenaStripes >= kArenaKeyLimit) return SIM_E_NOMEM;
     uint64_t* nb = nullptr;
     if (hipMalloc((void**)&nb, new_stripe_cap * kArenaStripes * sizeof(uint64_t)) != hipSuccess) {
         (void)hipGetLastError();
@@ -1006,6 +1006,22 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
         return SIM_E_INVAL;
     }
     s->S = cfg->method == SIM_BASIC ? 1 : cfg->n_interp + 1;
+    // With a reference level one pixel may fire at most kMaxLaneCount events per interval.  Above
+    // cmin a level step loses less than C/8 to rounding and R stays within C/8 of the samples, so
+    // one sub-interval fires at most 2 (max T - min T) / C + 3 events.
+    if (cfg->thresh_mode == SIM_THRESH_REFERENCE && cfg->method != SIM_DIFFERENCE) {
+        float tmin = s->lut_host[0], tmax = s->lut_host[0];
+        for (int v = 1; v < 256; ++v) {
+            tmin = std::min(tmin, s->lut_host[v]);
+            tmax = std::max(tmax, s->lut_host[v]);
+        }
+        const double c = std::min(cfg->c_pos, cfg->c_neg);
+        const double per_interval = (double)s->S * (2.0 * ((double)tmax - tmin) / c + 3.0);
+        if (per_interval > (double)kMaxLaneCount) {
+            delete s;
+            return SIM_E_INVAL;
+        }
+    }
     s->m = cfg->mask_threshold < 0.0f ? std::min(cfg->c_pos, cfg->c_neg) : cfg->mask_threshold;
     s->npix = (int64_t)cfg->width * cfg->height;
     {
@@ -1024,7 +1040,7 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     }
     uint64_t cap0 = cfg->event_capacity ? cfg->event_capacity : 2 * (uint64_t)s->npix;
     s->stripe_cap = std::max<uint64_t>(1, (cap0 + kArenaStripes - 1) / kArenaStripes);
-    if (s->stripe_cap * kArenaStripes >= (1ull << 31)) {
+    if (s->stripe_cap * kArenaStripes >= kArenaKeyLimit) {
         delete s;
         return SIM_E_INVAL;
     }

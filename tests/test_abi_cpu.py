@@ -62,6 +62,10 @@ def test_host_only_entry_points():
     assert lib.sim_create(ctypes.byref(bad), ctypes.byref(h)) == sim.E_INVAL
     bad.n_interp, bad.c_pos = 10, 1e-9     # R + C == R for reachable R
     assert lib.sim_create(ctypes.byref(bad), ctypes.byref(h)) == sim.E_INVAL
+    # one pixel could fire more than 2^24 events in one interval: 256 * (2 * 255 * 4096 + 3)
+    bad.method, bad.transform, bad.n_interp, bad.c_pos, bad.c_neg = sim.DENSE, sim.LINEAR, 255, \
+        2.0 ** -12, 2.0 ** -12
+    assert lib.sim_create(ctypes.byref(bad), ctypes.byref(h)) == sim.E_INVAL
 
 
 def test_product_path_does_not_use_the_oracle():

@@ -5,12 +5,18 @@ untouched (a later push gives the oracle's result), or SIM_E_NOMEM with the stre
 advanced.  No crash, no wrong result.  The same for batched pushes, server admission and the flow
 estimator.  These run on the host only; nothing here faults a GPU."""
 import ctypes
+import os
+import subprocess
+import sys
+import textwrap
+import time
 
 import numpy as np
 import pytest
 
 from paper_2209_04634_amd import sim, synth
-from test_cpu_emulated_kernels import emu_sim, monkeypatch_module, oracle_run  # noqa: F401
+from test_cpu_emulated_kernels import (emu_build, emu_sim, monkeypatch_module,  # noqa: F401
+                                       oracle_run, HERE)
 
 
 def _video():
@@ -166,3 +172,136 @@ def test_flow_estimator_allocation_failure(emu_sim):
             failures += 1
         _disarm(emu_sim)
     assert failures > 0
+
+
+
+def alternating_wave(c, pixels=range(320, 384)):
+    """A 640x1 image whose given pixels (inside 255 .. 383) see a period-2 pattern move 256 px in
+    one interval: with n_interp = 255 and the linear table all 256 samples alternate between 0 and
+    255, the most crossings a pixel can make.  With C a power of two every level step is exact,
+    so each such pixel fires exactly 256 * 255 / C events."""
+    pixels = list(pixels)
+    assert 255 <= min(pixels) and max(pixels) <= 383
+    W = 640
+    f0 = np.where(np.arange(W) % 2 == 1, 255, 0).astype(np.uint8)
+    flow = np.zeros((1, 1, W, 2), np.float32)
+    flow[0, 0, pixels, 0] = 256.0
+    cfg = dict(method="dense", transform="linear", c_pos=c, c_neg=c, n_interp=255)
+    return np.stack([f0, f0]).reshape(2, 1, W), flow, np.array([0, 1000], np.int64), cfg
+
+
+# (stream options, accepted): with a reference level S * (2 (max T - min T) / C + 3) <= 2^24
+BOUND_CASES = [
+    (dict(transform="linear", c=2.0 ** -12, n_interp=255), False),
+    (dict(transform="linear", c=0.0077, n_interp=255), False),
+    (dict(transform="linear", c=2.0 ** -7, n_interp=255), True),      # 16,712,448 <= 2^24
+    (dict(transform="log", c=2.0e-4, n_interp=255), False),
+    (dict(transform="log", c=2.2e-4, n_interp=255), True),
+    (dict(transform="linear", c=2.0 ** -12, n_interp=10), False),
+    (dict(transform="linear", c=2.0 ** -12, method="basic"), True),   # S = 1
+    (dict(transform="linear", c=2.0 ** -12, n_interp=255, thresh_mode="memoryless"), True),
+    (dict(transform="linear", c=2.0 ** -12, n_interp=255, method="difference"), True),
+]
+
+
+@pytest.mark.parametrize("opts,accepted", BOUND_CASES)
+def test_events_per_pixel_and_interval_bound(emu_sim, opts, accepted):
+    """Configurations in which one pixel could fire more than 2^24 events in one interval with a
+    reference level are refused (the chain kernel sums 64 pixels' counts in 32 bits); memoryless
+    thresholding fires at most S per interval and is not limited."""
+    o = dict(opts)
+    c = o.pop("c")
+    o.setdefault("method", "dense")
+    if accepted:
+        emu_sim.Stream(64, 4, c_pos=c, c_neg=c, **o).close()
+        emu_sim.Stream(64, 4, c_pos=c, c_neg=4 * c, **o).close()
+    else:
+        with pytest.raises(emu_sim.SimError) as e:
+            emu_sim.Stream(64, 4, c_pos=c, c_neg=c, **o)
+        assert e.value.status == emu_sim.E_INVAL
+        with pytest.raises(emu_sim.SimError):
+            emu_sim.Stream(64, 4, c_pos=4 * c, c_neg=c, **o)
+
+
+def run_heaviest_wave(s_mod, arm):
+    """The heaviest wave an accepted configuration allows: 64 pixels of 256 * 255 * 128 =
+    8,355,840 events each in one interval (5.3e8 in all; no sub-arena can hold that).  The k-th
+    device allocation of the push fails, k = 0, 1, ...: early failures leave the stream untouched;
+    the first that lands on the growth of the event arena, after the chain kernel counted, must
+    poison it.  Returns the seconds that push took."""
+    frames, flows, t, cfg = alternating_wave(2.0 ** -7)
+    for k in range(8):
+        s = s_mod.Stream(640, 1, **cfg)
+        arm(k)
+        t0 = time.time()
+        try:
+            s.push_frames(frames, flows, t)
+            raise AssertionError("5.3e8 events of one wave cannot fit a sub-arena")
+        except s_mod.SimError as e:
+            assert e.status == s_mod.E_NOMEM, e
+        finally:
+            arm(-1)
+        dt = time.time() - t0
+        try:
+            assert s.pending() == 0
+        except s_mod.SimError as e:
+            assert e.status == s_mod.E_POISONED
+            s.close()
+            return dt
+        s.close()
+    raise AssertionError("no allocation of the push failed after the chain kernel")
+
+
+def test_heaviest_wave_fails_cleanly(emu_sim):
+    dt = run_heaviest_wave(emu_sim, lambda k: _arm(emu_sim, k))
+    assert dt < 120, dt
+
+
+def test_alternating_pixel_count_on_the_oracle():
+    """The count the heaviest wave relies on: one alternating pixel at C = 2^-7 fires exactly
+    256 * 255 * 128 events in the oracle."""
+    frames, flows, t, _ = alternating_wave(2.0 ** -7, [340])
+    ok, _ = oracle_run(frames, flows, t, method=sim.DENSE, transform=sim.LINEAR,
+                       c_pos=2.0 ** -7, c_neg=2.0 ** -7, n_interp=255)
+    assert len(ok) == 256 * 255 * 128
+
+
+def test_alternating_pixels_equal_the_oracle(emu_sim):
+    """The same construction at a size that fits: one pixel in each of two waves."""
+    frames, flows, t, cfg = alternating_wave(1.0, [300, 330])
+    s = emu_sim.Stream(640, 1, event_capacity=256 * 65536, **cfg)
+    s.push_frames(frames, flows, t)
+    ok, oref = oracle_run(frames, flows, t, method=sim.DENSE, transform=sim.LINEAR,
+                          c_pos=1.0, c_neg=1.0, n_interp=255)
+    assert len(ok) == 2 * 256 * 255
+    np.testing.assert_array_equal(s.drain_keys(), ok)
+    np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32))
+    s.close()
+
+
+ASAN_SCRIPT = textwrap.dedent("""
+    import ctypes, sys
+    sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+    from paper_2209_04634_amd import sim
+    sim.LIB_PATH = {lib!r}; sim._lib = None
+    import test_cpu_emulated_failures as t
+    lib = sim.load()
+    lib.emu_fail_alloc_after.argtypes = [ctypes.c_long]
+    t.run_heaviest_wave(sim, lib.emu_fail_alloc_after)
+    print("asan-clean")
+""")
+
+
+def test_heaviest_wave_is_memory_safe_under_asan(tmp_path):
+    lib = emu_build.build(asan=True)
+    asan_rt = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True,
+                             text=True).stdout.strip()
+    if not os.path.exists(asan_rt):
+        pytest.skip("libasan not available")
+    script = tmp_path / "asan_wave.py"
+    script.write_text(ASAN_SCRIPT.format(root=os.path.dirname(HERE), tests=HERE, lib=lib))
+    env = dict(os.environ, LD_PRELOAD=asan_rt,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1:halt_on_error=1")
+    res = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env,
+                         timeout=900)
+    assert res.returncode == 0 and "asan-clean" in res.stdout, res.stderr[-4000:]
