@@ -250,9 +250,9 @@ const char* sim_strerror(int status);
  * of accumulated events): adds, for every pending (not yet drained) event with
  * t_begin <= t < t_end, one to counts[0][y][x] if it is positive or to counts[1][y][x] if it is
  * negative.  counts: uint32 [2][height][width], caller-owned, host or device (mem_kind); it is
- * added to, not cleared.  Host counts are complete when the call returns; device counts are
- * written in stream order on the handle's stream.  Pending events are not consumed.  Errors:
- * SIM_E_INVAL (NULL counts, t_end < t_begin, bad mem_kind). */
+ * added to, not cleared (each count wraps modulo 2^32).  Host counts are complete when the call
+ * returns; device counts are written in stream order on the handle's stream.  Pending events are
+ * not consumed.  Errors: SIM_E_INVAL (NULL counts, t_end < t_begin, bad mem_kind). */
 int sim_accumulate(sim_stream* s, int64_t t_begin, int64_t t_end, uint32_t* counts,
                    int32_t mem_kind);
 
@@ -261,6 +261,7 @@ int sim_accumulate(sim_stream* s, int64_t t_begin, int64_t t_end, uint32_t* coun
  * pixels, S1 = sum c and S2 = sum c^2 (exact integers), m1 = S1 / npix, m2 = S2 / npix and
  * T = (t_end - t_begin) * 1e-6 s, *mean = m1 / T and *stddev = sqrt(max(m2 - m1 * m1, 0)) / T
  * (population deviation over pixels; double precision).  sums (may be NULL) receives S1, S2.
+ * S1 and S2 are exact while S2 < 2^64 (so every c < 2^32).
  * Synchronises the stream.  Errors: SIM_E_INVAL (NULL mean or stddev, t_end <= t_begin). */
 int sim_event_rate(sim_stream* s, int64_t t_begin, int64_t t_end, double* mean, double* stddev,
                    uint64_t* sums);
