@@ -43,6 +43,24 @@ def test_emulated_memoryless_ragged_image(emu_sim, method, S):
           c_neg=C * 1.2, n_interp=S - 1, thresh_mode=sim.MEMORYLESS)
 
 
+@pytest.mark.parametrize("cfg", [dict(method=sim.DIFFERENCE),
+                                 dict(method=sim.DENSE, thresh_mode=sim.MEMORYLESS),
+                                 dict(method=sim.SPARSE, thresh_mode=sim.MEMORYLESS)],
+                         ids=["difference", "dense-memoryless", "sparse-memoryless"])
+def test_emulated_non_finite_flow_clamps_like_the_oracle(emu_sim, cfg):
+    """NaN and infinite flow components clamp the sample position to the border (fmin/fmax return
+    the other operand for NaN) in the difference-frame sampler too, as in the oracle."""
+    rng = np.random.default_rng(77)
+    frames, flows = synth.random_frames(rng, 4, 19, 41, flow_scale=4.0)
+    flows[0, 3, 5] = [np.nan, 1.0]
+    flows[1, 7, 8] = [np.inf, -np.inf]
+    flows[2, 2, 2] = [-np.inf, np.nan]
+    flows[2, 0, 40] = [np.nan, np.nan]
+    n = check(emu_sim, frames, flows, [0, 100, 200, 300], modes=("window", "single"),
+              c_pos=0.05, c_neg=0.05, n_interp=5, **cfg)
+    assert n > 0
+
+
 def test_emulated_difference_blob_video_and_chunked_pushes(emu_sim):
     """A blob video through the difference method: one window, single frames, and chunks of
     1, 2, 3 frames (the frame before the previous one comes from the window or the saved state)."""
