@@ -166,7 +166,8 @@ int sim_reset(sim_stream* s);
  * previous frame to this one; for SIM_DIFFERENCE the flow between the interval's difference
  * frames); required for SIM_DENSE / SIM_SPARSE / SIM_DIFFERENCE except on the first frame,
  * ignored otherwise (may be NULL).  mem_kind tells whether frame and flow are host or device
- * pointers; host inputs are copied before the call returns, device inputs must stay valid until
+ * pointers; host inputs are copied before the call returns (one window of frames and flows at a
+ * time, through a device staging buffer of that size), device inputs must stay valid until
  * the work queued on the stream has completed.  The first push only initialises the reference
  * levels (no events).  n_new_events (may be NULL) receives the number of events this push
  * produced.  Errors: SIM_E_INVAL (NULL frame, missing flow), SIM_E_ORDER (t_us not greater than

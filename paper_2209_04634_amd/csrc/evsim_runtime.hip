@@ -587,13 +587,19 @@ int push_validate(sim_stream* s, int32_t n_frames, const uint8_t* frames, const 
 }
 
 struct Staged {
-    const uint8_t* frames = nullptr;   // device copy (or the caller's device pointer)
-    const float* flows = nullptr;
+    const uint8_t* frames = nullptr;   // the caller's frames (host or device, see `host`)
+    const float* flows = nullptr;      // the caller's flows
+    bool host = false;                 // host inputs: copied to the device one window at a time
     int first = 0;                     // frames consumed by initialisation
     int n_int = 0;                     // intervals to simulate
 };
 
-// Copies host inputs to the device and initialises a fresh stream from its first frame.
+bool uses_flows(const sim_stream* s) {
+    return s->S > 1 && s->cfg.flow_source == SIM_FLOW_SUPPLIED;
+}
+
+// Reserves what the push needs whatever its events (host inputs: staging for one window of
+// frames and flows) and initialises a fresh stream from its first frame.
 int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const float* flows,
                const int64_t* t_us, int32_t mem_kind, Staged* out) {
     const size_t fbytes = (size_t)s->npix;
@@ -602,24 +608,21 @@ int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const flo
     out->n_int = n_frames - out->first;
     out->frames = frames;
     out->flows = flows;
-    if (mem_kind == SIM_MEM_HOST) {
+    out->host = mem_kind == SIM_MEM_HOST;
+    const uint8_t* init_frame = frames;
+    if (out->host) {
+        const int win = std::min(kMaxWindow, out->n_int);
         uint64_t cap = s->stage_frames_cap;
-        int rc = grow(s, &s->d_stage_frames, &cap, (uint64_t)n_frames * fbytes, 0);
+        int rc = grow(s, &s->d_stage_frames, &cap, (uint64_t)std::max(win, 1) * fbytes, 0);
         s->stage_frames_cap = (size_t)cap;
         if (rc) return rc;
-        HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, frames, (size_t)n_frames * fbytes,
-                                  hipMemcpyHostToDevice, s->stream));
-        out->frames = s->d_stage_frames;
-        if (out->n_int > 0 && s->S > 1 && s->cfg.flow_source == SIM_FLOW_SUPPLIED) {
+        if (win > 0 && uses_flows(s)) {
             cap = s->stage_flows_cap;
-            rc = grow(s, &s->d_stage_flows, &cap, (uint64_t)out->n_int * flfloats, 0);
+            rc = grow(s, &s->d_stage_flows, &cap, (uint64_t)win * flfloats, 0);
             s->stage_flows_cap = (size_t)cap;
             if (rc) return rc;
-            HIP_TRY(s, hipMemcpyAsync(s->d_stage_flows, flows,
-                                      (size_t)out->n_int * flfloats * 4, hipMemcpyHostToDevice,
-                                      s->stream));
-            out->flows = s->d_stage_flows;
         }
+        init_frame = s->d_stage_frames;
     }
     if (out->n_int > 0) {
         // every buffer whose size is known now, before anything changes: a failure here leaves
@@ -632,7 +635,10 @@ int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const flo
         if (rc) return rc;
     }
     if (!s->started) {
-        HIP_TRY(s, launch_init(out->frames, s->d_lut, s->d_lref, s->d_prev[s->cur], s->npix,
+        if (out->host)
+            HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, frames, fbytes, hipMemcpyHostToDevice,
+                                      s->stream));
+        HIP_TRY(s, launch_init(init_frame, s->d_lut, s->d_lref, s->d_prev[s->cur], s->npix,
                                s->stream));
         s->started = true;
         s->epoch = t_us[0];
@@ -643,13 +649,28 @@ int push_stage(sim_stream* s, int32_t n_frames, const uint8_t* frames, const flo
     return SIM_OK;
 }
 
-const uint8_t* window_frames(const sim_stream* s, const Staged& st, int j) {
-    return st.frames + (size_t)(st.first + j) * (size_t)s->npix;
-}
-
-const float* window_flows(const sim_stream* s, const Staged& st, int j) {
-    if (s->S <= 1 || s->cfg.flow_source != SIM_FLOW_SUPPLIED) return nullptr;
-    return st.flows + (size_t)j * 2 * (size_t)s->npix;
+// Device frames and flows of the window of K intervals starting at interval j.  Host inputs are
+// copied into the staging buffers on the stream, after the work queued before (the previous
+// window, which read the same buffers, has completed by then: every window ends with a host
+// wait).
+int stage_window(sim_stream* s, const Staged& st, int j, int K, const uint8_t** frames,
+                 const float** flows) {
+    const size_t npix = (size_t)s->npix;
+    const uint8_t* f = st.frames + (size_t)(st.first + j) * npix;
+    const float* fl = uses_flows(s) ? st.flows + (size_t)j * 2 * npix : nullptr;
+    if (st.host) {
+        HIP_TRY(s, hipMemcpyAsync(s->d_stage_frames, f, (size_t)K * npix, hipMemcpyHostToDevice,
+                                  s->stream));
+        f = s->d_stage_frames;
+        if (fl) {
+            HIP_TRY(s, hipMemcpyAsync(s->d_stage_flows, fl, (size_t)K * 2 * npix * sizeof(float),
+                                      hipMemcpyHostToDevice, s->stream));
+            fl = s->d_stage_flows;
+        }
+    }
+    *frames = f;
+    *flows = fl;
+    return SIM_OK;
 }
 
 int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
@@ -1132,8 +1153,10 @@ int sim_push_frames(sim_stream* s, int32_t n_frames, const uint8_t* frames, cons
     for (int j = 0; j < st.n_int; j += kMaxWindow) {
         const int K = std::min(kMaxWindow, st.n_int - j);
         uint64_t nn = 0;
-        rc = run_window(s, window_frames(s, st, j), window_flows(s, st, j), t_us + st.first + j,
-                        K, &nn);
+        const uint8_t* wf = nullptr;
+        const float* wfl = nullptr;
+        rc = stage_window(s, st, j, K, &wf, &wfl);
+        if (!rc) rc = run_window(s, wf, wfl, t_us + st.first + j, K, &nn);
         if (rc) return rc;
         total += nn;
     }
@@ -1175,8 +1198,8 @@ int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
             f.s = streams[i];
             f.it = &it;
             f.K = std::min(kMaxWindow, st[i].n_int - j);
-            f.frames = window_frames(streams[i], st[i], j);
-            f.flows = window_flows(streams[i], st[i], j);
+            it.status = stage_window(streams[i], st[i], j, f.K, &f.frames, &f.flows);
+            if (it.status) continue;
             f.t_us = it.t_us + st[i].first + j;
             fi.push_back(f);
         }

@@ -310,8 +310,15 @@ struct emu_event_t {
 // device allocation after k more successful ones fails (then the countdown is off again).
 static long g_fail_countdown = -1;
 static long g_allocs = 0;
+static std::vector<size_t> g_alloc_sizes;   // sizes of the device allocations since the reset
 extern "C" void emu_fail_alloc_after(long k) { g_fail_countdown = k; }
 extern "C" long emu_alloc_count(void) { return g_allocs; }
+extern "C" void emu_reset_alloc_log(void) { g_alloc_sizes.clear(); }
+// Copies up to cap logged sizes to out; returns how many are logged.
+extern "C" size_t emu_alloc_log(size_t* out, size_t cap) {
+    for (size_t i = 0; i < g_alloc_sizes.size() && i < cap; ++i) out[i] = g_alloc_sizes[i];
+    return g_alloc_sizes.size();
+}
 
 hipError_t emu_hipMalloc(void** p, size_t n) {
     if (g_fail_countdown == 0) {
@@ -324,6 +331,7 @@ hipError_t emu_hipMalloc(void** p, size_t n) {
     if (!*p) return hipErrorOutOfMemory;
     memset(*p, 0xA5, n);   // device memory starts as garbage
     ++g_allocs;
+    g_alloc_sizes.push_back(n);
     return hipSuccess;
 }
 hipError_t emu_hipFree(void* p) {

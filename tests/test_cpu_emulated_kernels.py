@@ -6,6 +6,7 @@ lockstep wave64 intrinsics, block barriers), so index arithmetic, overflow re-ru
 and every intrinsic use can be checked without a GPU -- and, in the AddressSanitizer build, every
 memory access is bounds-checked.  The product never loads these builds.
 """
+import ctypes
 import os
 import subprocess
 import sys
@@ -122,6 +123,32 @@ def test_emulated_long_sparse_sequence_spans_windows(emu_sim):
     v = synth.blob_video(spec)
     check(emu_sim, v.frames, v.flows, v.t_us, method=sim.SPARSE, c_pos=0.1, c_neg=0.1,
           n_interp=3)
+
+
+@pytest.mark.parametrize("method", [sim.DENSE, sim.DIFFERENCE])
+def test_emulated_host_push_stages_one_window_at_a_time(emu_sim, method):
+    """A 300-frame push from host memory (three windows) copies one window of frames and flows
+    to the device at a time: the staging buffers hold 128 frames and 128 flow fields, never the
+    whole push, and the events equal the oracle's."""
+    W, H = 32, 16
+    spec = synth.BlobVideoSpec(W, H, 300, 60.0, 3, seed=8, motion="random", speed_max=4.0)
+    v = synth.blob_video(spec)
+    lib = emu_sim.load()
+    lib.emu_alloc_log.restype = ctypes.c_size_t
+    lib.emu_alloc_log.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t]
+    lib.emu_reset_alloc_log()
+    cfg = dict(method=method, c_pos=0.05, c_neg=0.05, n_interp=3)
+    s = emu_sim.Stream(W, H, **cfg)
+    s.push_frames(v.frames, v.flows, v.t_us)
+    ok, oref = oracle_run(v.frames, v.flows, v.t_us, **cfg)
+    assert len(ok) > 1000
+    np.testing.assert_array_equal(s.drain_keys(), ok)
+    np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32))
+    s.close()
+    buf = (ctypes.c_size_t * 4096)()
+    sizes = set(buf[:min(lib.emu_alloc_log(buf, 4096), 4096)])
+    assert {128 * W * H, 128 * W * H * 2 * 4} <= sizes, sorted(sizes)
+    assert not {300 * W * H, 299 * W * H, 299 * W * H * 2 * 4} & sizes, sorted(sizes)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 70), (70, 1), (3, 129)])
