@@ -187,6 +187,22 @@ def _buffer(x, dtype, shape=None):
     return a.ctypes.data_as(ctypes.c_void_p), MEM_HOST, a
 
 
+def _out_buffer(x, dtype, shape=None, also=()):
+    """(pointer, mem_kind, keepalive) of a caller's output array or tensor, written in place: a
+    numpy array must already have the dtype (or one of `also`), be C-contiguous and writeable,
+    since a converted copy would receive the results instead."""
+    if _is_torch(x):
+        return _buffer(x, dtype, shape)
+    ok = tuple(np.dtype(d) for d in (dtype,) + tuple(also))
+    if not isinstance(x, np.ndarray) or x.dtype not in ok:
+        raise TypeError(f"expected a numpy array of {' or '.join(str(d) for d in ok)}")
+    if not x.flags.c_contiguous or not x.flags.writeable:
+        raise TypeError("output array must be C-contiguous and writeable")
+    if shape is not None and x.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {x.shape}")
+    return x.ctypes.data_as(ctypes.c_void_p), MEM_HOST, x
+
+
 def lk_params(levels: int = 3, radius: int = 7, iterations: int = 10, eps: float = 1e-4,
               min_trace: float = 1.0, min_ratio: float = 1e-3) -> SimLkParams:
     p = SimLkParams()
@@ -213,7 +229,9 @@ def lk_flow(f0, f1, points=None, hip_stream=None, **params):
         n = int(points.numel())
         flow = torch.zeros((n, 2), dtype=torch.float32, device=f0.device)
         valid = torch.zeros(n, dtype=torch.uint8, device=f0.device)
-        pp, _, keep_p = _buffer(points, np.uint32, (n,))
+        pp, pk, keep_p = _buffer(points, np.uint32, (n,))
+        if pk != MEM_DEVICE:
+            raise ValueError("points must be a device tensor when the frames are")
         fp = ctypes.c_void_p(flow.data_ptr())
         vp = ctypes.c_void_p(valid.data_ptr())
     else:
@@ -354,11 +372,14 @@ class Stream:
         return out[:got.value]
 
     def drain_keys(self, max_events: Optional[int] = None, out=None):
-        """Oldest pending events as packed uint64 keys: numpy (host) or into a torch int64
-        device tensor `out` (returns the number written)."""
+        """Oldest pending events as packed uint64 keys: numpy (host) or, into `out` (a uint64 or
+        int64 numpy array or an int64 torch tensor, at most its size), the number written."""
         if out is not None:
-            ptr, kind, keep = _buffer(out, np.int64, None)
-            n = int(out.numel()) if max_events is None else int(max_events)
+            ptr, kind, keep = _out_buffer(out, np.int64, None, also=(np.uint64,))
+            cap = int(out.numel()) if _is_torch(out) else int(out.size)
+            n = cap if max_events is None else int(max_events)
+            if not 0 <= n <= cap:
+                raise ValueError(f"max_events must be within 0..{cap} (the size of out)")
             got = ctypes.c_uint64()
             _check(self._lib.sim_drain_keys(self._h, ptr, n, kind, ctypes.byref(got)),
                    "sim_drain_keys", self._h)
@@ -378,9 +399,7 @@ class Stream:
         shape = (2, self.height, self.width)
         if counts is None:
             counts = np.zeros(shape, dtype=np.uint32)
-        if not _is_torch(counts) and (counts.dtype != np.uint32 or not counts.flags.c_contiguous):
-            raise TypeError("counts must be a C-contiguous uint32 array")
-        ptr, kind, keep = _buffer(counts, np.uint32, shape)
+        ptr, kind, keep = _out_buffer(counts, np.uint32, shape)
         _check(self._lib.sim_accumulate(self._h, int(t_begin), int(t_end), ptr, kind),
                "sim_accumulate", self._h)
         return counts
@@ -404,7 +423,7 @@ class Stream:
     def reference(self, out=None):
         """Per-pixel reference levels float32 [H, W] (numpy, or into a torch device tensor)."""
         if out is not None:
-            ptr, kind, keep = _buffer(out, np.float32, (self.height, self.width))
+            ptr, kind, keep = _out_buffer(out, np.float32, (self.height, self.width))
             _check(self._lib.sim_get_reference(self._h, ptr, kind), "sim_get_reference", self._h)
             return out
         arr = np.zeros((self.height, self.width), dtype=np.float32)

@@ -1,0 +1,69 @@
+"""The Python binding's handling of caller-owned output buffers, on the CPU emulation of the
+library: results land in the caller's array (never in a converted copy), and a request larger
+than the buffer is refused before the library is called."""
+import numpy as np
+import pytest
+
+from paper_2209_04634_amd import sim, synth
+from test_cpu_emulated_kernels import emu_sim, monkeypatch_module, oracle_run  # noqa: F401
+
+
+@pytest.fixture()
+def stream_with_events(emu_sim):
+    v = synth.blob_video(synth.BlobVideoSpec(40, 24, 4, 30.0, 5, seed=12, motion="random",
+                                             speed_max=5.0))
+    cfg = dict(method=sim.DENSE, c_pos=0.12, c_neg=0.12, n_interp=4)
+    ok, oref = oracle_run(v.frames, v.flows, v.t_us, **cfg)
+    s = emu_sim.Stream(40, 24, **cfg)
+    s.push_frames(v.frames, v.flows, v.t_us)
+    assert len(ok) > 20
+    yield s, ok, oref
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", [np.uint64, np.int64])
+def test_drain_into_a_numpy_array_in_place(stream_with_events, dtype):
+    s, ok, _ = stream_with_events
+    out = np.zeros(7, dtype=dtype)
+    assert s.drain_keys(out=out) == 7
+    np.testing.assert_array_equal(out.view(np.uint64), ok[:7])
+    out2 = np.zeros(len(ok), dtype=dtype)
+    assert s.drain_keys(out=out2, max_events=5) == 5
+    np.testing.assert_array_equal(out2[:5].view(np.uint64), ok[7:12])
+    assert not out2[5:].any()
+    assert s.pending() == len(ok) - 12
+
+
+def test_drain_refuses_more_than_the_buffer(stream_with_events):
+    s, ok, _ = stream_with_events
+    with pytest.raises(ValueError):
+        s.drain_keys(out=np.zeros(3, np.uint64), max_events=10)
+    with pytest.raises(ValueError):
+        s.drain_keys(out=np.zeros(3, np.uint64), max_events=-1)
+    with pytest.raises(TypeError):
+        s.drain_keys(out=np.zeros(8, np.int32))
+    with pytest.raises(TypeError):
+        s.drain_keys(out=np.zeros(16, np.uint64)[::2])        # not contiguous
+    ro = np.zeros(8, np.uint64)
+    ro.flags.writeable = False
+    with pytest.raises(TypeError):
+        s.drain_keys(out=ro)
+    assert s.pending() == len(ok)                              # nothing was drained
+
+
+def test_reference_and_accumulate_write_the_callers_array(stream_with_events):
+    s, ok, oref = stream_with_events
+    ref = np.full((24, 40), -1.0, np.float32)
+    assert s.reference(out=ref) is ref
+    np.testing.assert_array_equal(ref.view(np.uint32), oref.view(np.uint32))
+    with pytest.raises(TypeError):
+        s.reference(out=np.zeros((24, 40), np.float64))
+    with pytest.raises(TypeError):
+        s.reference(out=np.zeros((40, 24), np.float32).T)     # not C-contiguous
+    with pytest.raises(ValueError):
+        s.reference(out=np.zeros((24, 41), np.float32))
+    counts = np.zeros((2, 24, 40), np.uint32)
+    assert s.accumulate(0, 1 << 40, counts=counts) is counts
+    assert int(counts.sum()) == len(ok)
+    with pytest.raises(TypeError):
+        s.accumulate(0, 1 << 40, counts=np.zeros((2, 24, 40), np.int64))
