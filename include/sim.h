@@ -310,7 +310,9 @@ const char* sim_last_error(sim_stream* s);
  * cameras' GPU work overlaps; frames submitted after a step started wait for the next one.  The
  * latency of a frame is the time from its arrival stamp (srv_now_ns clock; 0 = now) to the end
  * of the step that ordered its events.  Results per camera are exactly those of the camera's
- * frames pushed alone.  A server is not thread-safe.
+ * frames pushed alone.  A server is not thread-safe.  srv_create reserves the server's own host
+ * bookkeeping (about 8 MB of latency record, plus a little per camera slot), so it does not grow
+ * while serving.
  * ------------------------------------------------------------------------------------------ */
 typedef struct sim_server sim_server;
 
@@ -325,7 +327,8 @@ typedef struct sim_server_stats {
     uint64_t steps;
     uint64_t events;
     uint64_t hbm_used, hbm_budget;/* footprint estimates of the admitted cameras, and the budget   */
-    double p50_ms, p99_ms, max_ms;/* per-frame latency, arrival to ordered events                  */
+    double p50_ms, p99_ms, max_ms;/* per-frame latency, arrival to ordered events, over the latest */
+                                  /* 2^20 completed frames since srv_clear_stats                  */
 } sim_server_stats;
 
 /* Estimated device bytes of one camera with this configuration and staging queue depth. */

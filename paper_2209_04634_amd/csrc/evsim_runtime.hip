@@ -960,6 +960,44 @@ int fused_window(std::vector<FusedItem>& items) {
 
 }  // namespace
 
+// The window loop of a batched push: chunk by chunk, every stream's window of the chunk runs in
+// the fused launches.  A failure poisons the streams of its chunk (their device state may have
+// advanced); the others go on.  *chunk receives the first interval of the chunk being run.  May
+// throw std::bad_alloc.
+void batch_windows(sim_stream** streams, sim_frames* items, const std::vector<Staged>& st, int n,
+                   int max_int, int* chunk) {
+    std::lock_guard<std::mutex> lock(batch_ctx().mu);
+    for (int j = 0; j < max_int; j += kMaxWindow) {
+        *chunk = j;
+        std::vector<FusedItem> fi;
+        for (int i = 0; i < n; ++i) {
+            sim_frames& it = items[i];
+            if (it.status || j >= st[i].n_int) continue;
+            FusedItem f;
+            memset(&f, 0, sizeof(f));
+            f.s = streams[i];
+            f.it = &it;
+            f.K = std::min(kMaxWindow, st[i].n_int - j);
+            it.status = stage_window(streams[i], st[i], j, f.K, &f.frames, &f.flows);
+            if (it.status) continue;
+            f.t_us = it.t_us + st[i].first + j;
+            fi.push_back(f);
+        }
+        if (fi.empty()) continue;
+        const int rc = fused_window(fi);
+        if (rc) {
+            // device state of the chunk's streams may have advanced: they cannot continue
+            for (FusedItem& f : fi) {
+                f.it->status = rc;
+                f.s->poisoned = true;
+                if (!f.s->last_error[0])
+                    snprintf(f.s->last_error, sizeof(f.s->last_error),
+                             "batched push failed (%s)", sim_strerror(rc));
+            }
+        }
+    }
+}
+
 extern "C" {
 
 void sim_config_init(sim_config* cfg) {
@@ -1177,7 +1215,12 @@ int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
         if (items[i].status && !first_err) first_err = items[i].status;
     }
     if (first_err) return first_err;
-    std::vector<Staged> st(n);
+    std::vector<Staged> st;
+    try {
+        st.resize(n);
+    } catch (...) {
+        return SIM_E_NOMEM;   // nothing has changed yet
+    }
     int max_int = 0;
     for (int i = 0; i < n; ++i) {
         sim_frames& it = items[i];
@@ -1186,34 +1229,19 @@ int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
         if (it.status && !first_err) first_err = it.status;
         if (!it.status) max_int = std::max(max_int, st[i].n_int);
     }
-    // window by window: every stream's window of a chunk runs in the fused launches
-    std::lock_guard<std::mutex> lock(batch_ctx().mu);
-    for (int j = 0; j < max_int; j += kMaxWindow) {
-        std::vector<FusedItem> fi;
+    int chunk = 0;
+    try {
+        batch_windows(streams, items, st, n, max_int, &chunk);
+    } catch (...) {
+        // host memory ran out: a staged stream with a window in this chunk or later may have
+        // advanced part of the way
         for (int i = 0; i < n; ++i) {
-            sim_frames& it = items[i];
-            if (it.status || j >= st[i].n_int) continue;
-            FusedItem f;
-            memset(&f, 0, sizeof(f));
-            f.s = streams[i];
-            f.it = &it;
-            f.K = std::min(kMaxWindow, st[i].n_int - j);
-            it.status = stage_window(streams[i], st[i], j, f.K, &f.frames, &f.flows);
-            if (it.status) continue;
-            f.t_us = it.t_us + st[i].first + j;
-            fi.push_back(f);
-        }
-        if (fi.empty()) continue;
-        const int rc = fused_window(fi);
-        if (rc) {
-            // device state of the chunk's streams may have advanced: they cannot continue
-            for (FusedItem& f : fi) {
-                f.it->status = rc;
-                f.s->poisoned = true;
-                if (!f.s->last_error[0])
-                    snprintf(f.s->last_error, sizeof(f.s->last_error),
-                             "batched push failed (%s)", sim_strerror(rc));
-            }
+            if (items[i].status || st[i].n_int <= chunk) continue;
+            items[i].status = SIM_E_NOMEM;
+            streams[i]->poisoned = true;
+            if (!streams[i]->last_error[0])
+                snprintf(streams[i]->last_error, sizeof(streams[i]->last_error),
+                         "batched push failed (host allocation)");
         }
     }
     for (int i = 0; i < n; ++i)

@@ -55,14 +55,36 @@ void release_camera(Camera& c) {
 
 }  // namespace
 
+// Per-frame latencies kept for the percentiles: the latest kLatencyWindow completed frames.
+constexpr size_t kLatencyWindow = size_t(1) << 20;
+
 struct sim_server {
     uint64_t budget = 0;
     uint64_t used = 0;
     int qcap = 0;
     std::vector<Camera> cams;
-    std::vector<float> lat_ms;     // per completed frame
+    // Everything below is reserved at creation, so that serving allocates no host memory.
+    std::vector<float> lat_ms;     // ring of per-frame latencies
+    size_t lat_next = 0;           // slot the next latency overwrites once the ring is full
+    std::vector<float> lat_sort;   // scratch for the percentiles
+    std::vector<sim_stream*> step_handles;
+    std::vector<sim_frames> step_items;
+    std::vector<int> step_cams;
     sim_server_stats st;
 };
+
+namespace {
+
+void record_latency(sim_server* srv, float ms) {
+    if (srv->lat_ms.size() < kLatencyWindow) {
+        srv->lat_ms.push_back(ms);   // within the reserved capacity
+    } else {
+        srv->lat_ms[srv->lat_next] = ms;
+        srv->lat_next = (srv->lat_next + 1) % kLatencyWindow;
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -98,6 +120,11 @@ int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_dep
     srv->qcap = queue_depth;
     try {
         srv->cams.resize(max_cameras);
+        srv->lat_ms.reserve(kLatencyWindow);
+        srv->lat_sort.reserve(kLatencyWindow);
+        srv->step_handles.reserve(max_cameras);
+        srv->step_items.reserve(max_cameras);
+        srv->step_cams.reserve(max_cameras);
     } catch (...) {
         delete srv;
         return SIM_E_NOMEM;
@@ -224,9 +251,12 @@ int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* 
 int srv_step(sim_server* srv, uint64_t* n_frames) {
     if (!srv) return SIM_E_INVAL;
     if (n_frames) *n_frames = 0;
-    std::vector<sim_stream*> handles;
-    std::vector<sim_frames> items;
-    std::vector<int> which;
+    std::vector<sim_stream*>& handles = srv->step_handles;   // capacity: one per camera slot
+    std::vector<sim_frames>& items = srv->step_items;
+    std::vector<int>& which = srv->step_cams;
+    handles.clear();
+    items.clear();
+    which.clear();
     for (int i = 0; i < (int)srv->cams.size(); ++i) {
         Camera& c = srv->cams[i];
         if (!c.used || c.q == 0) continue;
@@ -249,9 +279,8 @@ int srv_step(sim_server* srv, uint64_t* n_frames) {
     for (size_t j = 0; j < items.size(); ++j) {
         Camera& c = srv->cams[which[j]];
         if (items[j].status == SIM_OK) {
-            for (int f = 0; f < c.q; ++f) {
-                srv->lat_ms.push_back((float)((double)(done - c.arrival_ns[f]) * 1e-6));
-            }
+            for (int f = 0; f < c.q; ++f)
+                record_latency(srv, (float)((double)(done - c.arrival_ns[f]) * 1e-6));
             frames += (uint64_t)c.q;
             srv->st.events += items[j].n_new_events;
             c.started = true;
@@ -285,7 +314,8 @@ int srv_get_stats(sim_server* srv, sim_server_stats* out) {
     *out = srv->st;
     const size_t n = srv->lat_ms.size();
     if (n) {
-        std::vector<float> v(srv->lat_ms);
+        std::vector<float>& v = srv->lat_sort;   // reserved: no allocation
+        v.assign(srv->lat_ms.begin(), srv->lat_ms.end());
         auto pct = [&](double q) {
             size_t k = (size_t)floor(q * (double)(n - 1) + 0.5);
             std::nth_element(v.begin(), v.begin() + k, v.end());
@@ -306,6 +336,7 @@ int srv_clear_stats(sim_server* srv) {
     srv->st.hbm_budget = srv->budget;
     srv->st.hbm_used = srv->used;
     srv->lat_ms.clear();
+    srv->lat_next = 0;
     return SIM_OK;
 }
 
