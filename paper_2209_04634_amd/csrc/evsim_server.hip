@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/sim.h"
@@ -195,7 +196,7 @@ int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
         return SIM_E_NOMEM;
     }
     c.used = true;
-    srv->cams[slot] = c;
+    srv->cams[slot] = std::move(c);   // no copy of its vectors
     srv->used += fp;
     srv->st.cameras++;
     srv->st.admissions++;
