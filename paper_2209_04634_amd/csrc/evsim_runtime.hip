@@ -1283,25 +1283,35 @@ int sim_drain_events(sim_stream* s, sim_event* dst, uint64_t max_events, uint64_
     if (!s || (!dst && max_events)) return SIM_E_INVAL;
     if (s->poisoned) return SIM_E_POISONED;
     const uint64_t n = std::min(max_events, s->fifo_tail - s->fifo_head);
+    // keys come over in chunks, so the host buffer stays small whatever the count
     std::vector<uint64_t> keys;
     try {
-        keys.resize(n);
+        keys.resize((size_t)std::min<uint64_t>(n, 1u << 20));
     } catch (...) {
         return SIM_E_NOMEM;
     }
-    uint64_t got = 0;
-    int rc = sim_drain_keys(s, keys.data(), n, SIM_MEM_HOST, &got);
-    if (rc) return rc;
-    for (uint64_t j = 0; j < got; ++j) {
-        const uint64_t k = keys[j];
-        sim_event& e = dst[j];
-        e.t_us = s->epoch + (int64_t)(k >> 25);
-        e.y = (uint16_t)((k >> 13) & 0xFFF);
-        e.x = (uint16_t)((k >> 1) & 0xFFF);
-        e.p = (k & 1) ? 1 : -1;
-        e.pad[0] = e.pad[1] = e.pad[2] = 0;
+    uint64_t done = 0;
+    while (done < n) {
+        uint64_t got = 0;
+        int rc = sim_drain_keys(s, keys.data(), std::min<uint64_t>(n - done, keys.size()),
+                                SIM_MEM_HOST, &got);
+        if (rc) {
+            if (n_written) *n_written = done;
+            return rc;
+        }
+        if (got == 0) break;
+        for (uint64_t j = 0; j < got; ++j) {
+            const uint64_t k = keys[j];
+            sim_event& e = dst[done + j];
+            e.t_us = s->epoch + (int64_t)(k >> 25);
+            e.y = (uint16_t)((k >> 13) & 0xFFF);
+            e.x = (uint16_t)((k >> 1) & 0xFFF);
+            e.p = (k & 1) ? 1 : -1;
+            e.pad[0] = e.pad[1] = e.pad[2] = 0;
+        }
+        done += got;
     }
-    if (n_written) *n_written = got;
+    if (n_written) *n_written = done;
     return SIM_OK;
 }
 

@@ -67,3 +67,29 @@ def test_reference_and_accumulate_write_the_callers_array(stream_with_events):
     assert int(counts.sum()) == len(ok)
     with pytest.raises(TypeError):
         s.accumulate(0, 1 << 40, counts=np.zeros((2, 24, 40), np.int64))
+
+
+def test_drain_events_beyond_one_conversion_chunk(emu_sim):
+    """sim_drain_events converts keys in chunks of 2^20: a drain of more events than that, and
+    a partial drain ending inside a chunk, give the oracle's events in order."""
+    rng = np.random.default_rng(21)
+    H, W = 192, 256
+    f0 = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    f1 = (255 - f0).astype(np.uint8)
+    frames = np.stack([f0, f1])
+    t = np.array([0, 4], np.int64)                 # few time bits: a short sort
+    cfg = dict(method=sim.BASIC, c_pos=0.05, c_neg=0.05)
+    ok, _ = oracle_run(frames, None, t, **cfg)
+    assert len(ok) > (1 << 20) + 1000
+    s = emu_sim.Stream(W, H, **cfg)
+    s.push_frames(frames, None, t)
+    head = s.drain_events(1000)
+    rest = s.drain_events()
+    ev = np.concatenate([head, rest])
+    tt, x, y, p = sim.decode_keys(ok, 0)
+    np.testing.assert_array_equal(ev["t"], tt)
+    np.testing.assert_array_equal(ev["x"], x)
+    np.testing.assert_array_equal(ev["y"], y)
+    np.testing.assert_array_equal(ev["p"], p)
+    assert s.pending() == 0
+    s.close()
