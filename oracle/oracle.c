@@ -378,10 +378,13 @@ int oracle_lk_flow(const uint8_t* f0, const uint8_t* f1, int W, int H, const ora
     float* b = build_pyramid(f1, W, H, P->levels, J);
     if (!a || !b) { free(a); free(b); return OR_E_NOMEM; }
     for (uint64_t j = 0; j < n; ++j) {
-        const int px = (int)(points[j] % (uint32_t)W), py = (int)(points[j] / (uint32_t)W);
         int ok = 0;
         flow[2 * j] = flow[2 * j + 1] = 0.0f;
-        if (py < H) ok = lk_point(I, J, P, px, py, &flow[2 * j], &flow[2 * j + 1]);
+        /* an index at or beyond W * H names no pixel: invalid, flow (0, 0) */
+        if ((uint64_t)points[j] < (uint64_t)W * (uint64_t)H) {
+            const int px = (int)(points[j] % (uint32_t)W), py = (int)(points[j] / (uint32_t)W);
+            ok = lk_point(I, J, P, px, py, &flow[2 * j], &flow[2 * j + 1]);
+        }
         if (valid) valid[j] = (uint8_t)ok;
     }
     free(a);

@@ -204,11 +204,12 @@ __global__ __launch_bounds__(256) void k_lk_points(const float* __restrict__ A,
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const uint32_t p = pts[j];
-    const int W = L.w[0];
-    const int py = (int)(p / (uint32_t)W), px = (int)(p - (uint32_t)py * (uint32_t)W);
-    float fx = 0.0f, fy = 0.0f;
+    const uint32_t W = (uint32_t)L.w[0];
     // an index outside the image is invalid (flow 0) rather than read out of bounds
-    const bool ok = py < L.h[0] && lk_point(A, B, L, P, px, py, &fx, &fy);
+    const bool inside = (uint64_t)p < (uint64_t)W * (uint64_t)L.h[0];
+    const int py = inside ? (int)(p / W) : 0, px = inside ? (int)(p - (uint32_t)py * W) : 0;
+    float fx = 0.0f, fy = 0.0f;
+    const bool ok = inside && lk_point(A, B, L, P, px, py, &fx, &fy);
     flow[2 * j] = fx;
     flow[2 * j + 1] = fy;
     if (valid) valid[j] = ok ? 1 : 0;

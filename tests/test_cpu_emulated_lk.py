@@ -42,6 +42,24 @@ def test_emulated_lk_flow_equals_oracle(emu_sim, levels, radius):
     assert valid.sum() > 50 and not valid[-1] and not valid[-2]
 
 
+@pytest.mark.parametrize("shape", [(37, 1), (9, 7)])
+def test_emulated_lk_indices_outside_the_image(emu_sim, shape):
+    """Indices at or beyond W * H (up to 2^32 - 1, where p / W exceeds an int for a one-pixel-
+    wide image) are invalid with flow (0, 0), as in the oracle, with both rejection tests off."""
+    H, W = shape
+    rng = np.random.default_rng(H * 100 + W)
+    f0 = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    f1 = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    pts = np.array([0, W * H - 1, W * H, W * H + 7, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + 5,
+                    2 ** 32 - 1], np.uint32)
+    params = dict(levels=0, radius=1, min_trace=0.0, min_ratio=0.0)
+    flow, valid = emu_sim.lk_flow(f0, f1, pts, **params)
+    ref, rvalid = oracle_lk_flow(f0, f1, pts, **params)
+    np.testing.assert_array_equal(valid, rvalid)
+    np.testing.assert_array_equal(flow.view(np.uint32), ref.view(np.uint32))
+    assert not valid[2:].any() and (flow[2:] == 0).all()
+
+
 @pytest.mark.parametrize("method", [sim.SPARSE, sim.DENSE])
 def test_emulated_estimated_flow_simulation(emu_sim, method):
     """Windows of several intervals (pyramids of every frame of a window), single pushes and

@@ -73,6 +73,25 @@ def test_textureless_and_edge_windows_are_rejected(oracle_mod):
     assert valid[0]
 
 
+OUTSIDE = [1, 2, 1000, 2 ** 31 - 1, 2 ** 31, 2 ** 31 + 5, 2 ** 32 - 1]   # offsets past W * H - 1
+
+
+@pytest.mark.parametrize("shape", [(37, 1), (1, 53), (9, 7)])
+def test_indices_outside_the_image_are_invalid(oracle_mod, shape):
+    """An index at or beyond W * H names no pixel: invalid, flow (0, 0), even with both
+    rejection tests off, and also where p / W exceeds an int (a one-pixel-wide image)."""
+    H, W = shape
+    rng = np.random.default_rng(H * 100 + W)
+    f0 = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    f1 = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    last = W * H - 1
+    pts = np.array([last] + [min(last + d, 2 ** 32 - 1) for d in OUTSIDE], np.uint32)
+    pts[-4:] = np.array(OUTSIDE[-4:], np.uint32)
+    flow, valid = lk_flow(f0, f1, pts, levels=0, radius=1, min_trace=0.0, min_ratio=0.0)
+    assert not valid[1:].any()
+    assert (flow[1:] == 0).all()
+
+
 def test_antisymmetry(oracle_mod):
     H, W = 64, 64
     f0 = _blobs(H, W, [(30, 30), (40, 36)], sigma=6.0)
