@@ -4,7 +4,8 @@
 // (updated in place), two previous-frame buffers (ping-pong; two more for the difference
 // method), the sparse method's selection masks and active list, an event arena of 256 striped
 // sub-arenas, sort buffers, and a FIFO of sorted packed keys awaiting drain.  A push runs in
-// windows of up to 128 intervals: the selection pass (or the frame copies), flow estimation when
+// windows of up to 128 intervals (host inputs are copied to the device one window at a time):
+// the selection pass (or the frame copies), flow estimation when
 // it is on, one chain launch, a read of the overflow counters, re-runs of the chains that ran out
 // of arena space after growing it, the gather of the sub-arenas, and the sort whose last pass
 // appends to the FIFO.  A batched push runs each phase of every stream's window in one fused
