@@ -52,7 +52,8 @@
  * difference method by hand-worked fixtures, the float64 solver, a translating-edge closed form
  * and invariants; for the accumulated frame and the event rate by hand-worked examples and exact
  * rational arithmetic; for Lucas-Kanade by recovered known translations, rejection of flat and
- * edge windows and an independent float64 implementation (tests/lk64.py).  Planted one-token
+ * edge windows, invalidity of indices outside the image and an independent float64
+ * implementation (tests/lk64.py).  Planted one-token
  * mistakes each fail a pin (tests/test_oracle_mutants*.py).  The exact interpolation formula has
  * no anchor in the paper beyond those properties ("parity unpinned" against the paper itself for
  * that formula; pinned through endpoint exactness, the zero-flow and translating-edge closed forms
