@@ -1,0 +1,85 @@
+"""Randomised cross-check of the HIP sources on the CPU emulation against the oracle: each seeded
+case draws an image shape, method, thresholding mode, S, thresholds, initial event capacity, a
+split of the frames into pushes (single frames, chunks, or batched pushes beside a second
+stream) and sometimes flow estimated on the device, and requires the oracle's events and
+reference levels bit for bit.  Complements the hand-picked cases; the product never loads these
+builds."""
+import numpy as np
+import pytest
+
+from oracle.oracle import FLOW_LK
+from paper_2209_04634_amd import sim, synth
+from test_cpu_emulated_kernels import emu_sim, monkeypatch_module, oracle_run  # noqa: F401
+
+N_CASES = 24
+
+
+def draw_case(seed):
+    rng = np.random.default_rng(seed)
+    H = int(rng.choice([1, 2, 5, 16, 23, 40]))
+    W = int(rng.choice([1, 3, 17, 64, 65, 70]))
+    method = int(rng.choice([sim.BASIC, sim.DENSE, sim.SPARSE, sim.DIFFERENCE]))
+    thresh = int(rng.choice([sim.REFERENCE, sim.MEMORYLESS]))
+    S = 1 if method == sim.BASIC else int(rng.choice([1, 2, 5, 11, 32, 33]))
+    transform = int(rng.choice([sim.LOG, sim.LOG, sim.LINEAR]))
+    if transform == sim.LOG:
+        c = float(rng.uniform(0.02, 0.4))
+    else:
+        c = float(rng.uniform(3.0, 40.0))
+    c_neg = c * float(rng.uniform(0.6, 1.6))
+    n_frames = int(rng.integers(2, 10))
+    frames, flows = synth.random_frames(rng, n_frames, H, W, flow_scale=float(rng.uniform(0, 6)))
+    t = np.cumsum(rng.integers(1, 50000, n_frames)).astype(np.int64)
+    cap = int(rng.choice([0, 1, 7, 100]))
+    # pushes: lengths summing to n_frames
+    cuts = sorted(set(rng.integers(1, n_frames, int(rng.integers(0, n_frames))).tolist()))
+    bounds = [0] + cuts + [n_frames]
+    pushes = [(a, b) for a, b in zip(bounds[:-1], bounds[1:])]
+    batched = bool(rng.integers(0, 2))
+    cfg = dict(method=method, thresh_mode=thresh, n_interp=S - 1, transform=transform,
+               c_pos=c, c_neg=c_neg)
+    lk = None
+    if method in (sim.DENSE, sim.SPARSE) and S > 1 and rng.random() < 0.3:
+        lk = dict(levels=int(rng.integers(0, 4)), radius=int(rng.integers(1, 6)))
+    return frames, flows, t, cfg, cap, pushes, batched, lk
+
+
+def flows_of(cfg, flows, a, b, lk):
+    """The flow fields a push of frames[a:b] reads (one per interval it simulates)."""
+    if cfg["method"] == sim.BASIC or lk is not None:
+        return None
+    return flows[max(a - 1, 0):b - 1]
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_random_case_equals_the_oracle(emu_sim, seed):
+    frames, flows, t, cfg, cap, pushes, batched, lk = draw_case(seed)
+    T, H, W = frames.shape
+    ocfg, scfg = dict(cfg), dict(cfg)
+    if lk is not None:
+        ocfg.update(flow_source=FLOW_LK, lk_levels=lk["levels"], lk_radius=lk["radius"])
+        scfg.update(flow_source="lk", lk=lk)
+    supplied = cfg["method"] != sim.BASIC and lk is None
+    ok, oref = oracle_run(frames, flows if supplied else None, t, **ocfg)
+    s = emu_sim.Stream(W, H, event_capacity=cap, **scfg)
+    other = emu_sim.Stream(9, 7, method="dense", c_pos=0.1, c_neg=0.1, n_interp=3)
+    ov = synth.random_frames(np.random.default_rng(seed + 1000), T, 7, 9, flow_scale=3.0)
+    for a, b in pushes:
+        fl = flows_of(cfg, flows, a, b, lk)
+        if fl is not None and len(fl) == 0:
+            fl = None
+        if batched:
+            ofl = ov[1][max(a - 1, 0):b - 1]
+            emu_sim.push_batch([(s, frames[a:b], fl, t[a:b]),
+                                (other, ov[0][a:b], ofl if len(ofl) else None, t[a:b])])
+        else:
+            s.push_frames(frames[a:b], fl, t[a:b])
+    desc = f"seed {seed}: {W}x{H} {cfg} lk {lk} cap {cap} pushes {pushes} batched {batched}"
+    np.testing.assert_array_equal(s.drain_keys(), ok, err_msg=desc)
+    np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32),
+                                  err_msg=desc)
+    if batched:
+        ook, _ = oracle_run(ov[0], ov[1], t, method=sim.DENSE, c_pos=0.1, c_neg=0.1, n_interp=3)
+        np.testing.assert_array_equal(other.drain_keys(), ook, err_msg=desc)
+    s.close()
+    other.close()
