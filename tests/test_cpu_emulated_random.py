@@ -83,3 +83,53 @@ def test_random_case_equals_the_oracle(emu_sim, seed):
         np.testing.assert_array_equal(other.drain_keys(), ook, err_msg=desc)
     s.close()
     other.close()
+
+
+N_SERVER_CASES = 6
+
+
+@pytest.mark.parametrize("seed", range(N_SERVER_CASES))
+def test_random_serving_equals_cameras_alone(emu_sim, seed):
+    """Cameras of random shape, method and thresholding get frames interleaved at random; steps
+    run at random points (and whenever a queue is full).  Every camera's events equal the
+    oracle's for its frames alone."""
+    rng = np.random.default_rng(5000 + seed)
+    depth = int(rng.integers(1, 5))
+    srv = emu_sim.Server(hbm_budget_bytes=1 << 34, max_cameras=6, queue_depth=depth)
+    cams = []
+    for k in range(int(rng.integers(2, 6))):
+        H, W = int(rng.integers(1, 30)), int(rng.integers(1, 70))
+        method = str(rng.choice(["basic", "dense", "sparse", "difference"]))
+        thresh = str(rng.choice(["reference", "memoryless"]))
+        n = int(rng.integers(2, 9))
+        frames, flows = synth.random_frames(rng, n, H, W, flow_scale=3.0)
+        t = np.cumsum(rng.integers(1, 40000, n)).astype(np.int64)
+        cfg = dict(method=method, thresh_mode=thresh, c_pos=0.1, c_neg=0.13, n_interp=4)
+        cam = srv.admit(width=W, height=H, event_capacity=int(rng.choice([0, 3])), **cfg)
+        cams.append(dict(id=cam, frames=frames, flows=flows, t=t, cfg=cfg, next=0))
+    pending = [c for c in cams]
+    while pending:
+        c = pending[int(rng.integers(0, len(pending)))]
+        k = c["next"]
+        fl = None if (c["cfg"]["method"] == "basic" or k == 0) else c["flows"][k - 1]
+        try:
+            srv.submit(c["id"], c["frames"][k], fl, int(c["t"][k]))
+        except emu_sim.SimError as e:
+            assert e.status == emu_sim.E_BUSY
+            srv.step()
+            srv.submit(c["id"], c["frames"][k], fl, int(c["t"][k]))
+        c["next"] += 1
+        if c["next"] == len(c["t"]):
+            pending.remove(c)
+        if rng.random() < 0.3:
+            srv.step()
+    srv.step()
+    for c in cams:
+        m = emu_sim.METHODS[c["cfg"]["method"]]
+        ocfg = dict(c["cfg"], method=m, thresh_mode=emu_sim.THRESH_MODES[c["cfg"]["thresh_mode"]])
+        ok, _ = oracle_run(c["frames"], None if m == sim.BASIC else c["flows"], c["t"], **ocfg)
+        np.testing.assert_array_equal(srv.drain_keys(c["id"]), ok,
+                                      err_msg=f"seed {seed} camera {c['id']} {c['cfg']}")
+    st = srv.stats()
+    assert st["completed"] == sum(len(c["t"]) for c in cams) and st["failed_frames"] == 0
+    srv.close()
