@@ -133,3 +133,37 @@ def test_random_serving_equals_cameras_alone(emu_sim, seed):
     st = srv.stats()
     assert st["completed"] == sum(len(c["t"]) for c in cams) and st["failed_frames"] == 0
     srv.close()
+
+
+N_LK_CASES = 8
+
+
+@pytest.mark.parametrize("seed", range(N_LK_CASES))
+def test_random_flow_estimates_equal_the_oracle(emu_sim, seed):
+    """sim_lk_flow over random shapes and every parameter (levels 0..4, radius 1..15, up to 20
+    iterations, eps and both rejection thresholds), on a smooth moving pattern plus noise, with
+    indices inside and outside the image: bit for bit the oracle's flows and validity."""
+    from oracle.oracle import lk_flow as oracle_lk_flow
+    rng = np.random.default_rng(7000 + seed)
+    H, W = int(rng.integers(1, 48)), int(rng.integers(1, 64))
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    dx, dy = rng.uniform(-4, 4, 2)
+    fx, fy, ph = rng.uniform(0.1, 0.6), rng.uniform(0.1, 0.6), rng.uniform(0, 6)
+
+    def img(ox, oy):
+        v = 128 + 60 * np.sin(fx * (x - ox) + ph) * np.cos(fy * (y - oy)) \
+            + rng.normal(0, 4, (H, W))
+        return np.clip(np.rint(v), 0, 255).astype(np.uint8)
+    f0, f1 = img(0, 0), img(dx, dy)
+    pts = rng.integers(0, W * H + 20, int(rng.integers(1, 200))).astype(np.uint32)
+    params = dict(levels=int(rng.integers(0, 5)), radius=int(rng.integers(1, 16)),
+                  iterations=int(rng.integers(1, 21)), eps=float(rng.choice([0.0, 1e-4, 0.05])),
+                  min_trace=float(rng.choice([0.0, 1.0, 20.0])),
+                  min_ratio=float(rng.choice([0.0, 1e-3, 0.1])))
+    flow, valid = emu_sim.lk_flow(f0, f1, pts, **params)
+    oparams = dict(params)
+    oparams["iters"] = oparams.pop("iterations")
+    ref, rvalid = oracle_lk_flow(f0, f1, pts, **oparams)
+    np.testing.assert_array_equal(valid, rvalid, err_msg=f"seed {seed} {W}x{H} {params}")
+    np.testing.assert_array_equal(flow.view(np.uint32), ref.view(np.uint32),
+                                  err_msg=f"seed {seed} {W}x{H} {params}")
