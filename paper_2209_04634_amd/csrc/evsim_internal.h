@@ -8,6 +8,7 @@
 namespace evsim {
 
 constexpr int kSimThreads = 256;     // pixels per simulation tile (one per thread)
+constexpr int kMaxSubIntervals = 256;   // S = n_interp + 1 <= 256
 constexpr int kMaxStash = 31;        // interior samples kept in LDS per pixel (S - 1 <= 31)
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;

@@ -56,11 +56,11 @@ __device__ __forceinline__ float bilinear(const uint8_t* __restrict__ F, const f
     return gy * top + fy * bot;
 }
 
-// Interior sample V_k (0 < k < S) of the flow-guided blend between frames F0 and F1.
+// Interior sample V_k (0 < k < S) of the flow-guided blend between frames F0 and F1, at
+// tau = k / S (one fp32 division, taken from the block's table).
 __device__ __forceinline__ float interp_sample(const uint8_t* F0, const uint8_t* F1,
                                                const float* lut, int W, int H, int x, int y,
-                                               float u, float v, int k, int S) {
-    const float tau = (float)k / (float)S;
+                                               float u, float v, float tau) {
     const float om = 1.0f - tau;
     const float a = bilinear(F0, lut, W, H, (float)x - tau * u, (float)y - tau * v);
     const float b = bilinear(F1, lut, W, H, (float)x + om * u, (float)y + om * v);
@@ -72,6 +72,7 @@ struct PixelCtx {
     const uint8_t* F1;
     const float* lut;
     const float* stash;     // column of this thread's interior samples (stride 256) or null
+    const float* tau;       // tau[k] = k / S, k = 0..S (LDS table of the block)
     int W, H, x, y, S;
     float u, v;
     const uint8_t* Fm;      // difference method: the frame before F0
@@ -80,7 +81,7 @@ struct PixelCtx {
 __device__ __forceinline__ float sample_k(const PixelCtx& c, int k, float A1) {
     if (k == c.S) return A1;
     if (c.stash) return c.stash[(k - 1) * kSimThreads];
-    return interp_sample(c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, k, c.S);
+    return interp_sample(c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, c.tau[k]);
 }
 
 // Threshold crossings of one pixel's series V_0 = A0 .. V_S = A1 against reference level R.
@@ -159,9 +160,8 @@ __device__ __forceinline__ float bilinear_diff(const uint8_t* __restrict__ Fa,
 // the same flow-guided blend as interp_sample, between D1 = T[F0] - T[Fm] and D2 = T[F1] - T[F0].
 __device__ __forceinline__ float interp_diff_sample(const uint8_t* Fm, const uint8_t* F0,
                                                     const uint8_t* F1, const float* lut, int W,
-                                                    int H, int x, int y, float u, float v, int k,
-                                                    int S) {
-    const float tau = (float)k / (float)S;
+                                                    int H, int x, int y, float u, float v,
+                                                    float tau) {
     const float om = 1.0f - tau;
     const float a = bilinear_diff(Fm, F0, lut, W, H, (float)x - tau * u, (float)y - tau * v);
     const float b = bilinear_diff(F0, F1, lut, W, H, (float)x + om * u, (float)y + om * v);
@@ -173,9 +173,10 @@ __device__ __forceinline__ float sample_mode(const PixelCtx& c, int k, float A1)
     if (k == c.S) return A1;
     if (c.stash) return c.stash[(k - 1) * kSimThreads];
     if constexpr (MODE == kModeDifference)
-        return interp_diff_sample(c.Fm, c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, k, c.S);
+        return interp_diff_sample(c.Fm, c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v,
+                                  c.tau[k]);
     else
-        return interp_sample(c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, k, c.S);
+        return interp_sample(c.F0, c.F1, c.lut, c.W, c.H, c.x, c.y, c.u, c.v, c.tau[k]);
 }
 
 // Memoryless thresholding of one pixel's interval (the paper's Sec. III-A equations taken
@@ -200,7 +201,7 @@ __device__ __forceinline__ int flips(const PixelCtx& c, float A0, float A1, floa
             pol = -1;
         if (pol != 0) {
             if (WRITE) {
-                const float phi = (float)(k + 1) / (float)c.S;
+                const float phi = c.tau[k + 1];   // (k + 1) / S
                 const uint64_t trel = (uint64_t)(int64_t)floorf(phi * delta);
                 out[n] = keyhi | (trel << pbits) | pixkey | (pol > 0 ? 1ull : 0ull);
             }
@@ -372,9 +373,11 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
 template <int MODE>
 __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
     extern __shared__ float smem[];
+    __shared__ float tau[kMaxSubIntervals + 1];   // k / S for k = 0..S, shared by every sample
     float* lut = smem;
     const int tid = threadIdx.x, lane = tid & 63;
     lut[tid] = a.lut[tid];
+    for (int k = tid; k <= a.S; k += kSimThreads) tau[k] = (float)k / (float)a.S;
     __syncthreads();
 
     const int slot = bid * kSimThreads + tid;
@@ -418,7 +421,7 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
         int n = 0;
         float Rn = R, A0 = 0.0f, A1 = 0.0f, delta = 0.0f;
         PixelCtx c;
-        c.W = a.W; c.H = a.H; c.x = x; c.y = y; c.S = a.S; c.lut = lut;
+        c.W = a.W; c.H = a.H; c.x = x; c.y = y; c.S = a.S; c.lut = lut; c.tau = tau;
         c.u = 0.0f; c.v = 0.0f; c.stash = nullptr;
         c.F0 = i == 0 ? a.prev : a.frames + (int64_t)(i - 1) * a.fstride;
         c.F1 = a.frames + (int64_t)i * a.fstride;
@@ -442,10 +445,10 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
                 for (int k = 1; k <= stash_n; ++k) {
                     if constexpr (MODE == kModeDifference)
                         stash[(k - 1) * kSimThreads] = interp_diff_sample(
-                            c.Fm, c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
+                            c.Fm, c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, tau[k]);
                     else
                         stash[(k - 1) * kSimThreads] =
-                            interp_sample(c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, k, a.S);
+                            interp_sample(c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, tau[k]);
                 }
                 if (stash_n) c.stash = stash;
             }
