@@ -167,3 +167,4 @@ def test_random_flow_estimates_equal_the_oracle(emu_sim, seed):
     np.testing.assert_array_equal(valid, rvalid, err_msg=f"seed {seed} {W}x{H} {params}")
     np.testing.assert_array_equal(flow.view(np.uint32), ref.view(np.uint32),
                                   err_msg=f"seed {seed} {W}x{H} {params}")
+
