@@ -36,34 +36,56 @@ __device__ __forceinline__ int block_scan_256(int v, int* wsum, int* total) {
     return before + inc - v;
 }
 
-// Clamp-to-edge bilinear sample of T[F] at (sx, sy).
-__device__ __forceinline__ float bilinear(const uint8_t* __restrict__ F, const float* lut, int W,
-                                          int H, float sx, float sy) {
+// Clamp-to-edge bilinear footprint of the sample position (sx, sy): the offsets of its four
+// texels and its weights.  Callers load every texel of a sample before blending any, so that
+// the loads of one sample are in flight together.
+struct BilTap {
+    int64_t o00, o01, o10, o11;
+    float fx, fy, gx, gy;
+};
+
+__device__ __forceinline__ BilTap bil_tap(int W, int H, float sx, float sy) {
     sx = fminf(fmaxf(sx, 0.0f), (float)(W - 1));
     sy = fminf(fmaxf(sy, 0.0f), (float)(H - 1));
     const int x0 = (int)floorf(sx);
     const int y0 = (int)floorf(sy);
-    const float fx = sx - (float)x0;
-    const float fy = sy - (float)y0;
+    BilTap t;
+    t.fx = sx - (float)x0;
+    t.fy = sy - (float)y0;
     const int x1 = min(x0 + 1, W - 1);
     const int y1 = min(y0 + 1, H - 1);
-    const float gx = 1.0f - fx;
-    const float gy = 1.0f - fy;
-    const uint8_t* r0 = F + (int64_t)y0 * W;
-    const uint8_t* r1 = F + (int64_t)y1 * W;
-    const float top = gx * lut[r0[x0]] + fx * lut[r0[x1]];
-    const float bot = gx * lut[r1[x0]] + fx * lut[r1[x1]];
-    return gy * top + fy * bot;
+    t.gx = 1.0f - t.fx;
+    t.gy = 1.0f - t.fy;
+    const int64_t r0 = (int64_t)y0 * W;
+    const int64_t r1 = (int64_t)y1 * W;
+    t.o00 = r0 + x0;
+    t.o01 = r0 + x1;
+    t.o10 = r1 + x0;
+    t.o11 = r1 + x1;
+    return t;
+}
+
+// Bilinear blend of four texel values v (already transformed) with the tap's weights.
+__device__ __forceinline__ float bil_blend(const BilTap& t, float v00, float v01, float v10,
+                                           float v11) {
+    const float top = t.gx * v00 + t.fx * v01;
+    const float bot = t.gx * v10 + t.fx * v11;
+    return t.gy * top + t.fy * bot;
 }
 
 // Interior sample V_k (0 < k < S) of the flow-guided blend between frames F0 and F1, at
-// tau = k / S (one fp32 division, taken from the block's table).
+// tau = k / S (one fp32 division, taken from the block's table): clamp-to-edge bilinear samples
+// of T[F0] at p - tau F and of T[F1] at p + (1 - tau) F.
 __device__ __forceinline__ float interp_sample(const uint8_t* F0, const uint8_t* F1,
                                                const float* lut, int W, int H, int x, int y,
                                                float u, float v, float tau) {
     const float om = 1.0f - tau;
-    const float a = bilinear(F0, lut, W, H, (float)x - tau * u, (float)y - tau * v);
-    const float b = bilinear(F1, lut, W, H, (float)x + om * u, (float)y + om * v);
+    const BilTap ta = bil_tap(W, H, (float)x - tau * u, (float)y - tau * v);
+    const BilTap tb = bil_tap(W, H, (float)x + om * u, (float)y + om * v);
+    const uint32_t a00 = F0[ta.o00], a01 = F0[ta.o01], a10 = F0[ta.o10], a11 = F0[ta.o11];
+    const uint32_t b00 = F1[tb.o00], b01 = F1[tb.o01], b10 = F1[tb.o10], b11 = F1[tb.o11];
+    const float a = bil_blend(ta, lut[a00], lut[a01], lut[a10], lut[a11]);
+    const float b = bil_blend(tb, lut[b00], lut[b01], lut[b10], lut[b11]);
     return om * a + tau * b;
 }
 
@@ -130,41 +152,24 @@ __device__ __forceinline__ int crossings(const PixelCtx& c, float R, float A0, f
     return n;
 }
 
-// Clamp-to-edge bilinear sample at (sx, sy) of the difference frame T[Fb] - T[Fa] (each texel
-// difference is one fp32 subtraction, then the same blend as `bilinear`).
-__device__ __forceinline__ float bilinear_diff(const uint8_t* __restrict__ Fa,
-                                               const uint8_t* __restrict__ Fb, const float* lut,
-                                               int W, int H, float sx, float sy) {
-    sx = fminf(fmaxf(sx, 0.0f), (float)(W - 1));
-    sy = fminf(fmaxf(sy, 0.0f), (float)(H - 1));
-    const int x0 = (int)floorf(sx);
-    const int y0 = (int)floorf(sy);
-    const float fx = sx - (float)x0;
-    const float fy = sy - (float)y0;
-    const int x1 = min(x0 + 1, W - 1);
-    const int y1 = min(y0 + 1, H - 1);
-    const float gx = 1.0f - fx;
-    const float gy = 1.0f - fy;
-    const int64_t r0 = (int64_t)y0 * W;
-    const int64_t r1 = (int64_t)y1 * W;
-    const float d00 = lut[Fb[r0 + x0]] - lut[Fa[r0 + x0]];
-    const float d01 = lut[Fb[r0 + x1]] - lut[Fa[r0 + x1]];
-    const float d10 = lut[Fb[r1 + x0]] - lut[Fa[r1 + x0]];
-    const float d11 = lut[Fb[r1 + x1]] - lut[Fa[r1 + x1]];
-    const float top = gx * d00 + fx * d01;
-    const float bot = gx * d10 + fx * d11;
-    return gy * top + fy * bot;
-}
-
 // Interior interpolated difference frame D_k (0 < k < S) of the difference method (Sec. III-C):
-// the same flow-guided blend as interp_sample, between D1 = T[F0] - T[Fm] and D2 = T[F1] - T[F0].
+// the same flow-guided blend as interp_sample, between D1 = T[F0] - T[Fm] and D2 = T[F1] - T[F0],
+// each texel difference one fp32 subtraction before the bilinear blend.
 __device__ __forceinline__ float interp_diff_sample(const uint8_t* Fm, const uint8_t* F0,
                                                     const uint8_t* F1, const float* lut, int W,
                                                     int H, int x, int y, float u, float v,
                                                     float tau) {
     const float om = 1.0f - tau;
-    const float a = bilinear_diff(Fm, F0, lut, W, H, (float)x - tau * u, (float)y - tau * v);
-    const float b = bilinear_diff(F0, F1, lut, W, H, (float)x + om * u, (float)y + om * v);
+    const BilTap ta = bil_tap(W, H, (float)x - tau * u, (float)y - tau * v);
+    const BilTap tb = bil_tap(W, H, (float)x + om * u, (float)y + om * v);
+    const uint32_t m00 = Fm[ta.o00], m01 = Fm[ta.o01], m10 = Fm[ta.o10], m11 = Fm[ta.o11];
+    const uint32_t p00 = F0[ta.o00], p01 = F0[ta.o01], p10 = F0[ta.o10], p11 = F0[ta.o11];
+    const uint32_t q00 = F0[tb.o00], q01 = F0[tb.o01], q10 = F0[tb.o10], q11 = F0[tb.o11];
+    const uint32_t c00 = F1[tb.o00], c01 = F1[tb.o01], c10 = F1[tb.o10], c11 = F1[tb.o11];
+    const float a = bil_blend(ta, lut[p00] - lut[m00], lut[p01] - lut[m01], lut[p10] - lut[m10],
+                              lut[p11] - lut[m11]);
+    const float b = bil_blend(tb, lut[c00] - lut[q00], lut[c01] - lut[q01], lut[c10] - lut[q10],
+                              lut[c11] - lut[q11]);
     return om * a + tau * b;
 }
 
