@@ -295,15 +295,9 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
     for (int w = 0; w < kMaskWords && w * 32 < a.K; ++w) {
         uint32_t mw[4] = {0u, 0u, 0u, 0u};
         const int jend = min(32, a.K - w * 32);
-#pragma unroll 8
-        for (int jj = 0; jj < jend; ++jj) {
-            const uint8_t* F = a.frames + (int64_t)(w * 32 + jj) * a.fstride + base;
-            uint32_t v = 0;
-            if (VEC && cnt == 4) {
-                v = *(const uint32_t*)F;
-            } else {
-                for (int q = 0; q < cnt; ++q) v |= (uint32_t)F[q] << (8 * q);
-            }
+        const uint8_t* Fw = a.frames + (int64_t)(w * 32) * a.fstride + base;
+        // one frame's four pixels: transform, compare with the previous frame, set bit jj
+        auto step = [&](uint32_t v, int jj) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float A1 = lut[(v >> (8 * q)) & 255u];
@@ -311,6 +305,19 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
                 A0[q] = A1;
             }
             last = v;
+        };
+        if (VEC && cnt == 4) {
+            // branch-free, so that the unrolled loads of several frames are in flight together
+#pragma unroll 8
+            for (int jj = 0; jj < jend; ++jj)
+                step(*(const uint32_t*)(Fw + (int64_t)jj * a.fstride), jj);
+        } else {
+            for (int jj = 0; jj < jend; ++jj) {
+                const uint8_t* F = Fw + (int64_t)jj * a.fstride;
+                uint32_t v = 0;
+                for (int q = 0; q < cnt; ++q) v |= (uint32_t)F[q] << (8 * q);
+                step(v, jj);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
