@@ -633,10 +633,20 @@ __device__ __forceinline__ void hist_block(const uint64_t* __restrict__ keys,
     h[tid] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)bid * kSortTile;
-#pragma unroll 4
-    for (int j = 0; j < kSortItems; ++j) {
-        const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    if (base < n) {
+        // every key of the thread is loaded before any is counted (indices past the end re-read
+        // the last key and are not counted), so that the loads are in flight together
+        uint64_t kv[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
+            kv[j] = keys[idx < n ? idx : n - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
+            if (idx < n) atomicAdd(&h[(kv[j] >> shift) & 255u], 1u);
+        }
     }
     __syncthreads();
     hist[(size_t)tid * nblocks + bid] = h[tid];
@@ -703,7 +713,15 @@ __device__ __forceinline__ void scatter_block(
     s_base[tid] = (uint32_t)dex + hist[(size_t)tid * nblocks + bid];
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     const uint64_t base = (uint64_t)bid * kSortTile;
+    // each round loads the thread's key of the next round before ranking its own (indices past
+    // the end re-read the last key and are not used), so that the load overlaps a whole round
+    uint64_t next = in[base + tid < n ? base + tid : n - 1];
     for (int j = 0; j < kSortItems; ++j) {
+        const uint64_t mine = next;
+        if (j + 1 < kSortItems) {
+            const uint64_t idx1 = base + (uint64_t)(j + 1) * kSortThreads + tid;
+            next = in[idx1 < n ? idx1 : n - 1];
+        }
         s_wcnt[0][tid] = 0;
         s_wcnt[1][tid] = 0;
         s_wcnt[2][tid] = 0;
@@ -711,7 +729,7 @@ __device__ __forceinline__ void scatter_block(
         __syncthreads();
         const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
         const bool valid = idx < n;
-        const uint64_t key = valid ? in[idx] : 0ull;
+        const uint64_t key = valid ? mine : 0ull;
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
