@@ -440,6 +440,16 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
         if constexpr (MODE == kModeDifference)
             c.Fm = i == 0 ? a.prev2 : (i == 1 ? a.prev : a.frames + (int64_t)(i - 2) * a.fstride);
         if (have) {
+            // frame methods: the flow vector is loaded before the frame bytes, so that all of
+            // the interval's loads at this pixel are in flight together (the difference method
+            // keeps the later load: the earlier one costs it a wave of occupancy)
+            if constexpr (MODE != kModeDifference) {
+                if (a.S > 1) {
+                    const float* fl = a.flows + (int64_t)i * a.flstride + 2 * (int64_t)p;
+                    c.u = fl[0];
+                    c.v = fl[1];
+                }
+            }
             A0 = lut[c.F0[p]];
             A1 = lut[c.F1[p]];
             if constexpr (MODE == kModeDifference) {
@@ -451,9 +461,11 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
             }
             delta = a.delta[i];
             if (a.S > 1) {
-                const float* fl = a.flows + (int64_t)i * a.flstride + 2 * (int64_t)p;
-                c.u = fl[0];
-                c.v = fl[1];
+                if constexpr (MODE == kModeDifference) {
+                    const float* fl = a.flows + (int64_t)i * a.flstride + 2 * (int64_t)p;
+                    c.u = fl[0];
+                    c.v = fl[1];
+                }
                 for (int k = 1; k <= stash_n; ++k) {
                     if constexpr (MODE == kModeDifference)
                         stash[(k - 1) * kSimThreads] = interp_diff_sample(
