@@ -303,7 +303,7 @@ ASAN_SCRIPT = textwrap.dedent("""
     f, fl = synth.random_frames(rng, 3, 5, 7)
     cases.append((f, fl, np.array([0, 10, 20]), dict(method=1, n_interp=40, event_capacity=1)))
     from test_cpu_emulated_kernels import _camera_videos
-    cams = _camera_videos(sim)
+    cams = _camera_videos(sim)[:2]     # two cameras of different shape and method suffice here
     srv = sim.Server(hbm_budget_bytes=1 << 34, max_cameras=4, queue_depth=3)
     ids = [srv.admit(width=c["W"], height=c["H"], method=c["method"], c_pos=0.15, c_neg=0.15,
                      n_interp=4, event_capacity=8) for c in cams]
