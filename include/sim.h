@@ -206,7 +206,9 @@ typedef struct sim_frames {
  * Validation of every entry (and a handle listed twice, SIM_E_INVAL) happens before any work is
  * queued; on a validation error nothing changes.  Staging and buffer reservation follow per
  * entry (an entry failing there stays untouched while the others proceed).  A failure inside the
- * fused launches poisons every stream of that window.  Errors are reported per entry in `status`;
+ * fused launches poisons every stream of that window; a host allocation failure between windows
+ * returns SIM_E_NOMEM and poisons every stream that still had a window to run.  Errors are
+ * reported per entry in `status`;
  * returns SIM_OK or the first error.  One batched push runs at a time per process. */
 int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n);
 
