@@ -316,32 +316,58 @@ def legs_child(args):
     """The optional legs, run in a child process of the default bench so that the main line is
     measured and printed whatever happens here: the memoryless, difference-frame and
     estimated-flow workloads; 64 mixed-resolution streams batched against plain pushes; the
-    serving loop with 256 cameras."""
+    serving loop with 256 cameras.  Each leg prints its own JSON line when it ends (an error
+    inside a leg is recorded and the next leg runs), so finished legs survive a later failure."""
     import torch
     from paper_2209_04634_amd import sim, synth
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    res = {}
-    for name in LEG_WORKLOADS:
+
+    def leg(name, fn):
         t0 = time.perf_counter()
+        try:
+            out = fn()
+        except Exception as e:   # recorded in the bench line; the remaining legs still run
+            out = {"error": repr(e)[:400]}
+        if isinstance(out, dict):
+            out.setdefault("wall_s", round(time.perf_counter() - t0, 1))
+        print(json.dumps({name: out}), flush=True)
+        print(f"leg {name} done", file=sys.stderr, flush=True)
+
+    def workload(name):
         m = measure(name, 5, 2, sim, synth, torch, dev, plain=False)
         wl = m["_wl"]
-        res[name] = {k: v for k, v in m.items() if not k.startswith("_") and v is not None}
-        res[name]["config"] = {"method": wl["method"], "c": wl["c"], "n_interp": wl["n_interp"],
-                               "thresh_mode": wl.get("thresh", "reference"),
-                               "flow_source": wl.get("flow", "supplied"),
-                               "width": m["_shape"][2], "height": m["_shape"][1],
-                               "frames": m["_shape"][0]}
-        res[name]["wall_s"] = round(time.perf_counter() - t0, 1)
-        print(f"leg {name} done", file=sys.stderr, flush=True)
+        r = {k: v for k, v in m.items() if not k.startswith("_") and v is not None}
+        r["config"] = {"method": wl["method"], "c": wl["c"], "n_interp": wl["n_interp"],
+                       "thresh_mode": wl.get("thresh", "reference"),
+                       "flow_source": wl.get("flow", "supplied"),
+                       "width": m["_shape"][2], "height": m["_shape"][1],
+                       "frames": m["_shape"][0]}
+        return r
+
+    for name in LEG_WORKLOADS:
+        leg(name, lambda name=name: workload(name))
     args.batched = args.batched or 64
-    res["batched_vs_plain_streams"] = batched_leg(args, sim, synth, torch, dev)
-    print("leg batched done", file=sys.stderr, flush=True)
+    leg("batched_vs_plain_streams", lambda: batched_leg(args, sim, synth, torch, dev))
     args.cameras = 256
     args.serve = args.serve or 10.0
-    res["serving"] = serve_leg(args, sim, synth, torch, dev)
-    print("leg serving done", file=sys.stderr, flush=True)
-    print(json.dumps(res), flush=True)
+    leg("serving", lambda: serve_leg(args, sim, synth, torch, dev))
+
+
+def merge_leg_lines(text):
+    """The legs' JSON lines (one object per finished leg) merged into one object."""
+    res = {}
+    for line in (text or "").splitlines():
+        line = line.strip()
+        if not line.startswith("{"):
+            continue
+        try:
+            obj = json.loads(line)
+        except ValueError:
+            continue
+        if isinstance(obj, dict):
+            res.update(obj)
+    return res
 
 
 def run_legs(timeout_s):
@@ -349,16 +375,19 @@ def run_legs(timeout_s):
     cmd = [sys.executable, os.path.abspath(__file__), "--legs-child"]
     try:
         r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout_s)
-    except subprocess.TimeoutExpired:
-        return {"error": f"legs did not finish within {timeout_s} s"}
+    except subprocess.TimeoutExpired as e:
+        out = e.stdout.decode() if isinstance(e.stdout, bytes) else e.stdout
+        res = merge_leg_lines(out)
+        res["error"] = f"legs did not finish within {timeout_s} s"
+        return res
     sys.stderr.write(r.stderr[-2000:])
+    res = merge_leg_lines(r.stdout)
     if r.returncode != 0:
-        return {"error": f"legs exited with status {r.returncode}",
-                "stderr_tail": r.stderr[-600:]}
-    try:
-        return json.loads(r.stdout.strip().splitlines()[-1])
-    except (ValueError, IndexError):
-        return {"error": "legs printed no result"}
+        res["error"] = f"legs exited with status {r.returncode}"
+        res["stderr_tail"] = r.stderr[-600:]
+    elif not res:
+        res["error"] = "legs printed no result"
+    return res
 
 
 def main():
