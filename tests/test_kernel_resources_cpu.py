@@ -1,0 +1,75 @@
+"""Resources of the gfx950 kernels, read from the compiler's own assembly of the HIP sources
+(built here with the library's flags; no GPU needed): no kernel spills to scratch, the hot kernels
+keep the occupancy their design assumes, no packed-fp32 instruction is emitted (the build
+disables them), and the sources compile without warnings."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2209_04634_amd import build as hipbuild
+
+CSRC = os.path.join(hipbuild.ROOT, "paper_2209_04634_amd", "csrc")
+KERNEL_SOURCES = ["evsim_kernels.hip", "evsim_lk.hip"]
+
+# waves per SIMD the hot kernels must keep (their current values; lower only on purpose)
+MIN_OCCUPANCY = {
+    "_ZN5evsim7k_chainILi0EEEvNS_9ChainArgsE": 6,          # reference-level chain
+    "_ZN5evsim7k_chainILi1EEEvNS_9ChainArgsE": 7,          # memoryless chain
+    "_ZN5evsim7k_chainILi2EEEvNS_9ChainArgsE": 6,          # difference-frame chain
+    "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 8,       # selection pass
+    "_ZN5evsim12k_radix_histEPKmPKyiPji": 8,
+    "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 8,
+    "_ZN5evsim8k_gatherEPKmmPKyPmPy": 8,
+}
+
+
+def device_assembly(tmp_path):
+    hipcc = hipbuild.hipcc()
+    if not os.path.exists(hipcc) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    flags = [f for f in hipbuild.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    out = {}
+    for src in KERNEL_SOURCES:
+        asm = tmp_path / (src + ".s")
+        res = subprocess.run([hipcc, *flags, "--cuda-device-only", "-S", "-I",
+                              os.path.join(hipbuild.ROOT, "include"),
+                              os.path.join(CSRC, src), "-o", str(asm)],
+                             capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr[-3000:]
+        noise = "packed-fp32-ops' is not a recognized feature"
+        warnings = [l for l in res.stderr.splitlines() if "warning" in l and noise not in l]
+        assert not warnings, "\n".join(warnings)
+        out[src] = asm.read_text()
+    return out
+
+
+def kernels(asm):
+    """{kernel symbol: (vgprs, occupancy, scratch bytes, body text)} of every kernel."""
+    res = {}
+    for m in re.finditer(r"^(_ZN5evsim\w+):\s*; @", asm, re.M):
+        end = asm.index(".Lfunc_end", m.start())
+        tail = asm[end:end + 4000]
+        vg = re.search(r"; NumVgprs: (\d+)", tail)
+        if not vg:
+            continue
+        res[m.group(1)] = (int(vg.group(1)), int(re.search(r"; Occupancy: (\d+)", tail).group(1)),
+                           int(re.search(r"; ScratchSize: (\d+)", tail).group(1)),
+                           asm[m.start():end])
+    return res
+
+
+def test_kernel_resources(tmp_path):
+    found = {}
+    for src, asm in device_assembly(tmp_path).items():
+        found.update(kernels(asm))
+    assert len(found) >= 25, sorted(found)
+    for name, (vgprs, occ, scratch, body) in found.items():
+        assert scratch == 0, f"{name} spills: {scratch} bytes of scratch ({vgprs} VGPRs)"
+        for op in ("v_pk_add_f32", "v_pk_mul_f32", "v_pk_fma_f32"):
+            assert op not in body, f"{name} uses {op}"
+    for name, floor in MIN_OCCUPANCY.items():
+        assert name in found, name
+        assert found[name][1] >= floor, f"{name}: {found[name][1]} waves per SIMD < {floor}"
