@@ -116,6 +116,13 @@ hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
 // reserve[s] = min(reserve[s], cap) for every stripe (before re-running failed chains).
 hipError_t launch_clamp(unsigned long long* reserve, uint64_t cap, hipStream_t stream);
 hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream_t stream);
+// Zero-fills `bytes` (a multiple of 4) at p with a kernel (no memset node in a captured graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
+// Clears a window's counters[4], the reservation counters, n_active (if not null: sparse) and
+// resume[npix] (if not null: the other methods) in one launch.
+hipError_t launch_prep_window(unsigned long long* counters, unsigned long long* reserve,
+                              unsigned int* n_active, int* resume, int64_t npix,
+                              hipStream_t stream);
 // Sorts keys[0, *n) on bits [0, nbits) (stable LSD radix, 8-bit digits); the last pass writes
 // into `out` converted by `cv`.  The count is read on the device; grids are sized for n_max.
 // `alt` holds n_max keys; `hist` holds sort_hist_entries(n_max) counters and `totals` 256.

@@ -775,6 +775,36 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // ------------------------------------------------------------------------------------------
+// Clearing, as kernels rather than memset nodes, so that pushes recorded into a HIP graph replay
+// correctly.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = 0u;
+}
+
+// Start of a window: its counters, the reservation counters, the active-list counters (sparse)
+// and the per-pixel resume points (every other method).
+__global__ __launch_bounds__(256) void k_prep_window(unsigned long long* __restrict__ counters,
+                                                     unsigned long long* __restrict__ reserve,
+                                                     unsigned int* __restrict__ n_active,
+                                                     int* __restrict__ resume, int64_t npix) {
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0) {
+        if (tid < 4) counters[tid] = 0ull;
+        for (int i = tid; i < kArenaStripes * kCounterStride; i += 256) reserve[i] = 0ull;
+        if (n_active)
+            for (int i = tid; i < kActStripes * kCounterStride; i += 256) n_active[i] = 0u;
+    }
+    if (resume) {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < npix; i += stride)
+            resume[i] = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------------
 hipError_t launch_init(const uint8_t* frame, const float* lut, float* lref, uint8_t* prev,
@@ -832,6 +862,26 @@ hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
 
 hipError_t launch_clamp(unsigned long long* reserve, uint64_t cap, hipStream_t stream) {
     hipLaunchKernelGGL(k_clamp, dim3(1), dim3(kArenaStripes), 0, stream, reserve, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
+    const uint64_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, stream, (uint32_t*)p,
+                       words);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_window(unsigned long long* counters, unsigned long long* reserve,
+                              unsigned int* n_active, int* resume, int64_t npix,
+                              hipStream_t stream) {
+    const int64_t blocks = resume ? std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256,
+                                                                            1024))
+                                  : 1;
+    hipLaunchKernelGGL(k_prep_window, dim3((unsigned)blocks), dim3(256), 0, stream, counters,
+                       reserve, n_active, resume, npix);
     return hipGetLastError();
 }
 

@@ -438,19 +438,13 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
                               s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->d_tbase, s->h_tbase, K * sizeof(int64_t), hipMemcpyHostToDevice,
                               s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, 4 * sizeof(unsigned long long), s->stream));
-    HIP_TRY(s, hipMemsetAsync(s->d_reserve, 0,
-                              (size_t)kArenaStripes * kCounterStride * sizeof(unsigned long long),
-                              s->stream));
     const bool sparse = s->cfg.method == SIM_SPARSE;
+    HIP_TRY(s, launch_prep_window(s->d_counters, s->d_reserve, sparse ? s->d_nact : nullptr,
+                                  sparse ? nullptr : s->d_resume, s->npix, s->stream));
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[0], s->stream));
     if (sparse) {
-        HIP_TRY(s, hipMemsetAsync(s->d_nact, 0,
-                                  (size_t)kActStripes * kCounterStride * sizeof(unsigned int),
-                                  s->stream));
         HIP_TRY(s, launch_select(sa, s->stream));
     } else {
-        HIP_TRY(s, hipMemsetAsync(s->d_resume, 0, (size_t)s->npix * sizeof(int), s->stream));
         HIP_TRY(s, launch_copy_u8(frames + (size_t)(K - 1) * s->npix, sa.prev_out, s->npix,
                                   s->stream));
         if (s->cfg.method == SIM_DIFFERENCE) {
@@ -503,7 +497,7 @@ int win_check(sim_stream* s) {
         // finished chains have already advanced their reference levels: no roll-back
         if (rc) return fail_mid_push(s, rc, "event arena growth");
         HIP_TRY(s, launch_clamp(s->d_reserve, old, s->stream));
-        HIP_TRY(s, hipMemsetAsync(s->d_counters, 0, sizeof(unsigned long long), s->stream));
+        HIP_TRY(s, launch_zero(s->d_counters, sizeof(unsigned long long), s->stream));
         s->stats.retries++;
         a.arena = s->d_arena;
         a.stripe_cap = s->stripe_cap;
@@ -1141,9 +1135,9 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     }
     if (hipMemcpyAsync(s->d_lut, s->lut_host, sizeof(s->lut_host), hipMemcpyHostToDevice,
                        s->stream) != hipSuccess ||
-        hipMemsetAsync(s->d_stats, 0,
-                       (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
-                       s->stream) != hipSuccess ||
+        launch_zero(s->d_stats,
+                    (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
+                    s->stream) != hipSuccess ||
         hipStreamSynchronize(s->stream) != hipSuccess) {
         free_stream(s);
         return SIM_E_HIP;
@@ -1171,9 +1165,9 @@ int sim_reset(sim_stream* s) {
 int sim_clear_stats(sim_stream* s) {
     if (!s) return SIM_E_INVAL;
     if (s->poisoned) return SIM_E_POISONED;
-    HIP_TRY(s, hipMemsetAsync(s->d_stats, 0,
-                              (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
-                              s->stream));
+    HIP_TRY(s, launch_zero(s->d_stats,
+                           (size_t)kStatStripes * kCounterStride * sizeof(unsigned long long),
+                           s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     memset(&s->stats, 0, sizeof(s->stats));
     s->stats.event_capacity = s->stripe_cap * kArenaStripes;
@@ -1379,7 +1373,7 @@ int sim_event_rate(sim_stream* s, int64_t t_begin, int64_t t_end, double* mean, 
     int rc = grow(s, &s->d_acc, &s->acc_cap, 2 * plane, 0);
     if (!rc) rc = grow(s, &s->d_moments, &s->moments_cap, 2 * (uint64_t)moments_blocks(plane), 0);
     if (rc) return rc;
-    HIP_TRY(s, hipMemsetAsync(s->d_acc, 0, 2 * plane * sizeof(uint32_t), s->stream));
+    HIP_TRY(s, launch_zero(s->d_acc, 2 * plane * sizeof(uint32_t), s->stream));
     uint64_t lo = 0, hi = 0;
     const uint64_t n = s->fifo_tail - s->fifo_head;
     if (n && key_window(s, t_begin, t_end, &lo, &hi))
