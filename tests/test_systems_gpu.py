@@ -201,3 +201,41 @@ def test_c5_serving_256_cameras():
                                 c_pos=0.2, c_neg=0.2)
             np.testing.assert_array_equal(got, ok, err_msg=str(cam))
     srv.close()
+
+
+MODES_MIX = [
+    # (W, H, stream options, oracle options, flows supplied)
+    (346, 260, dict(method="dense", thresh_mode="memoryless", c_pos=0.03, c_neg=0.03),
+     dict(method=sim.DENSE, thresh_mode=sim.MEMORYLESS, c_pos=0.03, c_neg=0.03), True),
+    (640, 480, dict(method="sparse", thresh_mode="memoryless", c_pos=0.03, c_neg=0.03),
+     dict(method=sim.SPARSE, thresh_mode=sim.MEMORYLESS, c_pos=0.03, c_neg=0.03), True),
+    (346, 260, dict(method="difference", c_pos=0.2, c_neg=0.2),
+     dict(method=sim.DIFFERENCE, c_pos=0.2, c_neg=0.2), True),
+    (640, 480, dict(method="sparse", flow_source="lk", c_pos=0.15, c_neg=0.15),
+     dict(method=sim.SPARSE, flow_source=1, c_pos=0.15, c_neg=0.15), False),
+    (240, 180, dict(method="dense", c_pos=0.15, c_neg=0.15, event_capacity=64),
+     dict(method=sim.DENSE, c_pos=0.15, c_neg=0.15), True),
+]
+
+
+def test_batched_push_every_mode_equals_streams_alone():
+    """One fused batch holding every thresholding mode, the difference method and estimated flow
+    (host inputs, two batches, one stream forced through overflow re-runs): each stream equals
+    the oracle for it alone."""
+    vids = [synth.blob_video(synth.mixed_stream(W, H, seed=70 + i, n_frames=6))
+            for i, (W, H, _, _, _) in enumerate(MODES_MIX)]
+    streams = [sim.Stream(W, H, **opts) for (W, H, opts, _, _) in MODES_MIX]
+    for a, b in ((0, 3), (3, 6)):
+        entries = []
+        for st, v, (_, _, _, _, supplied) in zip(streams, vids, MODES_MIX):
+            fl = v.flows[max(a - 1, 0):b - 1] if supplied else None
+            entries.append((st, v.frames[a:b], fl if fl is None or len(fl) else None,
+                            v.t_us[a:b]))
+        sim.push_batch(entries)
+    for st, v, (_, _, opts, ocfg, supplied) in zip(streams, vids, MODES_MIX):
+        ok, oref = oracle_keys(v.frames, v.flows if supplied else None, v.t_us, **ocfg)
+        assert len(ok) > 0, opts
+        np.testing.assert_array_equal(st.drain_keys(), ok, err_msg=str(opts))
+        np.testing.assert_array_equal(st.reference().view(np.uint32), oref.view(np.uint32),
+                                      err_msg=str(opts))
+        st.close()
