@@ -47,6 +47,23 @@ def test_memoryless_ragged_image(method, S):
                   c_neg=C * 1.2, n_interp=S - 1, thresh_mode=sim.MEMORYLESS)
 
 
+@pytest.mark.parametrize("cfg", [dict(method=sim.DIFFERENCE),
+                                 dict(method=sim.DENSE, thresh_mode=sim.MEMORYLESS),
+                                 dict(method=sim.SPARSE, thresh_mode=sim.MEMORYLESS)],
+                         ids=["difference", "dense-memoryless", "sparse-memoryless"])
+def test_non_finite_flow_in_the_new_samplers(cfg):
+    """NaN and infinite flow components clamp sample positions to the border in the difference
+    sampler and the memoryless mode, as in the oracle."""
+    rng = np.random.default_rng(77)
+    frames, flows = synth.random_frames(rng, 4, 19, 41, flow_scale=4.0)
+    flows[0, 3, 5] = [np.nan, 1.0]
+    flows[1, 7, 8] = [np.inf, -np.inf]
+    flows[2, 2, 2] = [-np.inf, np.nan]
+    flows[2, 0, 40] = [np.nan, np.nan]
+    assert_parity(frames, flows, np.array([0, 100, 200, 300]), modes=("window", "single"),
+                  c_pos=0.05, c_neg=0.05, n_interp=5, **cfg)
+
+
 def test_difference_346x260_full_sequence():
     """The dense workload's 346x260 60-frame blob video through the difference method (Table I:
     10 interpolated difference frames), one window, chunks and device inputs."""
