@@ -245,3 +245,22 @@ def test_reset_and_determinism():
         np.testing.assert_array_equal(r, runs[0])
     ok, _ = oracle_keys(v.frames, v.flows, v.t_us, method=sim.DENSE, c_pos=0.15, c_neg=0.15)
     np.testing.assert_array_equal(runs[0], ok)
+
+
+def test_event_records_beyond_one_conversion_chunk():
+    """sim_drain_events converts keys to records in chunks of 2^20: more than 2^20 events, drained
+    in a partial call that ends inside a chunk and a call for the rest, equal the oracle's."""
+    rng = np.random.default_rng(21)
+    H, W = 384, 512
+    f0 = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    frames = np.stack([f0, (255 - f0).astype(np.uint8)])
+    t = np.array([0, 40000], np.int64)
+    ok, _ = oracle_keys(frames, None, t, method=sim.BASIC, c_pos=0.05, c_neg=0.05)
+    assert len(ok) > (1 << 20) + 1000
+    s = sim.Stream(W, H, method="basic", c_pos=0.05, c_neg=0.05)
+    s.push_frames(frames, None, t)
+    ev = np.concatenate([s.drain_events(1000), s.drain_events()])
+    tt, x, y, p = sim.decode_keys(ok, 0)
+    assert (ev["t"] == tt).all() and (ev["x"] == x).all() and (ev["y"] == y).all()
+    assert (ev["p"] == p).all() and s.pending() == 0
+    s.close()
