@@ -164,3 +164,21 @@ def test_emulated_lk_is_memory_safe_under_asan(tmp_path):
     res = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env,
                          timeout=900)
     assert res.returncode == 0 and "asan-clean" in res.stdout, res.stderr[-4000:]
+
+
+def test_emulated_estimated_flow_beyond_one_mask_word(emu_sim):
+    """Sparse with estimated flow over a 40-frame window: the flow kernel reads the selection
+    bitmask words of intervals 32 and later; window and single pushes equal the oracle."""
+    spec = synth.BlobVideoSpec(28, 20, 40, 60.0, 4, seed=12, motion="random", speed_max=3.0)
+    v = synth.blob_video(spec)
+    cfg = dict(method=sim.SPARSE, c_pos=0.08, c_neg=0.08, n_interp=3, flow_source=FLOW_LK,
+               lk_levels=1, lk_radius=3)
+    ok, oref = oracle_run(v.frames, None, v.t_us, **cfg)
+    assert len(ok) > 100
+    scfg = dict(method=sim.SPARSE, c_pos=0.08, c_neg=0.08, n_interp=3, flow_source="lk",
+                lk=dict(levels=1, radius=3))
+    for mode in ("window", "single"):
+        keys, ref, _ = emu_run(emu_sim, v.frames, None, v.t_us, mode=mode, event_capacity=32,
+                               **scfg)
+        np.testing.assert_array_equal(keys, ok, err_msg=mode)
+        np.testing.assert_array_equal(ref.view(np.uint32), oref.view(np.uint32))
