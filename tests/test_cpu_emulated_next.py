@@ -92,6 +92,20 @@ def test_emulated_memoryless_blob_video(emu_sim, method):
     assert n > 100
 
 
+@pytest.mark.parametrize("method", [sim.SPARSE, sim.DENSE])
+def test_emulated_memoryless_window_of_70_intervals(emu_sim, method):
+    """Memoryless thresholding over a 71-frame window (three selection mask words for sparse),
+    with a small event capacity so that chains re-run."""
+    spec = synth.BlobVideoSpec(30, 18, 71, 60.0, 4, seed=14, motion="random", speed_max=3.0)
+    v = synth.blob_video(spec)
+    cfg = dict(method=method, c_pos=0.02, c_neg=0.02, n_interp=3, thresh_mode=sim.MEMORYLESS)
+    ok, _ = oracle_run(v.frames, v.flows, v.t_us, **cfg)
+    assert len(ok) > 500
+    keys, _, st = emu_run(emu_sim, v.frames, v.flows, v.t_us, event_capacity=64, **cfg)
+    np.testing.assert_array_equal(keys, ok)
+    assert st["retries"] > 0
+
+
 @pytest.mark.parametrize("method,thresh", [(sim.DIFFERENCE, sim.MEMORYLESS),
                                            (sim.DENSE, sim.MEMORYLESS),
                                            (sim.SPARSE, sim.MEMORYLESS)])
