@@ -15,8 +15,14 @@ from paper_2209_04634_amd import sim, synth
 pytestmark = pytest.mark.gpu
 
 
+# Options of the simulator that do not change what it computes (buffer sizing, stream choice):
+# the oracle takes none of them.
+SIM_ONLY_KEYS = ("event_capacity", "hip_stream")
+
+
 def oracle_keys(frames, flows, t, **cfg):
     T, H, W = frames.shape
+    cfg = {k: v for k, v in cfg.items() if k not in SIM_ONLY_KEYS}
     o = OracleSim(W, H, **cfg)
     out = []
     for k in range(T):
@@ -87,9 +93,9 @@ def test_basic_240x180():
 
 @pytest.mark.skip(reason="a window driver that gathered and sorted before checking for "
                   "event-buffer overflow faulted the GPU on this sequence (many buffer regrowths) "
-                  "twice; that driver is removed, but this case stays off the GPU until the next "
-                  "round; the same arithmetic at this size is covered by the per-frame and "
-                  "overflow tests below")
+                  "twice; that driver is removed, but this case stays off the GPU until the cause "
+                  "is shown on the CPU and fixed; the same arithmetic at this size is covered by "
+                  "the per-frame and overflow tests below")
 def test_dense_346x260_full_sequence():
     v = synth.blob_video(synth.dense_346x260())
     n = assert_parity(v.frames, v.flows, v.t_us, modes=("window", "device"), method=sim.DENSE,
