@@ -74,6 +74,7 @@ extern "C" {
 #define SIM_E_POISONED (-6)  /* handle poisoned by an earlier SIM_E_HIP                         */
 #define SIM_E_BUSY (-7)      /* server: no slot or memory for the request (nothing changed)     */
 #define SIM_E_EMPTY (-8)     /* server: nothing to return yet                                   */
+#define SIM_E_TOO_BIG (-9)   /* sim_lk_flow_noalloc: the request needs more than its fixed scratch */
 
 enum { SIM_BASIC = 0, SIM_DENSE = 1, SIM_SPARSE = 2, SIM_DIFFERENCE = 3 };
 enum { SIM_THRESH_REFERENCE = 0, SIM_THRESH_MEMORYLESS = 1 };
@@ -295,6 +296,23 @@ int sim_set_lk_params(sim_stream* s, const sim_lk_params* p);
 int sim_lk_flow(const uint8_t* f0, const uint8_t* f1, int32_t width, int32_t height,
                 const uint32_t* points, uint64_t n_points, float* flow, uint8_t* valid,
                 const sim_lk_params* params, int32_t mem_kind, void* hip_stream);
+
+/* sim_lk_flow without any allocation, for callers that cannot allocate device memory: code
+ * recorded into a HIP graph, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, arithmetic and results as sim_lk_flow with mem_kind = SIM_MEM_DEVICE: f0, f1,
+ * points, flow and valid (may be NULL) are device memory owned by the caller.  The two pyramids
+ * live in a fixed device array that the library holds on every GPU it runs on until the process
+ * ends: 6 * 2^20 floats (24 MiB), enough for two pyramids of 1920x1080 frames at any level
+ * count; larger requests return SIM_E_TOO_BIG before any device work.  Work is queued on
+ * hip_stream (NULL: the null stream) and the call returns without waiting for it; read the
+ * outputs after synchronising with that stream.  Every call on one GPU shares that GPU's array:
+ * calls whose work overlaps on one GPU (queued on different streams, or from several threads)
+ * race and give undefined results; calls queued on one stream are ordered and safe.  No
+ * hipMalloc, hipFree, memset node or host wait is issued.
+ * Errors: as sim_lk_flow (SIM_E_INVAL, SIM_E_HIP) plus SIM_E_TOO_BIG; never SIM_E_NOMEM. */
+int sim_lk_flow_noalloc(const uint8_t* f0, const uint8_t* f1, int32_t width, int32_t height,
+                        const uint32_t* points, uint64_t n_points, float* flow, uint8_t* valid,
+                        const sim_lk_params* params, void* hip_stream);
 
 /* Text describing the HIP failure that poisoned the handle (call, source line, HIP's message);
  * empty when there was none.  Valid until the next call on the handle. */

@@ -993,6 +993,42 @@ void batch_windows(sim_stream** streams, sim_frames* items, const std::vector<St
     }
 }
 
+// Fixed device scratch of sim_lk_flow_noalloc (the two pyramids of one call), for callers that
+// cannot allocate.  Every GPU the library runs on holds its own copy from module load until the
+// process ends; host code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's name is a host-side stand-in, not a device address).
+constexpr uint64_t kLkScratchFloats = 6ull << 20;   // 24 MiB: two 1920x1080 pyramids, any depth
+static __device__ __align__(256) float scratch[kLkScratchFloats];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int lk_scratch_of_current_device(float** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+        (void)hipGetLastError();
+        return SIM_E_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return SIM_E_HIP;
+        }
+        g_scratch_dev[dev] = (float*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return SIM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void sim_config_init(sim_config* cfg) {
@@ -1020,6 +1056,7 @@ const char* sim_strerror(int status) {
         case SIM_E_POISONED: return "handle poisoned by an earlier HIP error";
         case SIM_E_BUSY: return "no capacity for the request";
         case SIM_E_EMPTY: return "nothing available";
+        case SIM_E_TOO_BIG: return "request exceeds the fixed scratch of the non-allocating call";
         default: return "unknown status";
     }
 }
@@ -1505,6 +1542,34 @@ int sim_lk_flow(const uint8_t* f0, const uint8_t* f1, int32_t width, int32_t hei
     dfree(d_valid);
     if (own) (void)hipStreamDestroy(st);
     return rc;
+}
+
+int sim_lk_flow_noalloc(const uint8_t* f0, const uint8_t* f1, int32_t width, int32_t height,
+                        const uint32_t* points, uint64_t n_points, float* flow, uint8_t* valid,
+                        const sim_lk_params* params, void* hip_stream) {
+    sim_lk_params P;
+    if (params)
+        P = *params;
+    else
+        sim_lk_params_init(&P);
+    if (!lk_ok(P) || width < 1 || height < 1 || width > 4096 || height > 4096)
+        return SIM_E_INVAL;
+    if (n_points == 0) return SIM_OK;
+    if (!f0 || !f1 || !points || !flow) return SIM_E_INVAL;
+    const PyrLayout pl = pyr_layout(width, height, P.levels);
+    if (2 * pl.total > kLkScratchFloats) return SIM_E_TOO_BIG;
+    float* pyr = nullptr;
+    int rc = lk_scratch_of_current_device(&pyr);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (launch_pyramids(f0, nullptr, 0, 1, pl, pyr, st) != hipSuccess ||
+        launch_pyramids(f1, nullptr, 0, 1, pl, pyr + pl.total, st) != hipSuccess ||
+        launch_lk_points(pyr, pyr + pl.total, pl, lk_from(P), points, n_points, flow, valid,
+                         st) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIM_E_HIP;
+    }
+    return SIM_OK;
 }
 
 int sim_sync(sim_stream* s) {

@@ -26,6 +26,7 @@ THRESH_MODES = {"reference": REFERENCE, "memoryless": MEMORYLESS}
 FLOW_SOURCES = {"supplied": FLOW_SUPPLIED, "lk": FLOW_LK}
 
 OK, E_INVAL, E_ORDER, E_NOMEM, E_RANGE, E_HIP, E_POISONED, E_BUSY, E_EMPTY = 0, -1, -2, -3, -4, -5, -6, -7, -8
+E_TOO_BIG = -9
 
 
 class SimConfig(ctypes.Structure):
@@ -132,6 +133,8 @@ def load() -> ctypes.CDLL:
         "sim_set_lk_params": (ctypes.c_int, [P, ctypes.POINTER(SimLkParams)]),
         "sim_lk_flow": (ctypes.c_int, [P, P, I32, I32, P, U64, P, P,
                                        ctypes.POINTER(SimLkParams), I32, P]),
+        "sim_lk_flow_noalloc": (ctypes.c_int, [P, P, I32, I32, P, U64, P, P,
+                                               ctypes.POINTER(SimLkParams), P]),
         "sim_accumulate": (ctypes.c_int, [P, I64, I64, P, I32]),
         "sim_event_rate": (ctypes.c_int, [P, I64, I64, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double), PU64]),
@@ -249,6 +252,29 @@ def lk_flow(f0, f1, points=None, hip_stream=None, **params):
     _check(lib.sim_lk_flow(a, b, W, H, pp, n, fp, vp, ctypes.byref(lk_params(**params)), ka, st),
            "sim_lk_flow")
     return flow, (valid != 0)
+
+
+def lk_flow_noalloc(f0, f1, points, flow, valid=None, hip_stream=None, **params):
+    """sim_lk_flow_noalloc: Lucas-Kanade flow into caller-allocated device tensors `flow`
+    ([n, 2] float32) and `valid` ([n] uint8 or None), with no allocation in the library.  The
+    work is queued on hip_stream (a torch stream, its handle, or None: the null stream) and not
+    waited for."""
+    lib = load()
+    H, W = int(f0.shape[0]), int(f0.shape[1])
+    a, ka, _ = _buffer(f0, np.uint8, (H, W))
+    b, kb, _ = _buffer(f1, np.uint8, (H, W))
+    n = int(points.numel())
+    pp, pk, _ = _buffer(points, np.uint32, (n,))
+    fp, fk, _ = _buffer(flow, np.float32, (n, 2))
+    vp, vk, _ = _buffer(valid, np.uint8, (n,))
+    if MEM_HOST in (ka, kb, pk, fk, vk) or not _is_torch(flow):
+        raise ValueError("sim_lk_flow_noalloc takes device tensors only")
+    if hip_stream is not None and hasattr(hip_stream, "cuda_stream"):
+        hip_stream = hip_stream.cuda_stream
+    st = ctypes.c_void_p(int(hip_stream)) if hip_stream else None
+    _check(lib.sim_lk_flow_noalloc(a, b, W, H, pp, n, fp, vp,
+                                   ctypes.byref(lk_params(**params)), st),
+           "sim_lk_flow_noalloc")
 
 
 def _check_flows(flows, needed: int, H: int, W: int) -> None:

@@ -395,4 +395,12 @@ hipError_t emu_hipGetLastError() {
     g_last = hipSuccess;
     return e;
 }
+hipError_t emu_hipGetDevice(int* dev) {
+    *dev = 0;
+    return hipSuccess;
+}
+hipError_t emu_hipGetSymbolAddress(void** p, const void* symbol) {
+    *p = const_cast<void*>(symbol);
+    return hipSuccess;
+}
 const char* emu_hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "error"; }

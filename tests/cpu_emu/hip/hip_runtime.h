@@ -24,6 +24,7 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define __align__(n) alignas(n)
 #define __shared__ thread_local
 #ifndef __restrict__
 #define __restrict__ __restrict
@@ -155,6 +156,9 @@ inline void emu_launch(const char* name, void (*k)(P...), dim3 grid, dim3 block,
 #define hipEventDestroy emu_hipEventDestroy
 #define hipGetLastError emu_hipGetLastError
 #define hipGetErrorString emu_hipGetErrorString
+#define hipGetDevice emu_hipGetDevice
+#define hipGetSymbolAddress emu_hipGetSymbolAddress
+#define HIP_SYMBOL(x) ((const void*)&(x))
 
 hipError_t emu_hipMalloc(void** p, size_t n);
 hipError_t emu_hipFree(void* p);
@@ -176,3 +180,6 @@ hipError_t emu_hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t emu_hipEventDestroy(hipEvent_t e);
 hipError_t emu_hipGetLastError();
 const char* emu_hipGetErrorString(hipError_t e);
+hipError_t emu_hipGetDevice(int* dev);
+// a __device__ variable is host memory here: its "device address" is its own address
+hipError_t emu_hipGetSymbolAddress(void** p, const void* symbol);

@@ -125,3 +125,18 @@ def test_host_only_entry_points_of_the_wider_rows():
     assert lib.srv_create(1 << 30, 0, 4, ctypes.byref(srv)) == sim.E_INVAL
     assert lib.srv_create(1 << 30, 4, 4, ctypes.byref(srv)) == sim.OK
     assert lib.srv_destroy(srv) == sim.OK
+
+
+def test_noalloc_flow_validates_on_the_host():
+    """sim_lk_flow_noalloc refuses bad arguments and requests beyond its fixed scratch before any
+    device call."""
+    lib = sim.load()
+    f = (ctypes.c_uint8 * 64)()
+    pts = (ctypes.c_uint32 * 1)()
+    fl = (ctypes.c_float * 2)()
+    assert lib.sim_lk_flow_noalloc(f, f, 0, 8, pts, 1, fl, None, None, None) == sim.E_INVAL
+    assert lib.sim_lk_flow_noalloc(f, f, 8, 8, None, 1, fl, None, None, None) == sim.E_INVAL
+    assert lib.sim_lk_flow_noalloc(f, f, 4096, 4096, pts, 1, fl, None, None, None) == \
+        sim.E_TOO_BIG
+    assert lib.sim_lk_flow_noalloc(f, f, 8, 8, pts, 0, fl, None, None, None) == sim.OK
+    assert lib.sim_strerror(sim.E_TOO_BIG) != lib.sim_strerror(-100)
