@@ -89,6 +89,160 @@ __device__ __forceinline__ float interp_sample(const uint8_t* F0, const uint8_t*
     return om * a + tau * b;
 }
 
+// The same footprint with 32-bit texel offsets (a frame has fewer than 2^24 pixels) and the
+// bounds as floats (wm1 = W - 1, hm1 = H - 1).  fx = sx - floor(sx) equals sx - (float)x0
+// exactly: floor is exact and x0 < 2^24.
+struct Tap32 {
+    uint32_t o00, o01, o10, o11;
+    float fx, fy;
+};
+
+__device__ __forceinline__ Tap32 tap32(int W, int H, float wm1, float hm1, float sx, float sy) {
+    sx = fminf(fmaxf(sx, 0.0f), wm1);
+    sy = fminf(fmaxf(sy, 0.0f), hm1);
+    const float flx = floorf(sx);
+    const float fly = floorf(sy);
+    const int x0 = (int)flx;
+    const int y0 = (int)fly;
+    const int x1 = min(x0 + 1, W - 1);
+    const int y1 = min(y0 + 1, H - 1);
+    Tap32 t;
+    t.fx = sx - flx;
+    t.fy = sy - fly;
+    const uint32_t r0 = __umul24((uint32_t)y0, (uint32_t)W);
+    const uint32_t r1 = __umul24((uint32_t)y1, (uint32_t)W);
+    t.o00 = r0 + (uint32_t)x0;
+    t.o01 = r0 + (uint32_t)x1;
+    t.o10 = r1 + (uint32_t)x0;
+    t.o11 = r1 + (uint32_t)x1;
+    return t;
+}
+
+// bil_blend with the weights given as (fx, fy).
+__device__ __forceinline__ float blend_w(float fx, float fy, float v00, float v01, float v10,
+                                         float v11) {
+    const float gx = 1.0f - fx;
+    const float gy = 1.0f - fy;
+    const float top = gx * v00 + fx * v01;
+    const float bot = gx * v10 + fx * v11;
+    return gy * top + fy * bot;
+}
+
+// Interior samples V_k, k = k0 .. min(k0 + G - 1, klast), of the frame methods into the stash
+// (stride kSimThreads): the same arithmetic as interp_sample, with every texel load of the G
+// samples issued before any of them is blended, so that a lane has 8 G loads in flight at once.
+template <int G>
+__device__ __forceinline__ void stash_frame_samples(const uint8_t* F0, const uint8_t* F1,
+                                                    const float* lut, const float* tau, int W,
+                                                    int H, float wm1, float hm1, float xf,
+                                                    float yf, float u, float v, int k0, int klast,
+                                                    float* stash) {
+    uint32_t t[G][8];
+    float w[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int k = k0 + g;
+        if (k <= klast) {
+            const float tk = tau[k];
+            const float om = 1.0f - tk;
+            const Tap32 ta = tap32(W, H, wm1, hm1, xf - tk * u, yf - tk * v);
+            const Tap32 tb = tap32(W, H, wm1, hm1, xf + om * u, yf + om * v);
+            t[g][0] = F0[ta.o00];
+            t[g][1] = F0[ta.o01];
+            t[g][2] = F0[ta.o10];
+            t[g][3] = F0[ta.o11];
+            t[g][4] = F1[tb.o00];
+            t[g][5] = F1[tb.o01];
+            t[g][6] = F1[tb.o10];
+            t[g][7] = F1[tb.o11];
+            w[g][0] = ta.fx;
+            w[g][1] = ta.fy;
+            w[g][2] = tb.fx;
+            w[g][3] = tb.fy;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int k = k0 + g;
+        if (k <= klast) {
+            const float tk = tau[k];
+            const float om = 1.0f - tk;
+            const float a = blend_w(w[g][0], w[g][1], lut[t[g][0]], lut[t[g][1]], lut[t[g][2]],
+                                    lut[t[g][3]]);
+            const float b = blend_w(w[g][2], w[g][3], lut[t[g][4]], lut[t[g][5]], lut[t[g][6]],
+                                    lut[t[g][7]]);
+            stash[(k - 1) * kSimThreads] = om * a + tk * b;
+        }
+    }
+}
+
+// The difference method's interior difference frames D_k into the stash, batched the same way
+// (16 texel loads per sample): the arithmetic of interp_diff_sample.
+template <int G>
+__device__ __forceinline__ void stash_diff_samples(const uint8_t* Fm, const uint8_t* F0,
+                                                   const uint8_t* F1, const float* lut,
+                                                   const float* tau, int W, int H, float wm1,
+                                                   float hm1, float xf, float yf, float u,
+                                                   float v, int k0, int klast, float* stash) {
+    uint32_t t[G][16];
+    float w[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int k = k0 + g;
+        if (k <= klast) {
+            const float tk = tau[k];
+            const float om = 1.0f - tk;
+            const Tap32 ta = tap32(W, H, wm1, hm1, xf - tk * u, yf - tk * v);
+            const Tap32 tb = tap32(W, H, wm1, hm1, xf + om * u, yf + om * v);
+            t[g][0] = Fm[ta.o00];
+            t[g][1] = Fm[ta.o01];
+            t[g][2] = Fm[ta.o10];
+            t[g][3] = Fm[ta.o11];
+            t[g][4] = F0[ta.o00];
+            t[g][5] = F0[ta.o01];
+            t[g][6] = F0[ta.o10];
+            t[g][7] = F0[ta.o11];
+            t[g][8] = F0[tb.o00];
+            t[g][9] = F0[tb.o01];
+            t[g][10] = F0[tb.o10];
+            t[g][11] = F0[tb.o11];
+            t[g][12] = F1[tb.o00];
+            t[g][13] = F1[tb.o01];
+            t[g][14] = F1[tb.o10];
+            t[g][15] = F1[tb.o11];
+            w[g][0] = ta.fx;
+            w[g][1] = ta.fy;
+            w[g][2] = tb.fx;
+            w[g][3] = tb.fy;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int k = k0 + g;
+        if (k <= klast) {
+            const float tk = tau[k];
+            const float om = 1.0f - tk;
+            const float a = blend_w(w[g][0], w[g][1], lut[t[g][4]] - lut[t[g][0]],
+                                    lut[t[g][5]] - lut[t[g][1]], lut[t[g][6]] - lut[t[g][2]],
+                                    lut[t[g][7]] - lut[t[g][3]]);
+            const float b = blend_w(w[g][2], w[g][3], lut[t[g][12]] - lut[t[g][8]],
+                                    lut[t[g][13]] - lut[t[g][9]], lut[t[g][14]] - lut[t[g][10]],
+                                    lut[t[g][15]] - lut[t[g][11]]);
+            stash[(k - 1) * kSimThreads] = om * a + tk * b;
+        }
+    }
+}
+
+// Samples in flight per lane in the chain pass (frame methods / difference method).
+#ifndef EVSIM_FRAME_BATCH
+#define EVSIM_FRAME_BATCH 10
+#endif
+#ifndef EVSIM_DIFF_BATCH
+#define EVSIM_DIFF_BATCH 2
+#endif
+constexpr int kFrameBatch = EVSIM_FRAME_BATCH;
+constexpr int kDiffBatch = EVSIM_DIFF_BATCH;
+
 struct PixelCtx {
     const uint8_t* F0;
     const uint8_t* F1;
@@ -273,8 +427,10 @@ __device__ __forceinline__ int next_selected(bool all, uint32_t m0, uint32_t m1,
 template <bool VEC>
 __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
     __shared__ float lut[256];
+    __shared__ unsigned int s_cls[kClasses];    // this block's active pixels per length class
     const int tid = threadIdx.x;
     lut[tid] = a.lut[tid];
+    if (tid < kClasses) s_cls[tid] = 0u;
     __syncthreads();
     const int lane = tid & 63;
     const int base = (bid * 256 + tid) * 4;
@@ -291,6 +447,7 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
     for (int q = 0; q < 4; ++q) A0[q] = lut[(last >> (8 * q)) & 255u];
 
     uint32_t any[4] = {0u, 0u, 0u, 0u};
+    int plen[4] = {0, 0, 0, 0};     // selected intervals per pixel
     int nsel = 0;
     for (int w = 0; w < kMaskWords && w * 32 < a.K; ++w) {
         uint32_t mw[4] = {0u, 0u, 0u, 0u};
@@ -324,7 +481,7 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
             if (q < cnt) {
                 a.mask[(int64_t)w * a.npix + base + q] = mw[q];
                 any[q] |= mw[q];
-                nsel += __popc(mw[q]);
+                plen[q] += __popc(mw[q]);
             }
         }
     }
@@ -337,8 +494,16 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
     __shared__ int s_wsum[4];
     __shared__ unsigned int s_slot0;
     int na = 0;
+    uint32_t cls[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) na += (q < cnt && any[q] != 0u) ? 1 : 0;
+    for (int q = 0; q < 4; ++q) {
+        nsel += plen[q];
+        cls[q] = (uint32_t)(min(plen[q], kClasses) - 1);
+        if (q < cnt && any[q] != 0u) {
+            ++na;
+            atomicAdd(&s_cls[cls[q]], 1u);
+        }
+    }
     int total;
     const int off = block_scan_256(na, s_wsum, &total);
     __syncthreads();
@@ -352,18 +517,73 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
         if (sel_total > 0) atomicAdd(st, (unsigned long long)sel_total);
         if (total > 0) atomicAdd(st + 1, (unsigned long long)total);
     }
+    if (tid < kClasses && s_cls[tid] != 0u)
+        atomicAdd(a.n_class + (stripe * kClasses + tid) * kCounterStride, s_cls[tid]);
     __syncthreads();
     unsigned int slot = (unsigned int)stripe * (unsigned int)a.act_cap + s_slot0 + (unsigned int)off;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (q < cnt && any[q] != 0u) {
-            a.act_px[slot] = (uint32_t)(base + q);
-            a.resume[slot] = 0;
+            a.act_px[slot] = (uint32_t)(base + q) | (cls[q] << kClassShift);
             ++slot;
         }
     }
     (void)lane;
 }
+
+// ------------------------------------------------------------------------------------------
+// Order pass of the sparse method: the selection's sub-lists into one list of active pixels,
+// length classes longest first (within a class: sub-list by sub-list, each in placement order),
+// with their resume points cleared.  A wave's 64 slots lie in one sub-list (act_cap is a multiple
+// of kSelectPx); per class present in the wave one lane reserves the wave's places with one
+// atomic on the (sub-list, class) cursor.  Which pixel lands in which slot of its segment depends
+// on the order of those atomics; the events do not (they are sorted by key afterwards).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void order_block(const OrderArgs& a, unsigned bid) {
+    // segment start per (sub-list, class): exclusive scan of the counts in the order
+    // (class descending, sub-list ascending); thread t holds the count of the t-th segment
+    __shared__ unsigned int s_seg[kActStripes * kClasses];
+    __shared__ int s_wsum[4];
+    static_assert(kActStripes * kClasses <= 256, "one thread per segment");
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int seg_c = kClasses - 1 - tid / kActStripes, seg_st = tid % kActStripes;
+    const bool is_seg = tid < kActStripes * kClasses;
+    const int cnt =
+        is_seg ? (int)a.n_class[(seg_st * kClasses + seg_c) * kCounterStride] : 0;
+    int seg_total;
+    const int seg_start = block_scan_256(cnt, s_wsum, &seg_total);
+    if (is_seg) s_seg[seg_st * kClasses + seg_c] = (unsigned int)seg_start;
+    __syncthreads();
+    const int slot = (int)bid * 256 + tid;
+    const int stripe = slot / a.act_cap;
+    const bool valid = stripe < kActStripes &&
+                       (slot - stripe * a.act_cap) < (int)a.n_active[stripe * kCounterStride];
+    uint32_t v = valid ? a.act_px[slot] : 0u;
+    const uint32_t c = v >> kClassShift;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    bool left = valid;
+    while (__any(left)) {
+        const uint64_t lm = __ballot(left);
+        const int leader = __ffsll((long long)lm) - 1;
+        const uint32_t cl = (uint32_t)__shfl((int)c, leader, 64);
+        const bool mine = left && c == cl;
+        const uint64_t m = __ballot(mine);
+        unsigned int base = 0u;
+        if (lane == leader)
+            base = atomicAdd(a.cursor + (stripe * kClasses + (int)cl) * kCounterStride,
+                             (unsigned int)__popcll(m));
+        base = (unsigned int)__shfl((int)base, leader, 64);
+        if (mine) {
+            const unsigned int pos =
+                s_seg[stripe * kClasses + (int)cl] + base + (unsigned int)__popcll(m & lt);
+            a.ord[pos] = v & kPixelMask;
+            a.resume[pos] = 0;
+            left = false;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_order(OrderArgs a) { order_block(a, blockIdx.x); }
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
@@ -395,9 +615,9 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
     const int slot = bid * kSimThreads + tid;
     bool valid;
     if (a.act_px) {
-        const int stripe = slot / a.act_cap;
-        valid = stripe < kActStripes &&
-                (slot - stripe * a.act_cap) < (int)a.n_active[stripe * kCounterStride];
+        unsigned int n_act = 0;
+        for (int st = 0; st < kActStripes; ++st) n_act += a.n_active[st * kCounterStride];
+        valid = slot < (int)n_act;
     } else {
         valid = slot < a.npix;
     }
@@ -408,6 +628,8 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
     uint64_t* arena = a.arena + (uint64_t)astripe * a.stripe_cap;
     const int y = p / a.W;
     const int x = p - y * a.W;
+    const float xf = (float)x, yf = (float)y;
+    const float wm1 = (float)(a.W - 1), hm1 = (float)(a.H - 1);
     const bool all = a.mask == nullptr;
     uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
     if (valid && !all) {
@@ -466,13 +688,16 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
                     c.u = fl[0];
                     c.v = fl[1];
                 }
-                for (int k = 1; k <= stash_n; ++k) {
-                    if constexpr (MODE == kModeDifference)
-                        stash[(k - 1) * kSimThreads] = interp_diff_sample(
-                            c.Fm, c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, tau[k]);
-                    else
-                        stash[(k - 1) * kSimThreads] =
-                            interp_sample(c.F0, c.F1, lut, a.W, a.H, x, y, c.u, c.v, tau[k]);
+                if constexpr (MODE == kModeDifference) {
+                    for (int k0 = 1; k0 <= stash_n; k0 += kDiffBatch)
+                        stash_diff_samples<kDiffBatch>(c.Fm, c.F0, c.F1, lut, tau, a.W, a.H, wm1,
+                                                       hm1, xf, yf, c.u, c.v, k0, stash_n,
+                                                       stash);
+                } else {
+                    for (int k0 = 1; k0 <= stash_n; k0 += kFrameBatch)
+                        stash_frame_samples<kFrameBatch>(c.F0, c.F1, lut, tau, a.W, a.H, wm1,
+                                                         hm1, xf, yf, c.u, c.v, k0, stash_n,
+                                                         stash);
                 }
                 if (stash_n) c.stash = stash;
             }
@@ -795,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_prep_window(unsigned long long* __restr
         if (tid < 4) counters[tid] = 0ull;
         for (int i = tid; i < kArenaStripes * kCounterStride; i += 256) reserve[i] = 0ull;
         if (n_active)
-            for (int i = tid; i < kActStripes * kCounterStride; i += 256) n_active[i] = 0u;
+            for (int i = tid; i < kActCounters; i += 256) n_active[i] = 0u;
     }
     if (resume) {
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -823,6 +1048,13 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t stream) {
         hipLaunchKernelGGL(k_select<true>, dim3(blocks), dim3(256), 0, stream, a);
     else
         hipLaunchKernelGGL(k_select<false>, dim3(blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_order(const OrderArgs& a, hipStream_t stream) {
+    const int blocks = kActStripes * a.act_cap / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_order, dim3(blocks), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -969,7 +1201,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BatchEntry* __restrict
     for (int i = tid; i < kArenaStripes * kCounterStride; i += 256) reserve[i] = 0ull;
     if (tid < 4) e->counters[tid] = 0ull;
     if (e->sparse)
-        for (int i = tid; i < kActStripes * kCounterStride; i += 256) e->sel.n_active[i] = 0u;
+        for (int i = tid; i < kActCounters; i += 256) e->sel.n_active[i] = 0u;
 }
 
 // Selection pass of sparse entries; frame copies and chain resets of the others (kSelectPx
@@ -993,6 +1225,12 @@ __global__ __launch_bounds__(256) void k_batch_select(const BatchEntry* __restri
         if (e->copy2_dst) e->copy2_dst[p] = e->copy2_src[p];
         e->chain.resume[p] = 0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_batch_order(const BatchEntry* __restrict__ entries,
+                                                     const int* __restrict__ start, int n) {
+    const int ei = batch_entry(start, n, blockIdx.x);
+    order_block(entries[ei].ord, blockIdx.x - (unsigned)start[ei]);
 }
 
 template <int MODE>
@@ -1076,6 +1314,13 @@ hipError_t launch_batch_select(const BatchEntry* e, const int* start, int n, int
                                hipStream_t stream) {
     if (n <= 0 || blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_select, dim3(blocks), dim3(256), 0, stream, e, start, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_order(const BatchEntry* e, const int* start, int n, int blocks,
+                              hipStream_t stream) {
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_order, dim3(blocks), dim3(256), 0, stream, e, start, n);
     return hipGetLastError();
 }
 

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_lk_window(LkWindowArgs a) {
         if (stripe >= kActStripes ||
             slot - stripe * a.act_cap >= (int)a.n_active[stripe * kCounterStride])
             return;
-        p = (int)a.act_px[slot];
+        p = (int)(a.act_px[slot] & kPixelMask);
     } else {
         if (slot >= a.npix) return;
         p = slot;

@@ -89,8 +89,9 @@ struct sim_stream {
     int64_t* d_tbase = nullptr;
     int* d_resume = nullptr;                     // per chain slot
     uint32_t* d_mask = nullptr;                  // sparse: [kMaskWords][npix]
-    uint32_t* d_act = nullptr;                   // sparse: active pixel list
-    unsigned int* d_nact = nullptr;              // sparse: its length
+    uint32_t* d_act = nullptr;                   // sparse: active pixel sub-lists (selection)
+    unsigned int* d_nact = nullptr;              // sparse: their lengths, length classes, cursors
+    uint32_t* d_ord = nullptr;                   // sparse: active pixels ordered by chain length
     float* h_delta = nullptr;                    // pinned
     int64_t* h_tbase = nullptr;                  // pinned
 
@@ -187,6 +188,7 @@ void free_stream(sim_stream* s) {
     dfree(s->d_mask);
     dfree(s->d_act);
     dfree(s->d_nact);
+    dfree(s->d_ord);
     dfree(s->d_delta);
     dfree(s->d_tbase);
     dfree(s->d_resume);
@@ -307,7 +309,7 @@ LkParams lk_from(const sim_lk_params& p) {
 // layout, and the selection and chain arguments, whose table pointers are d_delta / d_tbase.
 int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
                 int K, float* h_delta, int64_t* h_tbase, const float* d_delta, KeyLayout* lay_out,
-                int* nbits_out, SelectArgs* sa, ChainArgs* a) {
+                int* nbits_out, SelectArgs* sa, OrderArgs* oa, ChainArgs* a) {
     const int W = s->cfg.width, H = s->cfg.height;
     uint64_t max_delta = 0;
     for (int i = 0; i < K; ++i) {
@@ -336,13 +338,21 @@ int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const 
     sa->prev_out = s->d_prev[1 - s->cur];
     sa->mask = s->d_mask;
     sa->act_px = s->d_act;
-    sa->resume = s->d_resume;
     sa->n_active = s->d_nact;
+    sa->n_class = s->d_nact ? s->d_nact + kActStripes * kCounterStride : nullptr;
     sa->stats = s->d_stats;
     sa->npix = (int)s->npix;
     sa->K = K;
     sa->act_cap = s->act_cap;
     sa->m = s->m;
+
+    oa->act_px = s->d_act;
+    oa->n_active = s->d_nact;
+    oa->n_class = sa->n_class;
+    oa->cursor = s->d_nact ? sa->n_class + kActStripes * kClasses * kCounterStride : nullptr;
+    oa->ord = s->d_ord;
+    oa->resume = s->d_resume;
+    oa->act_cap = s->act_cap;
 
     const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
     a->prev = s->d_prev[s->cur];
@@ -354,7 +364,7 @@ int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const 
     a->delta = d_delta;
     a->lref = s->d_lref;
     a->mask = sparse ? s->d_mask : nullptr;
-    a->act_px = sparse ? s->d_act : nullptr;
+    a->act_px = sparse ? s->d_ord : nullptr;
     a->n_active = sparse ? s->d_nact : nullptr;
     a->act_cap = s->act_cap;
     a->resume = s->d_resume;
@@ -379,7 +389,11 @@ int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const 
     return SIM_OK;
 }
 
-int chain_slots(const sim_stream* s) {
+// Slots of the chain pass: the ordered active list (sparse) or every pixel.
+int chain_slots(const sim_stream* s) { return (int)s->npix; }
+
+// Slots of the selection's sub-lists (sparse) or every pixel.
+int select_slots(const sim_stream* s) {
     return s->cfg.method == SIM_SPARSE ? kActStripes * s->act_cap : (int)s->npix;
 }
 
@@ -416,7 +430,7 @@ hipError_t launch_lk(sim_stream* s, const uint8_t* frames, int K, hipStream_t st
     la.W = s->cfg.width;
     la.K = K;
     la.flow = s->d_lkflow;
-    return launch_lk_window(la, chain_slots(s), stream);
+    return launch_lk_window(la, select_slots(s), stream);
 }
 
 int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
@@ -429,9 +443,10 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
     KeyLayout lay;
     int nbits = 0;
     SelectArgs sa;
+    OrderArgs oa;
     ChainArgs a;
     int rc = plan_window(s, frames, flows, t_us, K, s->h_delta, s->h_tbase, s->d_delta, &lay,
-                         &nbits, &sa, &a);
+                         &nbits, &sa, &oa, &a);
     if (rc) return rc;
 
     HIP_TRY(s, hipMemcpyAsync(s->d_delta, s->h_delta, K * sizeof(float), hipMemcpyHostToDevice,
@@ -444,6 +459,7 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[0], s->stream));
     if (sparse) {
         HIP_TRY(s, launch_select(sa, s->stream));
+        HIP_TRY(s, launch_order(oa, s->stream));
     } else {
         HIP_TRY(s, launch_copy_u8(frames + (size_t)(K - 1) * s->npix, sa.prev_out, s->npix,
                                   s->stream));
@@ -783,13 +799,13 @@ int fused_window(std::vector<FusedItem>& items) {
     int* ds = (int*)(c.d_blob + ent_bytes);
     auto hstart = [&](int k) { return hs + (size_t)k * (n + 1); };
     auto dstart = [&](int k) { return ds + (size_t)k * (n + 1); };
-    enum { kSel = 0, kChain0 = 1, kGather = 4, kSort = 5 };
+    enum { kSel = 0, kChain0 = 1, kGather = 4, kSort = 5, kOrder = 6 };
 
     // every stream's staged inputs and earlier work are complete before the batch stream reads
     for (FusedItem& f : items)
         if (hipStreamSynchronize(f.s->stream) != hipSuccess) return SIM_E_HIP;
 
-    std::vector<int> sel_blocks(n), chain_blocks[3], blocks(n);
+    std::vector<int> sel_blocks(n), order_blocks(n), chain_blocks[3], blocks(n);
     for (int m = 0; m < 3; ++m) chain_blocks[m].assign(n, 0);
     int max_stash[3] = {0, 0, 0};
     for (int e = 0; e < n; ++e) {
@@ -807,7 +823,7 @@ int fused_window(std::vector<FusedItem>& items) {
         BatchEntry& b = he[e];
         memset(&b, 0, sizeof(b));
         int rc = plan_window(s, f.frames, f.flows, f.t_us, f.K, h_delta, h_tbase,
-                             d_delta, &f.lay, &f.nbits, &b.sel, &b.chain);
+                             d_delta, &f.lay, &f.nbits, &b.sel, &b.ord, &b.chain);
         if (rc) return rc;
         b.sparse = s->cfg.method == SIM_SPARSE ? 1 : 0;
         b.vec = (b.sel.fstride % 4) == 0 && ((uintptr_t)b.sel.frames % 4) == 0 &&
@@ -822,11 +838,13 @@ int fused_window(std::vector<FusedItem>& items) {
         b.counters = s->d_counters;
         b.cv.tbase = d_tbase;
         sel_blocks[e] = (int)((s->npix + kSelectPx - 1) / kSelectPx);
+        order_blocks[e] = b.sparse ? kActStripes * s->act_cap / 256 : 0;
         const int m = b.chain.mode;
         chain_blocks[m][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
         max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
     }
     const int sel_total = fill_starts(hstart(kSel), sel_blocks);
+    const int order_total = fill_starts(hstart(kOrder), order_blocks);
     int chain_total[3];
     for (int m = 0; m < 3; ++m) chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
     hipStream_t st = c.stream;
@@ -841,6 +859,7 @@ int fused_window(std::vector<FusedItem>& items) {
     BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, tab, hipMemcpyHostToDevice, st));
     BATCH_TRY(launch_batch_prep(de, n, st));
     BATCH_TRY(launch_batch_select(de, dstart(kSel), n, sel_total, st));
+    BATCH_TRY(launch_batch_order(de, dstart(kOrder), n, order_total, st));
     for (FusedItem& f : items)
         if (f.s->cfg.flow_source == SIM_FLOW_LK && f.s->S > 1)
             BATCH_TRY(launch_lk(f.s, f.frames, f.K, st));
@@ -1154,7 +1173,8 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     if (cfg->method == SIM_SPARSE) {
         ok = ok && dev_alloc(&s->d_mask, (size_t)kMaskWords * s->npix) == hipSuccess;
         ok = ok && dev_alloc(&s->d_act, (size_t)kActStripes * s->act_cap) == hipSuccess;
-        ok = ok && dev_alloc(&s->d_nact, (size_t)kActStripes * kCounterStride) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_nact, (size_t)kActCounters) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_ord, (size_t)s->npix) == hipSuccess;
     }
     ok = ok && dev_alloc(&s->d_delta, kMaxWindow) == hipSuccess;
     ok = ok && dev_alloc(&s->d_tbase, kMaxWindow) == hipSuccess;

@@ -98,9 +98,9 @@ int srv_footprint(const sim_config* cfg, int32_t queue_depth, uint64_t* bytes) {
     const bool interp = cfg->method != SIM_BASIC && cfg->flow_source == SIM_FLOW_SUPPLIED;
     // reference levels 4, previous frames 2, chain resume points 4, event arena at its initial
     // capacity of 2 keys per pixel 16, sort buffers 32, FIFO 16; sparse: selection masks 16 and
-    // active list 4; difference method: the frames before the previous ones 2; staging: one
-    // frame (+ flow) per queued slot
-    uint64_t per_px = 4 + 2 + 4 + 16 + 32 + 16 + (sparse ? 20 : 0) +
+    // active lists 8 (the selection's and the length-ordered one); difference method: the
+    // frames before the previous ones 2; staging: one frame (+ flow) per queued slot
+    uint64_t per_px = 4 + 2 + 4 + 16 + 32 + 16 + (sparse ? 24 : 0) +
                       (cfg->method == SIM_DIFFERENCE ? 2 : 0);
     per_px += (uint64_t)queue_depth * (1 + (interp ? 8 : 0));
     // estimated flow: a pyramid (at most 4/3 of a float frame) per frame of a step and one

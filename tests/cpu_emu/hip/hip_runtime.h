@@ -24,7 +24,7 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
-#define __align__(n) alignas(n)
+#define __align__(n) __attribute__((aligned(n)))
 #define __shared__ thread_local
 #ifndef __restrict__
 #define __restrict__ __restrict
@@ -104,6 +104,8 @@ inline T emu_shfl_up(T v, unsigned delta, int width, int line) {
 inline int __popc(unsigned v) { return __builtin_popcount(v); }
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 inline int __ffs(unsigned v) { return __builtin_ffs((int)v); }
+inline int __ffsll(long long v) { return __builtin_ffsll(v); }
+inline unsigned __umul24(unsigned a, unsigned b) { return (a & 0xFFFFFFu) * (b & 0xFFFFFFu); }
 
 // single OS thread runs every fiber: plain read-modify-write is atomic
 template <class T, class U>

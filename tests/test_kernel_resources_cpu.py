@@ -14,11 +14,13 @@ from paper_2209_04634_amd import build as hipbuild
 CSRC = os.path.join(hipbuild.ROOT, "paper_2209_04634_amd", "csrc")
 KERNEL_SOURCES = ["evsim_kernels.hip", "evsim_lk.hip"]
 
-# waves per SIMD the hot kernels must keep (their current values; lower only on purpose)
+# waves per SIMD the hot kernels must keep (their current values; lower only on purpose).  The
+# chain kernels hold the texel loads of ten interior samples (two for difference frames) in flight
+# per lane, which costs registers: two waves per SIMD, measured faster than five with two samples.
 MIN_OCCUPANCY = {
-    "_ZN5evsim7k_chainILi0EEEvNS_9ChainArgsE": 6,          # reference-level chain
-    "_ZN5evsim7k_chainILi1EEEvNS_9ChainArgsE": 7,          # memoryless chain
-    "_ZN5evsim7k_chainILi2EEEvNS_9ChainArgsE": 6,          # difference-frame chain
+    "_ZN5evsim7k_chainILi0EEEvNS_9ChainArgsE": 2,          # reference-level chain
+    "_ZN5evsim7k_chainILi1EEEvNS_9ChainArgsE": 2,          # memoryless chain
+    "_ZN5evsim7k_chainILi2EEEvNS_9ChainArgsE": 4,          # difference-frame chain
     "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 8,       # selection pass
     "_ZN5evsim12k_radix_histEPKmPKyiPji": 8,
     "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 8,
