@@ -27,8 +27,6 @@ constexpr int kSelectPx = 1024;      // pixels per selection block (4 per thread
 // selected intervals in the window (the last class: kClasses or more).  The chain pass takes the
 // classes longest first, so the 64 lanes of a wave walk chains of (nearly) equal length.
 constexpr int kClasses = 16;
-constexpr int kClassShift = 24;      // active-list entry: pixel | class << kClassShift
-constexpr uint32_t kPixelMask = (1u << kClassShift) - 1u;   // pixel indices < 4096 * 4096
 // The event arena of one window holds fewer than kArenaKeyLimit keys (so every count, offset and
 // prefix sum over it fits 32 bits), hence each sub-arena fewer than kArenaKeyLimit / kArenaStripes.
 constexpr uint64_t kArenaKeyLimit = 1ull << 31;
@@ -58,7 +56,9 @@ struct KeyLayout {
 };
 
 // Selection pass (sparse method): streams every frame of the window once, writes the per-pixel
-// bitmask of selected intervals, compacts the pixels selected at least once into an active list.
+// bitmask of selected intervals, and writes each block's pixels selected at least once as one run
+// (at block * kSelectPx of act_px), longest length class first, pixel order within a class.  No
+// atomics: per-block counts go to plain arrays for the order pass.
 struct SelectArgs {
     const uint8_t* prev;        // frame before the window, uint8 [H][W]
     const uint8_t* frames;      // window frames; frame j at frames + j * fstride
@@ -66,25 +66,26 @@ struct SelectArgs {
     const float* lut;           // 256-entry transform table
     uint8_t* prev_out;          // receives the window's last frame
     uint32_t* mask;             // [kMaskWords][npix] selected-interval bits
-    uint32_t* act_px;           // kActStripes sub-lists of act_cap slots: pixel | class << 24
-    unsigned int* n_active;     // kActStripes counters (stride kCounterStride)
-    unsigned int* n_class;      // [kActStripes][kClasses] active pixels per sub-list and class
-                                // (stride kCounterStride)
-    unsigned long long* stats;  // kStatStripes counter pairs: += selected pixel-intervals, active px
-    int npix, K, act_cap;
+    uint32_t* act_px;           // per block: its run of active pixels (kSelectPx slots)
+    uint32_t* counts;           // [block][kClasses] active pixels per length class
+    uint32_t* bsel;             // [block] selected pixel-intervals
+    int npix, K;
     float m;
 };
 
-// Order pass (sparse method): the active pixels of the selection's sub-lists into one list,
-// chain-length classes longest first, resume points cleared.
+// Order pass (sparse method): the selection blocks' runs into one list of active pixels, length
+// classes longest first, blocks in order within a class (so the list is deterministic), resume
+// points cleared.  Two kernels: a one-block scan of the per-block counts, then the copy.
 struct OrderArgs {
-    const uint32_t* act_px;     // selection sub-lists (pixel | class << kClassShift)
-    const unsigned int* n_active;
-    const unsigned int* n_class;
-    unsigned int* cursor;       // [kActStripes][kClasses] placement counters, zero at entry
-    uint32_t* ord;              // ordered pixels, sum(n_active) entries
+    const uint32_t* act_px;     // the selection's runs
+    const uint32_t* counts;     // [block][kClasses]
+    const uint32_t* bsel;       // [block]
+    int nblocks;
+    uint32_t* goff;             // [block][kClasses]: place of the block's class run in ord
+    unsigned int* n_total;      // length of ord
+    unsigned long long* stats;  // += selected pixel-intervals, active pixels (one atomic each)
+    uint32_t* ord;
     int* resume;                // per ordered slot: set to 0
-    int act_cap;
 };
 
 // Chain pass: one lane per active pixel (sparse) or per pixel (dense, basic) walks its selected
@@ -100,9 +101,7 @@ struct ChainArgs {
     float* lref;                // per-pixel reference level, updated in place
     const uint32_t* mask;       // sparse: [kMaskWords][npix]; null: every interval selected
     const uint32_t* act_px;     // sparse: the ordered active list; null: slot = pixel
-    const unsigned int* n_active;  // sparse: the selection's sub-list lengths (their sum is the
-                                   // ordered list's length); null: npix slots
-    int act_cap;                // sparse: slots per selection sub-list (unused by the chain pass)
+    const unsigned int* n_active;  // sparse: its length (one counter); null: npix slots
     int* resume;                // per slot: first interval still to run (updated on exit)
     uint64_t* arena;            // kArenaStripes sub-arenas of stripe_cap keys
     uint64_t stripe_cap;
@@ -129,6 +128,8 @@ hipError_t launch_init(const uint8_t* frame, const float* lut, float* lref, uint
                        int64_t npix, hipStream_t stream);
 hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
 hipError_t launch_order(const OrderArgs& a, hipStream_t stream);
+// Blocks of the selection (and of the order copy) for npix pixels.
+inline int select_blocks(int64_t npix) { return (int)((npix + kSelectPx - 1) / kSelectPx); }
 hipError_t launch_chain(const ChainArgs& a, int max_slots, hipStream_t stream);
 // Concatenates the used part of every sub-arena into `out`; writes the total to *n_total.
 hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
@@ -139,16 +140,10 @@ hipError_t launch_clamp(unsigned long long* reserve, uint64_t cap, hipStream_t s
 hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream_t stream);
 // Zero-fills `bytes` (a multiple of 4) at p with a kernel (no memset node in a captured graph).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
-// Clears a window's counters[4], the reservation counters, n_active, n_class and the order
-// cursors (if n_active is not null: sparse) and resume[npix] (if not null: the other methods) in
-// one launch.  n_class and cursor are kActStripes * kClasses counters each (stride
-// kCounterStride) right after n_active's kActStripes.
+// Clears a window's counters[4], the reservation counters and resume[npix] (if not null: every
+// method but the sparse one, whose order pass clears its own) in one launch.
 hipError_t launch_prep_window(unsigned long long* counters, unsigned long long* reserve,
-                              unsigned int* n_active, int* resume, int64_t npix,
-                              hipStream_t stream);
-// Counters of the sparse method's active lists, one allocation: n_active, then n_class, then the
-// order cursors.
-constexpr int kActCounters = (kActStripes + 2 * kActStripes * kClasses) * kCounterStride;
+                              int* resume, int64_t npix, hipStream_t stream);
 // Sorts keys[0, *n) on bits [0, nbits) (stable LSD radix, 8-bit digits); the last pass writes
 // into `out` converted by `cv`.  The count is read on the device; grids are sized for n_max.
 // `alt` holds n_max keys; `hist` holds sort_hist_entries(n_max) counters and `totals` 256.
@@ -199,7 +194,8 @@ struct BatchEntry {
 hipError_t launch_batch_prep(const BatchEntry* e, int n, hipStream_t stream);
 hipError_t launch_batch_select(const BatchEntry* e, const int* start, int n, int blocks,
                                hipStream_t stream);
-// Order pass of the sparse entries (entries without one own no block).
+// Order pass of the sparse entries: one scan block per entry (non-sparse entries' blocks return),
+// then the copy (entries without one own no block).
 hipError_t launch_batch_order(const BatchEntry* e, const int* start, int n, int blocks,
                               hipStream_t stream);
 hipError_t launch_batch_chain(const BatchEntry* e, const int* start, int n, int blocks, int mode,
@@ -255,9 +251,8 @@ struct LkWindowArgs {
     PyrLayout lay;
     LkParams P;
     const uint32_t* mask;            // sparse: [kMaskWords][npix]; null: every interval
-    const uint32_t* act_px;          // sparse: active sub-lists; null: slot = pixel
-    const unsigned int* n_active;
-    int act_cap;
+    const uint32_t* act_px;          // sparse: the ordered active list; null: slot = pixel
+    const unsigned int* n_active;    // sparse: its length
     int npix, W, K;
     float* flow;
 };

@@ -399,6 +399,49 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Per-class counts over a wave, without atomics on shared addresses: every lane contributes
+// packed 16-bit counts of the kClasses length classes (four classes per word); returns the lane's
+// exclusive prefix in *excl and the wave's totals in *tot (both packed the same way).  Each field
+// stays below 2^16 (a wave counts at most 256 pixels).
+constexpr int kClassWords = 4;   // kClasses / 4
+__device__ __forceinline__ void wave_class_counts(const uint64_t (&mine)[kClassWords],
+                                                  uint64_t (&excl)[kClassWords],
+                                                  uint64_t (&tot)[kClassWords]) {
+#pragma unroll
+    for (int k = 0; k < kClassWords; ++k) {
+        const uint64_t inc = wave_incl_scan_u64(mine[k]);
+        excl[k] = inc - mine[k];
+        tot[k] = __shfl(inc, 63, 64);
+    }
+}
+
+// Field c of packed class counts (selects, no indexed access, so the words stay in registers).
+__device__ __forceinline__ uint32_t class_field(const uint64_t (&w)[kClassWords], uint32_t c) {
+    const uint32_t k = c >> 2;
+    const uint64_t v = k == 0 ? w[0] : (k == 1 ? w[1] : (k == 2 ? w[2] : w[3]));
+    return (uint32_t)(v >> (16 * (c & 3u))) & 0xFFFFu;
+}
+
+// Adds one to field c of packed class counts.
+__device__ __forceinline__ void class_add(uint64_t (&w)[kClassWords], uint32_t c) {
+    const uint64_t one = 1ull << (16 * (c & 3u));
+    const uint32_t k = c >> 2;
+    w[0] += k == 0 ? one : 0ull;
+    w[1] += k == 1 ? one : 0ull;
+    w[2] += k == 2 ? one : 0ull;
+    w[3] += k == 3 ? one : 0ull;
+}
+
 __device__ __forceinline__ uint32_t pick4(uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3,
                                           int w) {
     return w == 0 ? m0 : (w == 1 ? m1 : (w == 2 ? m2 : m3));
@@ -427,12 +470,10 @@ __device__ __forceinline__ int next_selected(bool all, uint32_t m0, uint32_t m1,
 template <bool VEC>
 __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
     __shared__ float lut[256];
-    __shared__ unsigned int s_cls[kClasses];    // this block's active pixels per length class
     const int tid = threadIdx.x;
     lut[tid] = a.lut[tid];
-    if (tid < kClasses) s_cls[tid] = 0u;
     __syncthreads();
-    const int lane = tid & 63;
+    const int lane = tid & 63, wv = tid >> 6;
     const int base = (bid * 256 + tid) * 4;
     const int cnt = max(0, min(4, a.npix - base));
 
@@ -464,10 +505,17 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
             last = v;
         };
         if (VEC && cnt == 4) {
-            // branch-free, so that the unrolled loads of several frames are in flight together
-#pragma unroll 8
-            for (int jj = 0; jj < jend; ++jj)
-                step(*(const uint32_t*)(Fw + (int64_t)jj * a.fstride), jj);
+            // eight frames' loads issued before any is used, so that they are in flight together
+            int jj = 0;
+            for (; jj + 8 <= jend; jj += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = *(const uint32_t*)(Fw + (int64_t)(jj + u) * a.fstride);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) step(v[u], jj + u);
+            }
+            for (; jj < jend; ++jj) step(*(const uint32_t*)(Fw + (int64_t)jj * a.fstride), jj);
         } else {
             for (int jj = 0; jj < jend; ++jj) {
                 const uint8_t* F = Fw + (int64_t)jj * a.fstride;
@@ -491,99 +539,147 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
         for (int q = 0; q < cnt; ++q) a.prev_out[base + q] = (uint8_t)(last >> (8 * q));
     }
 
-    __shared__ int s_wsum[4];
-    __shared__ unsigned int s_slot0;
-    int na = 0;
+    // The block's run of active pixels: class kClasses-1 first, pixel order within a class.
+    // Ranks come from a block-wide exclusive scan of packed per-class counts (no atomics).
+    __shared__ uint64_t s_wt[4][kClassWords];   // per wave: class totals
+    __shared__ uint32_t s_cs[kClasses];         // start of each class in the run
+    __shared__ uint32_t s_nsel[4];
     uint32_t cls[4];
+    bool act[4];
+    uint64_t cw[kClassWords] = {0ull, 0ull, 0ull, 0ull};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         nsel += plen[q];
         cls[q] = (uint32_t)(min(plen[q], kClasses) - 1);
-        if (q < cnt && any[q] != 0u) {
-            ++na;
-            atomicAdd(&s_cls[cls[q]], 1u);
-        }
+        act[q] = q < cnt && any[q] != 0u;
+        if (act[q]) class_add(cw, cls[q]);
     }
-    int total;
-    const int off = block_scan_256(na, s_wsum, &total);
-    __syncthreads();
-    int sel_total;
-    block_scan_256(nsel, s_wsum, &sel_total);
-    const int stripe = bid % kActStripes;
-    if (tid == 0) {
-        s_slot0 = total > 0 ? atomicAdd(a.n_active + stripe * kCounterStride, (unsigned int)total)
-                            : 0u;
-        unsigned long long* st = a.stats + (bid % kStatStripes) * kCounterStride;
-        if (sel_total > 0) atomicAdd(st, (unsigned long long)sel_total);
-        if (total > 0) atomicAdd(st + 1, (unsigned long long)total);
+    uint64_t ex[kClassWords], wt[kClassWords];
+    wave_class_counts(cw, ex, wt);
+    const int wsel = wave_incl_scan(nsel);
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < kClassWords; ++k) s_wt[wv][k] = wt[k];
+        s_nsel[wv] = (uint32_t)wsel;
     }
-    if (tid < kClasses && s_cls[tid] != 0u)
-        atomicAdd(a.n_class + (stripe * kClasses + tid) * kCounterStride, s_cls[tid]);
     __syncthreads();
-    unsigned int slot = (unsigned int)stripe * (unsigned int)a.act_cap + s_slot0 + (unsigned int)off;
+    uint64_t bt[kClassWords], wp[kClassWords];
+#pragma unroll
+    for (int k = 0; k < kClassWords; ++k) {
+        bt[k] = s_wt[0][k] + s_wt[1][k] + s_wt[2][k] + s_wt[3][k];
+        wp[k] = 0ull;
+        for (int j = 0; j < wv; ++j) wp[k] += s_wt[j][k];
+    }
+    if (tid < kClasses) {
+        uint32_t start = 0u;
+        for (int c = kClasses - 1; c > tid; --c) start += class_field(bt, (uint32_t)c);
+        s_cs[tid] = start;
+        a.counts[(size_t)bid * kClasses + tid] = class_field(bt, (uint32_t)tid);
+    }
+    if (tid == 0) a.bsel[bid] = s_nsel[0] + s_nsel[1] + s_nsel[2] + s_nsel[3];
+    __syncthreads();
+    uint32_t* run = a.act_px + (size_t)bid * kSelectPx;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (q < cnt && any[q] != 0u) {
-            a.act_px[slot] = (uint32_t)(base + q) | (cls[q] << kClassShift);
-            ++slot;
+        if (act[q]) {
+            uint32_t r = class_field(ex, cls[q]) + class_field(wp, cls[q]);
+#pragma unroll
+            for (int q2 = 0; q2 < 3; ++q2)
+                if (q2 < q) r += (act[q2] && cls[q2] == cls[q]) ? 1u : 0u;
+            run[s_cs[cls[q]] + r] = (uint32_t)(base + q);
         }
     }
-    (void)lane;
 }
 
 // ------------------------------------------------------------------------------------------
-// Order pass of the sparse method: the selection's sub-lists into one list of active pixels,
-// length classes longest first (within a class: sub-list by sub-list, each in placement order),
-// with their resume points cleared.  A wave's 64 slots lie in one sub-list (act_cap is a multiple
-// of kSelectPx); per class present in the wave one lane reserves the wave's places with one
-// atomic on the (sub-list, class) cursor.  Which pixel lands in which slot of its segment depends
-// on the order of those atomics; the events do not (they are sorted by key afterwards).
+// Order pass of the sparse method: the selection blocks' runs into one list, length classes
+// longest first and, within a class, blocks in order (a deterministic list), resume points
+// cleared.  k_order_scan (one block, a wave per class) places every (block, class) run; k_order_copy
+// (a block per selection block) moves the runs.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void order_block(const OrderArgs& a, unsigned bid) {
-    // segment start per (sub-list, class): exclusive scan of the counts in the order
-    // (class descending, sub-list ascending); thread t holds the count of the t-th segment
-    __shared__ unsigned int s_seg[kActStripes * kClasses];
-    __shared__ int s_wsum[4];
-    static_assert(kActStripes * kClasses <= 256, "one thread per segment");
+__device__ __forceinline__ void order_scan_block(const OrderArgs& a) {
+    static_assert(kClasses * 64 == 1024, "one wave per class");
+    __shared__ uint32_t s_tot[kClasses];
+    __shared__ uint64_t s_sel[kClasses];
     const int tid = threadIdx.x, lane = tid & 63;
-    const int seg_c = kClasses - 1 - tid / kActStripes, seg_st = tid % kActStripes;
-    const bool is_seg = tid < kActStripes * kClasses;
-    const int cnt =
-        is_seg ? (int)a.n_class[(seg_st * kClasses + seg_c) * kCounterStride] : 0;
-    int seg_total;
-    const int seg_start = block_scan_256(cnt, s_wsum, &seg_total);
-    if (is_seg) s_seg[seg_st * kClasses + seg_c] = (unsigned int)seg_start;
-    __syncthreads();
-    const int slot = (int)bid * 256 + tid;
-    const int stripe = slot / a.act_cap;
-    const bool valid = stripe < kActStripes &&
-                       (slot - stripe * a.act_cap) < (int)a.n_active[stripe * kCounterStride];
-    uint32_t v = valid ? a.act_px[slot] : 0u;
-    const uint32_t c = v >> kClassShift;
-    const uint64_t lt = (1ull << lane) - 1ull;
-    bool left = valid;
-    while (__any(left)) {
-        const uint64_t lm = __ballot(left);
-        const int leader = __ffsll((long long)lm) - 1;
-        const uint32_t cl = (uint32_t)__shfl((int)c, leader, 64);
-        const bool mine = left && c == cl;
-        const uint64_t m = __ballot(mine);
-        unsigned int base = 0u;
-        if (lane == leader)
-            base = atomicAdd(a.cursor + (stripe * kClasses + (int)cl) * kCounterStride,
-                             (unsigned int)__popcll(m));
-        base = (unsigned int)__shfl((int)base, leader, 64);
-        if (mine) {
-            const unsigned int pos =
-                s_seg[stripe * kClasses + (int)cl] + base + (unsigned int)__popcll(m & lt);
-            a.ord[pos] = v & kPixelMask;
-            a.resume[pos] = 0;
-            left = false;
+    const int c = kClasses - 1 - (tid >> 6);      // wave w scans class kClasses-1-w
+    const int nb = a.nblocks;
+    const int per = (nb + 63) / 64;
+    const int b0 = min(nb, lane * per), b1 = min(nb, b0 + per);
+    // loads in groups of 16, issued before they are summed
+    uint32_t sum = 0u;
+    uint64_t sel = 0ull;
+    for (int b = b0; b < b1; b += 16) {
+        uint32_t v[16], w[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            v[u] = b + u < b1 ? a.counts[(size_t)(b + u) * kClasses + c] : 0u;
+            w[u] = (c == 0 && b + u < b1) ? a.bsel[b + u] : 0u;   // selected, counted once
         }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            sum += v[u];
+            sel += w[u];
+        }
+    }
+    const int inc = wave_incl_scan((int)sum);
+    const uint64_t sinc = wave_incl_scan_u64(sel);
+    if (lane == 63) {
+        s_tot[c] = (uint32_t)inc;
+        s_sel[c] = sinc;
+    }
+    __syncthreads();
+    uint32_t cbase = 0u;
+    for (int c2 = kClasses - 1; c2 > c; --c2) cbase += s_tot[c2];
+    uint32_t pos = cbase + (uint32_t)(inc - (int)sum);
+    for (int b = b0; b < b1; b += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = b + u < b1 ? a.counts[(size_t)(b + u) * kClasses + c] : 0u;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (b + u < b1) a.goff[(size_t)(b + u) * kClasses + c] = pos;
+            pos += v[u];
+        }
+    }
+    if (tid == 0) {
+        uint32_t total = 0u;
+        for (int c2 = 0; c2 < kClasses; ++c2) total += s_tot[c2];
+        *a.n_total = total;
+        if (s_sel[0] > 0) atomicAdd(a.stats, (unsigned long long)s_sel[0]);
+        if (total > 0) atomicAdd(a.stats + 1, (unsigned long long)total);
     }
 }
 
-__global__ __launch_bounds__(256) void k_order(OrderArgs a) { order_block(a, blockIdx.x); }
+__device__ __forceinline__ void order_copy_block(const OrderArgs& a, unsigned bid) {
+    __shared__ uint32_t s_start[kClasses + 1];    // class starts within the run, descending
+    __shared__ uint32_t s_goff[kClasses];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        uint32_t pos = 0u;
+        for (int c = kClasses - 1; c >= 0; --c) {
+            s_start[c] = pos;
+            pos += a.counts[(size_t)bid * kClasses + c];
+        }
+        s_start[kClasses] = pos;
+    }
+    if (tid < kClasses) s_goff[tid] = a.goff[(size_t)bid * kClasses + tid];
+    __syncthreads();
+    const uint32_t n = s_start[kClasses];
+    const uint32_t* run = a.act_px + (size_t)bid * kSelectPx;
+    for (uint32_t i = tid; i < n; i += 256) {
+        int c = kClasses - 1;
+        while (c > 0 && i >= s_start[c - 1]) --c;   // the class whose part of the run holds i
+        const uint32_t dst = s_goff[c] + (i - s_start[c]);
+        a.ord[dst] = run[i];
+        a.resume[dst] = 0;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_order_scan(OrderArgs a) { order_scan_block(a); }
+__global__ __launch_bounds__(256) void k_order_copy(OrderArgs a) {
+    order_copy_block(a, blockIdx.x);
+}
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
@@ -615,9 +711,7 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
     const int slot = bid * kSimThreads + tid;
     bool valid;
     if (a.act_px) {
-        unsigned int n_act = 0;
-        for (int st = 0; st < kActStripes; ++st) n_act += a.n_active[st * kCounterStride];
-        valid = slot < (int)n_act;
+        valid = slot < (int)*a.n_active;
     } else {
         valid = slot < a.npix;
     }
@@ -1013,14 +1107,11 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* __restrict__ p, uint
 // and the per-pixel resume points (every other method).
 __global__ __launch_bounds__(256) void k_prep_window(unsigned long long* __restrict__ counters,
                                                      unsigned long long* __restrict__ reserve,
-                                                     unsigned int* __restrict__ n_active,
                                                      int* __restrict__ resume, int64_t npix) {
     const int tid = threadIdx.x;
     if (blockIdx.x == 0) {
         if (tid < 4) counters[tid] = 0ull;
         for (int i = tid; i < kArenaStripes * kCounterStride; i += 256) reserve[i] = 0ull;
-        if (n_active)
-            for (int i = tid; i < kActCounters; i += 256) n_active[i] = 0u;
     }
     if (resume) {
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1052,9 +1143,9 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_order(const OrderArgs& a, hipStream_t stream) {
-    const int blocks = kActStripes * a.act_cap / 256;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_order, dim3(blocks), dim3(256), 0, stream, a);
+    if (a.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL(k_order_copy, dim3(a.nblocks), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -1107,13 +1198,12 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
 }
 
 hipError_t launch_prep_window(unsigned long long* counters, unsigned long long* reserve,
-                              unsigned int* n_active, int* resume, int64_t npix,
-                              hipStream_t stream) {
+                              int* resume, int64_t npix, hipStream_t stream) {
     const int64_t blocks = resume ? std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256,
                                                                             1024))
                                   : 1;
     hipLaunchKernelGGL(k_prep_window, dim3((unsigned)blocks), dim3(256), 0, stream, counters,
-                       reserve, n_active, resume, npix);
+                       reserve, resume, npix);
     return hipGetLastError();
 }
 
@@ -1200,8 +1290,6 @@ __global__ __launch_bounds__(256) void k_batch_prep(const BatchEntry* __restrict
     unsigned long long* reserve = e->chain.reserve;
     for (int i = tid; i < kArenaStripes * kCounterStride; i += 256) reserve[i] = 0ull;
     if (tid < 4) e->counters[tid] = 0ull;
-    if (e->sparse)
-        for (int i = tid; i < kActCounters; i += 256) e->sel.n_active[i] = 0u;
 }
 
 // Selection pass of sparse entries; frame copies and chain resets of the others (kSelectPx
@@ -1227,10 +1315,17 @@ __global__ __launch_bounds__(256) void k_batch_select(const BatchEntry* __restri
     }
 }
 
-__global__ __launch_bounds__(256) void k_batch_order(const BatchEntry* __restrict__ entries,
-                                                     const int* __restrict__ start, int n) {
+// One scan block per entry (blockIdx.x = entry); entries that are not sparse return.
+__global__ __launch_bounds__(1024) void k_batch_order_scan(const BatchEntry* __restrict__ entries) {
+    const BatchEntry* e = entries + blockIdx.x;
+    if (!e->sparse) return;
+    order_scan_block(e->ord);
+}
+
+__global__ __launch_bounds__(256) void k_batch_order_copy(const BatchEntry* __restrict__ entries,
+                                                          const int* __restrict__ start, int n) {
     const int ei = batch_entry(start, n, blockIdx.x);
-    order_block(entries[ei].ord, blockIdx.x - (unsigned)start[ei]);
+    order_copy_block(entries[ei].ord, blockIdx.x - (unsigned)start[ei]);
 }
 
 template <int MODE>
@@ -1320,7 +1415,8 @@ hipError_t launch_batch_select(const BatchEntry* e, const int* start, int n, int
 hipError_t launch_batch_order(const BatchEntry* e, const int* start, int n, int blocks,
                               hipStream_t stream) {
     if (n <= 0 || blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_order, dim3(blocks), dim3(256), 0, stream, e, start, n);
+    hipLaunchKernelGGL(k_batch_order_scan, dim3(n), dim3(1024), 0, stream, e);
+    hipLaunchKernelGGL(k_batch_order_copy, dim3(blocks), dim3(256), 0, stream, e, start, n);
     return hipGetLastError();
 }
 

@@ -219,11 +219,8 @@ __global__ __launch_bounds__(256) void k_lk_window(LkWindowArgs a) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     int p;
     if (a.act_px) {
-        const int stripe = slot / a.act_cap;
-        if (stripe >= kActStripes ||
-            slot - stripe * a.act_cap >= (int)a.n_active[stripe * kCounterStride])
-            return;
-        p = (int)(a.act_px[slot] & kPixelMask);
+        if (slot >= (int)*a.n_active) return;
+        p = (int)a.act_px[slot];
     } else {
         if (slot >= a.npix) return;
         p = slot;

@@ -74,7 +74,6 @@ struct sim_stream {
     uint64_t stripe_cap = 0;
     unsigned long long* d_reserve = nullptr;     // per sub-arena reservation counters
     unsigned long long* d_stats = nullptr;       // striped selection statistics
-    int act_cap = 0;                             // sparse: slots per active sub-list
     uint64_t* d_alt = nullptr;                   // gathered keys (sort input)
     uint64_t alt_cap = 0;
     uint64_t* d_alt2 = nullptr;                  // sort ping-pong buffer; never the arena, which
@@ -89,8 +88,9 @@ struct sim_stream {
     int64_t* d_tbase = nullptr;
     int* d_resume = nullptr;                     // per chain slot
     uint32_t* d_mask = nullptr;                  // sparse: [kMaskWords][npix]
-    uint32_t* d_act = nullptr;                   // sparse: active pixel sub-lists (selection)
-    unsigned int* d_nact = nullptr;              // sparse: their lengths, length classes, cursors
+    uint32_t* d_act = nullptr;                   // sparse: the selection blocks' runs
+    uint32_t* d_olist = nullptr;                 // sparse: per-block class counts, run places,
+                                                 // selected counts, the ordered list's length
     uint32_t* d_ord = nullptr;                   // sparse: active pixels ordered by chain length
     float* h_delta = nullptr;                    // pinned
     int64_t* h_tbase = nullptr;                  // pinned
@@ -187,7 +187,7 @@ void free_stream(sim_stream* s) {
     dfree(s->d_counters);
     dfree(s->d_mask);
     dfree(s->d_act);
-    dfree(s->d_nact);
+    dfree(s->d_olist);
     dfree(s->d_ord);
     dfree(s->d_delta);
     dfree(s->d_tbase);
@@ -337,22 +337,27 @@ int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const 
     sa->lut = s->d_lut;
     sa->prev_out = s->d_prev[1 - s->cur];
     sa->mask = s->d_mask;
+    const int nblk = select_blocks(s->npix);
+    uint32_t* counts = s->d_olist;
+    uint32_t* goff = counts ? counts + (size_t)nblk * kClasses : nullptr;
+    uint32_t* bsel = goff ? goff + (size_t)nblk * kClasses : nullptr;
+    unsigned int* n_total = bsel ? bsel + nblk : nullptr;
     sa->act_px = s->d_act;
-    sa->n_active = s->d_nact;
-    sa->n_class = s->d_nact ? s->d_nact + kActStripes * kCounterStride : nullptr;
-    sa->stats = s->d_stats;
+    sa->counts = counts;
+    sa->bsel = bsel;
     sa->npix = (int)s->npix;
     sa->K = K;
-    sa->act_cap = s->act_cap;
     sa->m = s->m;
 
     oa->act_px = s->d_act;
-    oa->n_active = s->d_nact;
-    oa->n_class = sa->n_class;
-    oa->cursor = s->d_nact ? sa->n_class + kActStripes * kClasses * kCounterStride : nullptr;
+    oa->counts = counts;
+    oa->bsel = bsel;
+    oa->nblocks = nblk;
+    oa->goff = goff;
+    oa->n_total = n_total;
+    oa->stats = s->d_stats;
     oa->ord = s->d_ord;
     oa->resume = s->d_resume;
-    oa->act_cap = s->act_cap;
 
     const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
     a->prev = s->d_prev[s->cur];
@@ -365,8 +370,7 @@ int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const 
     a->lref = s->d_lref;
     a->mask = sparse ? s->d_mask : nullptr;
     a->act_px = sparse ? s->d_ord : nullptr;
-    a->n_active = sparse ? s->d_nact : nullptr;
-    a->act_cap = s->act_cap;
+    a->n_active = sparse ? n_total : nullptr;
     a->resume = s->d_resume;
     a->reserve = s->d_reserve;
     a->fails = s->d_counters;          // [0] failed reservations, [1] sentinels, [2] gathered
@@ -392,9 +396,11 @@ int plan_window(sim_stream* s, const uint8_t* frames, const float* flows, const 
 // Slots of the chain pass: the ordered active list (sparse) or every pixel.
 int chain_slots(const sim_stream* s) { return (int)s->npix; }
 
-// Slots of the selection's sub-lists (sparse) or every pixel.
-int select_slots(const sim_stream* s) {
-    return s->cfg.method == SIM_SPARSE ? kActStripes * s->act_cap : (int)s->npix;
+// Words of d_olist: counts and run places per (block, class), selected counts per block, the
+// ordered list's length.
+size_t olist_words(int64_t npix) {
+    const size_t nblk = (size_t)select_blocks(npix);
+    return 2 * nblk * kClasses + nblk + 1;
 }
 
 // Estimated flow (SIM_FLOW_LK): buffers for a window of K intervals.
@@ -423,14 +429,13 @@ hipError_t launch_lk(sim_stream* s, const uint8_t* frames, int K, hipStream_t st
     la.lay = pl;
     la.P = s->lk;
     la.mask = sparse ? s->d_mask : nullptr;
-    la.act_px = sparse ? s->d_act : nullptr;
-    la.n_active = sparse ? s->d_nact : nullptr;
-    la.act_cap = s->act_cap;
+    la.act_px = sparse ? s->d_ord : nullptr;
+    la.n_active = sparse ? s->d_olist + olist_words(s->npix) - 1 : nullptr;
     la.npix = (int)s->npix;
     la.W = s->cfg.width;
     la.K = K;
     la.flow = s->d_lkflow;
-    return launch_lk_window(la, select_slots(s), stream);
+    return launch_lk_window(la, chain_slots(s), stream);
 }
 
 int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
@@ -454,8 +459,8 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
     HIP_TRY(s, hipMemcpyAsync(s->d_tbase, s->h_tbase, K * sizeof(int64_t), hipMemcpyHostToDevice,
                               s->stream));
     const bool sparse = s->cfg.method == SIM_SPARSE;
-    HIP_TRY(s, launch_prep_window(s->d_counters, s->d_reserve, sparse ? s->d_nact : nullptr,
-                                  sparse ? nullptr : s->d_resume, s->npix, s->stream));
+    HIP_TRY(s, launch_prep_window(s->d_counters, s->d_reserve, sparse ? nullptr : s->d_resume,
+                                  s->npix, s->stream));
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[0], s->stream));
     if (sparse) {
         HIP_TRY(s, launch_select(sa, s->stream));
@@ -838,7 +843,7 @@ int fused_window(std::vector<FusedItem>& items) {
         b.counters = s->d_counters;
         b.cv.tbase = d_tbase;
         sel_blocks[e] = (int)((s->npix + kSelectPx - 1) / kSelectPx);
-        order_blocks[e] = b.sparse ? kActStripes * s->act_cap / 256 : 0;
+        order_blocks[e] = b.sparse ? select_blocks(s->npix) : 0;
         const int m = b.chain.mode;
         chain_blocks[m][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
         max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
@@ -1155,8 +1160,7 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
         return SIM_E_INVAL;
     }
     const int sel_blocks = (int)((s->npix + kSelectPx - 1) / kSelectPx);
-    s->act_cap = ((sel_blocks + kActStripes - 1) / kActStripes) * kSelectPx;
-    const size_t slots = std::max<size_t>((size_t)s->npix, (size_t)kActStripes * s->act_cap);
+    const size_t slots = (size_t)s->npix;
     ok = ok && dev_alloc(&s->d_lut, 256) == hipSuccess;
     ok = ok && dev_alloc(&s->d_lref, s->npix) == hipSuccess;
     ok = ok && dev_alloc(&s->d_prev[0], s->npix) == hipSuccess;
@@ -1172,8 +1176,8 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     }
     if (cfg->method == SIM_SPARSE) {
         ok = ok && dev_alloc(&s->d_mask, (size_t)kMaskWords * s->npix) == hipSuccess;
-        ok = ok && dev_alloc(&s->d_act, (size_t)kActStripes * s->act_cap) == hipSuccess;
-        ok = ok && dev_alloc(&s->d_nact, (size_t)kActCounters) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_act, (size_t)sel_blocks * kSelectPx) == hipSuccess;
+        ok = ok && dev_alloc(&s->d_olist, olist_words(s->npix)) == hipSuccess;
         ok = ok && dev_alloc(&s->d_ord, (size_t)s->npix) == hipSuccess;
     }
     ok = ok && dev_alloc(&s->d_delta, kMaxWindow) == hipSuccess;

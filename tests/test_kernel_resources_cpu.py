@@ -21,7 +21,8 @@ MIN_OCCUPANCY = {
     "_ZN5evsim7k_chainILi0EEEvNS_9ChainArgsE": 2,          # reference-level chain
     "_ZN5evsim7k_chainILi1EEEvNS_9ChainArgsE": 2,          # memoryless chain
     "_ZN5evsim7k_chainILi2EEEvNS_9ChainArgsE": 4,          # difference-frame chain
-    "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 8,       # selection pass
+    # selection pass (a 1280x720 window launches 3.5 waves per SIMD: six per SIMD is ample)
+    "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 6,
     "_ZN5evsim12k_radix_histEPKmPKyiPji": 8,
     "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 8,
     "_ZN5evsim8k_gatherEPKmmPKyPmPy": 8,
