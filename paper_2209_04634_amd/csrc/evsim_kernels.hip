@@ -1028,40 +1028,47 @@ __device__ __forceinline__ uint64_t convert_key(uint64_t k, const ConvertArgs& c
     return (t << 25) | (y << 13) | (x << 1) | (pix & 1ull);
 }
 
+// One pass's scatter of a block's tile.  Each wave ranks its own quarter of the tile (keys
+// base + w * 1024 + j * 64 + lane, j = 0..15, the tile's order) against wave-private digit counts
+// in LDS: ballot peer matching gives the rank among the wave's lanes, the count before it the
+// rank among the wave's earlier keys, so no block barrier is needed until the quarters are
+// combined (the waves before w, per digit).  Stable: a key's place follows every key before it
+// in the tile with the same digit.
 __device__ __forceinline__ void scatter_block(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
     const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv, unsigned bid) {
+    static_assert(kSortThreads == 256 && kSortItems == 16, "four waves of 16 x 64 keys");
     __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_wc[4][256];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t n = *n_dev;
-    if ((uint64_t)bid * kSortTile >= n) return;
+    const uint64_t base = (uint64_t)bid * kSortTile;
+    if (base >= n) return;
     const uint64_t n_valid = cv.enabled ? n - *cv.n_sentinel : n;
+    const uint64_t wbase = base + (uint64_t)w * (kSortItems * 64) + lane;
+    uint64_t kv[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const uint64_t idx = wbase + (uint64_t)j * 64;
+        kv[j] = in[idx < n ? idx : n - 1];
+    }
     int tot;
     const int dex = block_scan_256((int)totals[tid], s_wsum, &tot);
     s_base[tid] = (uint32_t)dex + hist[(size_t)tid * nblocks + bid];
+    s_wc[0][tid] = 0u;
+    s_wc[1][tid] = 0u;
+    s_wc[2][tid] = 0u;
+    s_wc[3][tid] = 0u;
+    __syncthreads();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    const uint64_t base = (uint64_t)bid * kSortTile;
-    // each round loads the thread's key of the next round before ranking its own (indices past
-    // the end re-read the last key and are not used), so that the load overlaps a whole round
-    uint64_t next = in[base + tid < n ? base + tid : n - 1];
+    uint32_t lrank[kSortItems];
+    uint32_t* wc = s_wc[w];
+#pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        const uint64_t mine = next;
-        if (j + 1 < kSortItems) {
-            const uint64_t idx1 = base + (uint64_t)(j + 1) * kSortThreads + tid;
-            next = in[idx1 < n ? idx1 : n - 1];
-        }
-        s_wcnt[0][tid] = 0;
-        s_wcnt[1][tid] = 0;
-        s_wcnt[2][tid] = 0;
-        s_wcnt[3][tid] = 0;
-        __syncthreads();
-        const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
-        const bool valid = idx < n;
-        const uint64_t key = valid ? mine : 0ull;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const bool valid = wbase + (uint64_t)j * 64 < n;
+        const uint32_t d = (uint32_t)(kv[j] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -1069,20 +1076,37 @@ __device__ __forceinline__ void scatter_block(
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        if (valid && rank == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = 0;
-            for (int q = 0; q < w; ++q) pre += s_wcnt[q][d];
-            const uint64_t pos = (uint64_t)s_base[d] + pre + rank;
+        // the first lane of each digit group reads the wave's count and hands it to its group;
+        // after the exchange it advances the count (the next key's read comes after the next
+        // key's ballots, which every lane reaches only after this write)
+        const bool leader = valid && rank == 0;
+        const int src = valid ? __ffsll((long long)peers) - 1 : lane;
+        const uint32_t mine = leader ? wc[d] : 0u;
+        const uint32_t before = (uint32_t)__shfl((int)mine, src, 64);
+        lrank[j] = before + rank;
+        if (leader) wc[d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit (thread tid): the counts of the waves before each wave, in place
+    {
+        const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid];
+        s_wc[0][tid] = 0u;
+        s_wc[1][tid] = c0;
+        s_wc[2][tid] = c0 + c1;
+        s_wc[3][tid] = c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (wbase + (uint64_t)j * 64 < n) {
+            const uint32_t d = (uint32_t)(kv[j] >> shift) & 255u;
+            const uint64_t pos = (uint64_t)s_base[d] + wc[d] + lrank[j];
             if (!cv.enabled) {
-                out[pos] = key;
+                out[pos] = kv[j];
             } else if (pos < n_valid) {
-                out[pos] = convert_key(key, cv);
+                out[pos] = convert_key(kv[j], cv);
             }
         }
-        __syncthreads();
-        s_base[tid] += s_wcnt[0][tid] + s_wcnt[1][tid] + s_wcnt[2][tid] + s_wcnt[3][tid];
     }
 }
 

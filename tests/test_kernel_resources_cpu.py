@@ -24,7 +24,8 @@ MIN_OCCUPANCY = {
     # selection pass (a 1280x720 window launches 3.5 waves per SIMD: six per SIMD is ample)
     "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 6,
     "_ZN5evsim12k_radix_histEPKmPKyiPji": 8,
-    "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 8,
+    # the scatter holds its 16 keys and their ranks in registers for the wave-private ranking
+    "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 4,
     "_ZN5evsim8k_gatherEPKmmPKyPmPy": 8,
 }
 
