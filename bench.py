@@ -138,6 +138,7 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
         return ev
 
     res, secs = {}, {}
+    g0 = sim.batch_stats()
     for name, batched in (("batched", True), ("plain", False)):
         run(batched)                                   # warm-up: buffers reach their sizes
         t0 = time.perf_counter()
@@ -151,6 +152,8 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
         st.close()
     res["streams"] = args.batched
     res["speedup"] = round(secs["plain"] / secs["batched"], 3)
+    g1 = sim.batch_stats()
+    res["graphs"] = {k: g1[k] - g0[k] for k in g1}   # recorded, launched, re-run windows
     return res
 
 

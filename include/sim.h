@@ -201,8 +201,12 @@ typedef struct sim_frames {
 
 /* Pushes frames to n distinct streams at once, with exactly the result of n sim_push_frames
  * calls.  Streams of any resolution, method, thresholding mode and flow source may be combined:
- * each window of all streams runs as one launch per phase (clearing, selection, chains, overflow
- * re-runs, gather, every sort pass) on a library stream, with one host wait per phase.  The
+ * each window of all streams runs as one launch per phase (clearing, selection and ordering,
+ * chains, gather, every sort pass) on a library stream, all queued before one host wait; unless
+ * a stream estimates its flow, that sequence is recorded once as a HIP graph per launch shape
+ * (streams, sizes, sort passes) and replayed for later windows of the same shape.  Streams whose
+ * window ran out of event-buffer space, or produced more events than the sort was sized for,
+ * are finished after that wait by re-runs (one host wait per phase).  The
  * streams' earlier work is completed first; their events are ordered when the call returns.
  * Validation of every entry (and a handle listed twice, SIM_E_INVAL) happens before any work is
  * queued; on a validation error nothing changes.  Staging and buffer reservation follow per
@@ -212,6 +216,11 @@ typedef struct sim_frames {
  * reported per entry in `status`;
  * returns SIM_OK or the first error.  One batched push runs at a time per process. */
 int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n);
+
+/* Process-wide counts of the batched pushes since the library was loaded: graphs recorded,
+ * graph launches, and stream windows finished by re-runs (sim_push_batch).  Any pointer may be
+ * NULL.  Errors: none (returns SIM_OK). */
+int sim_batch_stats(uint64_t* graphs_recorded, uint64_t* graph_launches, uint64_t* rerun_windows);
 
 /* Number of events produced and not yet drained. */
 int sim_pending_events(sim_stream* s, uint64_t* n);

@@ -208,6 +208,9 @@ hipError_t launch_batch_clamp(const BatchEntry* e, int n, hipStream_t stream);
 hipError_t launch_batch_gather(const BatchEntry* e, const int* start, int n, int blocks,
                                hipStream_t stream);
 // out[2e] = sentinels, out[2e + 1] = gathered keys of entry e.
+// out[3e], out[3e + 1], out[3e + 2] = failed reservations, sentinels, gathered keys of entry e.
+hipError_t launch_batch_status(const BatchEntry* e, int n, unsigned long long* out,
+                               hipStream_t stream);
 hipError_t launch_batch_counts(const BatchEntry* e, int n, unsigned long long* out,
                                hipStream_t stream);
 // Every pass of the sort of every entry (`passes` passes; the last converts into `out`).

@@ -1382,6 +1382,17 @@ __global__ __launch_bounds__(kArenaStripes) void k_batch_gather(
                  e->counters + 2, blockIdx.x - (unsigned)start[ei]);
 }
 
+// out[3e .. 3e+2] = failed reservations, sentinels, gathered keys of entry e.
+__global__ void k_batch_status(const BatchEntry* __restrict__ entries, int n,
+                               unsigned long long* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) {
+        out[3 * e] = entries[e].counters[0];
+        out[3 * e + 1] = entries[e].counters[1];
+        out[3 * e + 2] = entries[e].counters[2];
+    }
+}
+
 __global__ void k_batch_counts(const BatchEntry* __restrict__ entries, int n,
                                unsigned long long* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1485,6 +1496,13 @@ hipError_t launch_batch_gather(const BatchEntry* e, const int* start, int n, int
     if (n <= 0 || blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_gather, dim3(blocks), dim3(kArenaStripes), 0, stream, e, start,
                        n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const BatchEntry* e, int n, unsigned long long* out,
+                               hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_status, dim3((n + 255) / 256), dim3(256), 0, stream, e, n, out);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -65,6 +66,8 @@ struct sim_stream {
     uint8_t* d_prev2[2] = {nullptr, nullptr};    // difference method: the frame before d_prev
     int cur = 0;
     uint64_t n_int = 0;                          // intervals simulated since the first frame
+    uint64_t est_events = 0;                     // most events of a batched window so far
+                                                 // (sizes the sort grid of the next one)
 
     bool started = false;
     int64_t epoch = 0, t_prev = 0;
@@ -705,9 +708,25 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
 // one per stream.  Per stream the kernels run the same block bodies on the same data as its
 // own launches, so every stream's result is that of the stream pushed alone.
 // ------------------------------------------------------------------------------------------
+// Launch shape of a fused chunk: what a recorded graph's nodes depend on besides the blob's
+// contents (grid sizes, sizes of the copies, the buffers the nodes read and write).
+struct BatchShape {
+    int n = 0;
+    size_t tab = 0;
+    std::array<int, 11> totals{};
+    const void* blob = nullptr;
+    const void* out = nullptr;
+    bool operator==(const BatchShape& o) const {
+        return n == o.n && tab == o.tab && totals == o.totals && blob == o.blob && out == o.out;
+    }
+};
+
 struct BatchCtx {
     std::mutex mu;                   // one fused batch at a time (shared buffers below)
     hipStream_t stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;   // the recorded chunk of the last shape
+    BatchShape graph_key;
+    uint64_t graph_captures = 0, graph_launches = 0, redo_windows = 0;
     char* h_blob = nullptr;          // pinned: entries, block offsets, per-interval tables
     size_t h_cap = 0;
     char* d_blob = nullptr;
@@ -730,6 +749,10 @@ bool batch_reserve(BatchCtx& c, size_t blob, size_t outs) {
         return false;
     if (blob > c.h_cap || blob > c.d_cap) {
         if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
+        if (c.graph_exec) {   // its nodes point at the buffers being replaced
+            (void)hipGraphExecDestroy(c.graph_exec);
+            c.graph_exec = nullptr;
+        }
         if (c.h_blob) (void)hipHostFree(c.h_blob);
         if (c.d_blob) (void)hipFree(c.d_blob);
         c.h_blob = nullptr;
@@ -742,6 +765,10 @@ bool batch_reserve(BatchCtx& c, size_t blob, size_t outs) {
     }
     if (outs > c.out_cap) {
         if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
+        if (c.graph_exec) {
+            (void)hipGraphExecDestroy(c.graph_exec);
+            c.graph_exec = nullptr;
+        }
         if (c.h_out) (void)hipHostFree(c.h_out);
         if (c.d_out) (void)hipFree(c.d_out);
         c.h_out = nullptr;
@@ -783,6 +810,17 @@ int fill_starts(int* start, const std::vector<int>& blocks) {
 
 // One window chunk of a batch: the streams in `items` (each with K >= 1 intervals).  Returns
 // SIM_OK or the status every participating item gets.
+//
+// Every grid is sized on the host before any work is queued (the event arena's capacity bounds a
+// window's events; the sort's grid follows a running estimate of the stream's events per window),
+// so the whole chunk -- upload of the entries, clears, selection and order, chains, gather, every
+// sort pass and the readback of each entry's status -- is queued with no host wait in between and
+// ends with one wait.  Without estimated flow (whose launches take per-window pointers) that
+// sequence is recorded once as a HIP graph per launch shape and replayed: its kernels find their
+// per-window arguments in the entry blob that the graph's first node uploads from pinned memory.
+// Entries whose chains ran out of arena space, or whose events outgrew the sort's grid, are
+// finished afterwards by the re-run path (grow the arena, resume the unfinished chains, gather and
+// sort again), which overwrites what the chunk's gather and sort wrote for them.
 int fused_window(std::vector<FusedItem>& items) {
     BatchCtx& c = batch_ctx();
     const int n = (int)items.size();
@@ -794,7 +832,7 @@ int fused_window(std::vector<FusedItem>& items) {
         f.tab_off = tab;
         tab += align8((size_t)f.K * sizeof(float)) + (size_t)f.K * sizeof(int64_t);
     }
-    if (!batch_reserve(c, tab, 2 * (size_t)n)) {
+    if (!batch_reserve(c, tab, 3 * (size_t)n)) {
         (void)hipGetLastError();
         return SIM_E_NOMEM;
     }
@@ -810,16 +848,38 @@ int fused_window(std::vector<FusedItem>& items) {
     for (FusedItem& f : items)
         if (hipStreamSynchronize(f.s->stream) != hipSuccess) return SIM_E_HIP;
 
-    std::vector<int> sel_blocks(n), order_blocks(n), chain_blocks[3], blocks(n);
+    std::vector<int> sel_blocks(n), order_blocks(n), chain_blocks[3], gather_blocks(n),
+        sort_blocks(n), blocks(n);
+    std::vector<uint64_t> sort_cap(n);
     for (int m = 0; m < 3; ++m) chain_blocks[m].assign(n, 0);
     int max_stash[3] = {0, 0, 0};
+    int passes = 1;
+    bool capturable = true;
     for (int e = 0; e < n; ++e) {
         FusedItem& f = items[e];
         sim_stream* s = f.s;
         if (s->cfg.flow_source == SIM_FLOW_LK && s->S > 1) {
             int rc = ensure_lk_buffers(s, f.K);
             if (rc) return rc;
+            capturable = false;
         }
+        // buffers for the most events the arena can hold, before anything changes
+        const uint64_t n_max = (uint64_t)kArenaStripes * s->stripe_cap;
+        // the sort's grid: twice the most events a window of this stream has had, rounded up to
+        // a power of two, so that steps of a steady stream keep one launch shape (the first
+        // window: the whole arena)
+        uint64_t want = n_max;
+        if (s->est_events) {
+            want = kSortTile;
+            while (want < 2 * s->est_events) want *= 2;
+        }
+        sort_cap[e] = std::min<uint64_t>(n_max, want);
+        int rc = ensure_alt(s, n_max);
+        if (!rc) rc = ensure_sort_scratch(s, n_max);
+        if (!rc && s->fifo_tail + n_max > s->fifo_cap)
+            rc = grow(s, &s->d_fifo, &s->fifo_cap,
+                      std::max<uint64_t>(s->fifo_tail + n_max, 2 * s->fifo_cap), s->fifo_tail);
+        if (rc) return rc;
         float* h_delta = (float*)(c.h_blob + f.tab_off);
         int64_t* h_tbase = (int64_t*)(c.h_blob + f.tab_off + align8((size_t)f.K * sizeof(float)));
         const float* d_delta = (const float*)(c.d_blob + f.tab_off);
@@ -827,8 +887,8 @@ int fused_window(std::vector<FusedItem>& items) {
             (const int64_t*)(c.d_blob + f.tab_off + align8((size_t)f.K * sizeof(float)));
         BatchEntry& b = he[e];
         memset(&b, 0, sizeof(b));
-        int rc = plan_window(s, f.frames, f.flows, f.t_us, f.K, h_delta, h_tbase,
-                             d_delta, &f.lay, &f.nbits, &b.sel, &b.ord, &b.chain);
+        rc = plan_window(s, f.frames, f.flows, f.t_us, f.K, h_delta, h_tbase, d_delta, &f.lay,
+                         &f.nbits, &b.sel, &b.ord, &b.chain);
         if (rc) return rc;
         b.sparse = s->cfg.method == SIM_SPARSE ? 1 : 0;
         b.vec = (b.sel.fstride % 4) == 0 && ((uintptr_t)b.sel.frames % 4) == 0 &&
@@ -841,17 +901,34 @@ int fused_window(std::vector<FusedItem>& items) {
         }
         b.npix = s->npix;
         b.counters = s->d_counters;
+        b.gathered = s->d_alt;
+        b.sort_alt = s->d_alt2;
+        b.hist = s->d_hist;
+        b.totals = s->d_totals;
+        b.out = s->d_fifo + s->fifo_tail;
+        b.cv.enabled = 1;
+        b.cv.n_sentinel = s->d_counters + 1;
         b.cv.tbase = d_tbase;
-        sel_blocks[e] = (int)((s->npix + kSelectPx - 1) / kSelectPx);
+        b.cv.K = f.K;
+        b.cv.lay = f.lay;
+        b.sort_blocks = (int)std::max<uint64_t>(1, (sort_cap[e] + kSortTile - 1) / kSortTile);
+        sort_blocks[e] = b.sort_blocks;
+        sel_blocks[e] = select_blocks(s->npix);
         order_blocks[e] = b.sparse ? select_blocks(s->npix) : 0;
+        gather_blocks[e] =
+            (int)(std::max<uint64_t>(1, (s->stripe_cap + kSortTile - 1) / kSortTile) *
+                  kArenaStripes);
         const int m = b.chain.mode;
         chain_blocks[m][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
         max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
+        passes = std::max(passes, (f.nbits + 7) / 8);
     }
     const int sel_total = fill_starts(hstart(kSel), sel_blocks);
     const int order_total = fill_starts(hstart(kOrder), order_blocks);
     int chain_total[3];
     for (int m = 0; m < 3; ++m) chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
+    const int gather_total = fill_starts(hstart(kGather), gather_blocks);
+    const int sort_total = fill_starts(hstart(kSort), sort_blocks);
     hipStream_t st = c.stream;
     const size_t head = ent_bytes + starts_bytes;
 #define BATCH_TRY(expr)                       \
@@ -861,110 +938,159 @@ int fused_window(std::vector<FusedItem>& items) {
             return SIM_E_HIP;                 \
         }                                     \
     } while (0)
-    BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, tab, hipMemcpyHostToDevice, st));
-    BATCH_TRY(launch_batch_prep(de, n, st));
-    BATCH_TRY(launch_batch_select(de, dstart(kSel), n, sel_total, st));
-    BATCH_TRY(launch_batch_order(de, dstart(kOrder), n, order_total, st));
-    for (FusedItem& f : items)
-        if (f.s->cfg.flow_source == SIM_FLOW_LK && f.s->S > 1)
-            BATCH_TRY(launch_lk(f.s, f.frames, f.K, st));
-    for (int m = 0; m < 3; ++m)
-        BATCH_TRY(launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m, max_stash[m],
-                                     st));
-    BATCH_TRY(launch_batch_fails(de, n, c.d_out, st));
-    BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, (size_t)n * sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, st));
+
+    // the chunk's whole device sequence (entries with fewer sort passes than `passes` take the
+    // extra ones harmlessly: their keys are zero, their sentinels all ones, in those digits)
+    auto enqueue = [&]() -> hipError_t {
+        hipError_t r = hipMemcpyAsync(c.d_blob, c.h_blob, tab, hipMemcpyHostToDevice, st);
+        if (r == hipSuccess) r = launch_batch_prep(de, n, st);
+        if (r == hipSuccess) r = launch_batch_select(de, dstart(kSel), n, sel_total, st);
+        if (r == hipSuccess) r = launch_batch_order(de, dstart(kOrder), n, order_total, st);
+        for (FusedItem& f : items)
+            if (r == hipSuccess && f.s->cfg.flow_source == SIM_FLOW_LK && f.s->S > 1)
+                r = launch_lk(f.s, f.frames, f.K, st);
+        for (int m = 0; m < 3 && r == hipSuccess; ++m)
+            r = launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m, max_stash[m],
+                                   st);
+        if (r == hipSuccess) r = launch_batch_gather(de, dstart(kGather), n, gather_total, st);
+        if (r == hipSuccess) r = launch_batch_sort(de, dstart(kSort), n, sort_total, passes, st);
+        if (r == hipSuccess) r = launch_batch_status(de, n, c.d_out, st);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(c.h_out, c.d_out, 3 * (size_t)n * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st);
+        return r;
+    };
+    if (capturable) {
+        BatchShape key;
+        key.n = n;
+        key.tab = tab;
+        key.totals = {sel_total, order_total, chain_total[0], chain_total[1], chain_total[2],
+                      gather_total, sort_total, passes, max_stash[0], max_stash[1],
+                      max_stash[2]};
+        key.blob = c.d_blob;
+        key.out = c.d_out;
+        if (!(c.graph_exec && c.graph_key == key)) {
+            if (c.graph_exec) {
+                (void)hipGraphExecDestroy(c.graph_exec);
+                c.graph_exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            BATCH_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const hipError_t er = enqueue();
+            const hipError_t ee = hipStreamEndCapture(st, &g);
+            if (er != hipSuccess || ee != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+                return SIM_E_HIP;
+            }
+            const hipError_t ei = hipGraphInstantiate(&c.graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                c.graph_exec = nullptr;
+                (void)hipGetLastError();
+                return SIM_E_HIP;
+            }
+            c.graph_key = key;
+            c.graph_captures++;
+        }
+        BATCH_TRY(hipGraphLaunch(c.graph_exec, st));
+        c.graph_launches++;
+    } else {
+        BATCH_TRY(enqueue());
+    }
     BATCH_TRY(hipStreamSynchronize(st));
 
-    // chains that ran out of event-buffer space: grow those buffers, re-run only them
-    for (;;) {
-        bool any = false;
-        for (int m = 0; m < 3; ++m) std::fill(chain_blocks[m].begin(), chain_blocks[m].end(), 0);
-        for (int e = 0; e < n; ++e) {
-            he[e].clamp_cap = 0;
-            if (c.h_out[e] == 0) continue;
-            any = true;
-            sim_stream* s = items[e].s;
-            const uint64_t old = s->stripe_cap;
-            int rc = grow_arena(s, 2 * old);
-            if (rc) return fail_mid_push(s, rc, "event arena growth");
-            s->stats.retries++;
-            he[e].clamp_cap = old;
-            he[e].chain.arena = s->d_arena;
-            he[e].chain.stripe_cap = s->stripe_cap;
-            chain_blocks[he[e].chain.mode][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
+    // entries that need the re-run path: chains out of arena space, or more events than the
+    // sort's grid covered
+    std::vector<int> redo;
+    for (int e = 0; e < n; ++e) {
+        he[e].clamp_cap = 0;
+        const unsigned long long fails = c.h_out[3 * e], gathered = c.h_out[3 * e + 2];
+        if (fails != 0 || gathered > sort_cap[e]) redo.push_back(e);
+    }
+    if (!redo.empty()) {
+        // chains that ran out of event-buffer space: grow those buffers, re-run only them
+        for (;;) {
+            bool any = false;
+            for (int m = 0; m < 3; ++m) std::fill(chain_blocks[m].begin(), chain_blocks[m].end(), 0);
+            for (int e : redo) {
+                he[e].clamp_cap = 0;
+                if (c.h_out[3 * e] == 0) continue;
+                any = true;
+                sim_stream* s = items[e].s;
+                const uint64_t old = s->stripe_cap;
+                int rc = grow_arena(s, 2 * old);
+                if (rc) return fail_mid_push(s, rc, "event arena growth");
+                s->stats.retries++;
+                he[e].clamp_cap = old;
+                he[e].chain.arena = s->d_arena;
+                he[e].chain.stripe_cap = s->stripe_cap;
+                chain_blocks[he[e].chain.mode][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
+            }
+            if (!any) break;
+            for (int m = 0; m < 3; ++m)
+                chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
+            BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
+            BATCH_TRY(launch_batch_clamp(de, n, st));
+            for (int m = 0; m < 3; ++m)
+                BATCH_TRY(launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m,
+                                             max_stash[m], st));
+            BATCH_TRY(launch_batch_status(de, n, c.d_out, st));
+            BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, 3 * (size_t)n * sizeof(unsigned long long),
+                                     hipMemcpyDeviceToHost, st));
+            BATCH_TRY(hipStreamSynchronize(st));
         }
-        if (!any) break;
-        for (int m = 0; m < 3; ++m)
-            chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
+        // every chain has finished: gather and sort the re-run entries again, grids from counts
+        std::fill(blocks.begin(), blocks.end(), 0);
+        for (int e : redo) {
+            sim_stream* s = items[e].s;
+            int rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
+            if (rc) return fail_mid_push(s, rc, "sort buffer growth");
+            he[e].clamp_cap = 0;
+            he[e].gathered = s->d_alt;
+            he[e].sort_alt = s->d_alt2;
+            blocks[e] = (int)(std::max<uint64_t>(1, (s->stripe_cap + kSortTile - 1) / kSortTile) *
+                              kArenaStripes);
+        }
+        const int gt = fill_starts(hstart(kGather), blocks);
         BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
-        BATCH_TRY(launch_batch_clamp(de, n, st));
-        for (int m = 0; m < 3; ++m)
-            BATCH_TRY(launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m,
-                                         max_stash[m], st));
-        BATCH_TRY(launch_batch_fails(de, n, c.d_out, st));
-        BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, (size_t)n * sizeof(unsigned long long),
+        BATCH_TRY(launch_batch_gather(de, dstart(kGather), n, gt, st));
+        BATCH_TRY(launch_batch_status(de, n, c.d_out, st));
+        BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, 3 * (size_t)n * sizeof(unsigned long long),
                                  hipMemcpyDeviceToHost, st));
         BATCH_TRY(hipStreamSynchronize(st));
+        std::fill(blocks.begin(), blocks.end(), 0);
+        int rpasses = 1;
+        for (int e : redo) {
+            FusedItem& f = items[e];
+            sim_stream* s = f.s;
+            const uint64_t n_total = c.h_out[3 * e + 2];
+            int rc = ensure_sort_scratch(s, n_total);
+            if (!rc && s->fifo_tail + n_total > s->fifo_cap)
+                rc = grow(s, &s->d_fifo, &s->fifo_cap,
+                          std::max<uint64_t>(s->fifo_tail + n_total, 2 * s->fifo_cap),
+                          s->fifo_tail);
+            if (rc) return fail_mid_push(s, rc, "event buffer growth");
+            BatchEntry& b = he[e];
+            b.hist = s->d_hist;
+            b.out = s->d_fifo + s->fifo_tail;
+            b.sort_blocks = (int)std::max<uint64_t>(1, (n_total + kSortTile - 1) / kSortTile);
+            blocks[e] = b.sort_blocks;
+            rpasses = std::max(rpasses, (f.nbits + 7) / 8);
+        }
+        const int rt = fill_starts(hstart(kSort), blocks);
+        BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
+        BATCH_TRY(launch_batch_sort(de, dstart(kSort), n, rt, rpasses, st));
+        BATCH_TRY(hipStreamSynchronize(st));
+        c.redo_windows += redo.size();
     }
-
-    // every chain has finished: concatenate each stream's sub-arenas
-    for (int e = 0; e < n; ++e) {
-        sim_stream* s = items[e].s;
-        int rc = ensure_alt(s, kArenaStripes * s->stripe_cap);
-        if (rc) return rc;
-        he[e].clamp_cap = 0;
-        he[e].gathered = s->d_alt;
-        he[e].sort_alt = s->d_alt2;
-        blocks[e] = (int)(std::max<uint64_t>(1, (s->stripe_cap + kSortTile - 1) / kSortTile) *
-                          kArenaStripes);
-    }
-    const int gather_total = fill_starts(hstart(kGather), blocks);
-    BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
-    BATCH_TRY(launch_batch_gather(de, dstart(kGather), n, gather_total, st));
-    BATCH_TRY(launch_batch_counts(de, n, c.d_out, st));
-    BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, 2 * (size_t)n * sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, st));
-    BATCH_TRY(hipStreamSynchronize(st));
-
-    // order: every stream's keys sorted into its FIFO
-    int passes = 0;
+#undef BATCH_TRY
     for (int e = 0; e < n; ++e) {
         FusedItem& f = items[e];
         sim_stream* s = f.s;
-        const uint64_t n_total = c.h_out[2 * e + 1];
-        f.n_valid = n_total - c.h_out[2 * e];
-        blocks[e] = 0;
-        if (f.n_valid == 0) continue;
-        int rc = ensure_sort_scratch(s, n_total);
-        if (!rc && s->fifo_tail + f.n_valid > s->fifo_cap)
-            rc = grow(s, &s->d_fifo, &s->fifo_cap,
-                      std::max<uint64_t>(s->fifo_tail + f.n_valid, 2 * s->fifo_cap),
-                      s->fifo_tail);
-        if (rc) return rc;
-        BatchEntry& b = he[e];
-        b.hist = s->d_hist;
-        b.totals = s->d_totals;
-        b.out = s->d_fifo + s->fifo_tail;
-        b.cv.enabled = 1;
-        b.cv.n_sentinel = s->d_counters + 1;
-        b.cv.K = f.K;
-        b.cv.lay = f.lay;
-        b.sort_blocks = (int)std::max<uint64_t>(1, (n_total + kSortTile - 1) / kSortTile);
-        blocks[e] = b.sort_blocks;
-        passes = std::max(passes, (f.nbits + 7) / 8);
-    }
-    const int sort_total = fill_starts(hstart(kSort), blocks);
-    if (sort_total > 0) {
-        // entries needing fewer passes get more: their keys are zero (sentinels all ones) in
-        // the extra digits, which a stable pass leaves in place
-        BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
-        BATCH_TRY(launch_batch_sort(de, dstart(kSort), n, sort_total, passes, st));
-        BATCH_TRY(hipStreamSynchronize(st));
-    }
-#undef BATCH_TRY
-    for (FusedItem& f : items) {
-        sim_stream* s = f.s;
+        const uint64_t n_total = c.h_out[3 * e + 2];
+        f.n_valid = n_total - c.h_out[3 * e + 1];
+        s->est_events = std::max<uint64_t>(s->est_events, n_total);
         s->fifo_tail += f.n_valid;
         s->cur = 1 - s->cur;
         s->t_prev = f.t_us[f.K - 1];
@@ -1303,6 +1429,15 @@ int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
     for (int i = 0; i < n; ++i)
         if (items[i].status && !first_err) first_err = items[i].status;
     return first_err;
+}
+
+int sim_batch_stats(uint64_t* graphs_recorded, uint64_t* graph_launches, uint64_t* rerun_windows) {
+    BatchCtx& c = batch_ctx();
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (graphs_recorded) *graphs_recorded = c.graph_captures;
+    if (graph_launches) *graph_launches = c.graph_launches;
+    if (rerun_windows) *rerun_windows = c.redo_windows;
+    return SIM_OK;
 }
 
 int sim_push_frame(sim_stream* s, const uint8_t* frame, const float* flow, int64_t t_us,

@@ -117,6 +117,7 @@ def load() -> ctypes.CDLL:
         "sim_clear_stats": (ctypes.c_int, [P]),
         "sim_last_error": (ctypes.c_char_p, [P]),
         "sim_push_batch": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(SimFrames), I32]),
+        "sim_batch_stats": (ctypes.c_int, [PU64, PU64, PU64]),
         "srv_footprint": (ctypes.c_int, [ctypes.POINTER(SimConfig), I32, PU64]),
         "srv_create": (ctypes.c_int, [U64, I32, I32, ctypes.POINTER(P)]),
         "srv_destroy": (ctypes.c_int, [P]),
@@ -213,6 +214,15 @@ def lk_params(levels: int = 3, radius: int = 7, iterations: int = 10, eps: float
     p.levels, p.radius, p.iterations = int(levels), int(radius), int(iterations)
     p.eps, p.min_trace, p.min_ratio = float(eps), float(min_trace), float(min_ratio)
     return p
+
+
+def batch_stats() -> dict:
+    """sim_batch_stats: graphs recorded, graph launches and re-run windows of batched pushes."""
+    lib = load()
+    g, l, r = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib.sim_batch_stats(ctypes.byref(g), ctypes.byref(l), ctypes.byref(r)),
+           "sim_batch_stats")
+    return {"graphs_recorded": g.value, "graph_launches": l.value, "rerun_windows": r.value}
 
 
 def lk_flow(f0, f1, points=None, hip_stream=None, **params):

@@ -350,7 +350,48 @@ hipError_t emu_hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) {
     if (n) memmove(dst, src, n);
     return hipSuccess;
 }
+// ---- stream capture
+struct emu_graph_t {
+    std::vector<std::function<void()>> ops;
+};
+static thread_local emu_graph_t* g_capture = nullptr;
+bool emu_capturing() { return g_capture != nullptr; }
+void emu_record(std::function<void()> op) { g_capture->ops.push_back(std::move(op)); }
+hipError_t emu_hipStreamBeginCapture(hipStream_t, int) {
+    if (g_capture) return hipErrorInvalidValue;
+    g_capture = new emu_graph_t();
+    return hipSuccess;
+}
+hipError_t emu_hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
+    if (!g_capture) return hipErrorInvalidValue;
+    *g = g_capture;
+    g_capture = nullptr;
+    return hipSuccess;
+}
+hipError_t emu_hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*,
+                                   size_t) {
+    *e = new emu_graph_t(*g);   // an executable graph is a copy of the recorded ops
+    return hipSuccess;
+}
+hipError_t emu_hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+    if (g_capture) return hipErrorInvalidValue;
+    for (auto& op : e->ops) op();
+    return hipSuccess;
+}
+hipError_t emu_hipGraphDestroy(hipGraph_t g) {
+    delete g;
+    return hipSuccess;
+}
+hipError_t emu_hipGraphExecDestroy(hipGraphExec_t e) {
+    delete e;
+    return hipSuccess;
+}
+
 hipError_t emu_hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind k, hipStream_t) {
+    if (g_capture) {
+        emu_record([=]() { (void)emu_hipMemcpy(dst, src, n, k); });
+        return hipSuccess;
+    }
     return emu_hipMemcpy(dst, src, n, k);
 }
 hipError_t emu_hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch,
@@ -368,7 +409,9 @@ hipError_t emu_hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
     *s = new emu_stream_t();
     return hipSuccess;
 }
-hipError_t emu_hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t emu_hipStreamSynchronize(hipStream_t) {
+    return g_capture ? hipErrorInvalidValue : hipSuccess;   // not allowed while capturing
+}
 hipError_t emu_hipStreamDestroy(hipStream_t s) {
     delete s;
     return hipSuccess;

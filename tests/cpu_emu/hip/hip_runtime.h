@@ -130,10 +130,23 @@ inline typename std::common_type<A, B>::type max(A a, B b) {
 void emu_run_grid(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body,
                   const char* name);
 
+// Stream capture (HIP graphs): while a capture is open, launches and asynchronous copies are
+// recorded, not run; a launched graph runs its records in order (a memcpy node reads its source
+// when it runs, as on the device).
+bool emu_capturing();
+void emu_record(std::function<void()> op);
+
 template <class... P, class... A>
 inline void emu_launch(const char* name, void (*k)(P...), dim3 grid, dim3 block, size_t shmem,
                        hipStream_t, A... args) {
     std::tuple<typename std::decay<P>::type...> params(args...);
+    if (emu_capturing()) {
+        emu_record([=]() {
+            auto p = params;
+            emu_run_grid(grid, block, shmem, [&]() { std::apply(k, p); }, name);
+        });
+        return;
+    }
     emu_run_grid(grid, block, shmem, [&]() { std::apply(k, params); }, name);
 }
 #define hipLaunchKernelGGL(k, grid, block, shmem, stream, ...) \
@@ -159,6 +172,12 @@ inline void emu_launch(const char* name, void (*k)(P...), dim3 grid, dim3 block,
 #define hipGetLastError emu_hipGetLastError
 #define hipGetErrorString emu_hipGetErrorString
 #define hipGetDevice emu_hipGetDevice
+#define hipStreamBeginCapture emu_hipStreamBeginCapture
+#define hipStreamEndCapture emu_hipStreamEndCapture
+#define hipGraphInstantiate emu_hipGraphInstantiate
+#define hipGraphLaunch emu_hipGraphLaunch
+#define hipGraphDestroy emu_hipGraphDestroy
+#define hipGraphExecDestroy emu_hipGraphExecDestroy
 #define hipGetSymbolAddress emu_hipGetSymbolAddress
 #define HIP_SYMBOL(x) ((const void*)&(x))
 
@@ -183,5 +202,18 @@ hipError_t emu_hipEventDestroy(hipEvent_t e);
 hipError_t emu_hipGetLastError();
 const char* emu_hipGetErrorString(hipError_t e);
 hipError_t emu_hipGetDevice(int* dev);
+typedef struct emu_graph_t* hipGraph_t;
+typedef struct emu_graph_t* hipGraphExec_t;
+typedef struct emu_graph_node_t* hipGraphNode_t;
+enum { hipStreamCaptureModeGlobal = 0, hipStreamCaptureModeThreadLocal = 1,
+       hipStreamCaptureModeRelaxed = 2 };
+typedef int hipStreamCaptureMode;
+hipError_t emu_hipStreamBeginCapture(hipStream_t s, int mode);
+hipError_t emu_hipStreamEndCapture(hipStream_t s, hipGraph_t* g);
+hipError_t emu_hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t* err,
+                                   char* log, size_t log_size);
+hipError_t emu_hipGraphLaunch(hipGraphExec_t e, hipStream_t s);
+hipError_t emu_hipGraphDestroy(hipGraph_t g);
+hipError_t emu_hipGraphExecDestroy(hipGraphExec_t e);
 // a __device__ variable is host memory here: its "device address" is its own address
 hipError_t emu_hipGetSymbolAddress(void** p, const void* symbol);

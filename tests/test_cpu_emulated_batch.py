@@ -93,6 +93,35 @@ def test_emulated_fused_batch_uneven_windows(emu_sim):
         s.close()
 
 
+def test_emulated_batch_steps_replay_one_recorded_graph(emu_sim):
+    """Frame by frame, five streams without estimated flow (every other method and mode), one
+    batch per frame step: the first step records the step's sequence as a graph, the later steps
+    of the same shape replay it (the emulation records and replays kernels and copies like
+    stream capture), and every stream equals the oracle; one stream overflows its tiny arena, so
+    its windows take the re-run path after the replay."""
+    mix = [m for m in MIX if m[1].get("flow_source") != "lk"]
+    vids = [synth.blob_video(synth.BlobVideoSpec(W, H, 6, 30.0, 5, seed=90 + i,
+                                                 motion="random", speed_max=5.0))
+            for i, ((W, H), _, _) in enumerate(mix)]
+    streams = [emu_sim.Stream(W, H, **opts) for (W, H), opts, _ in mix]
+    before = emu_sim.batch_stats()
+    emu_sim.push_batch([(st, v.frames[0:1], None, v.t_us[0:1]) for st, v in zip(streams, vids)])
+    for k in range(1, 6):
+        emu_sim.push_batch([(st, v.frames[k:k + 1], _flows_for(opts, v, k, k + 1),
+                             v.t_us[k:k + 1]) for st, v, (_, opts, _) in zip(streams, vids, mix)])
+    after = emu_sim.batch_stats()
+    launches = after["graph_launches"] - before["graph_launches"]
+    recorded = after["graphs_recorded"] - before["graphs_recorded"]
+    assert launches == 5 and 1 <= recorded < launches     # later steps replay a recorded graph
+    assert after["rerun_windows"] > before["rerun_windows"]
+    for st, v, (_, opts, ocfg) in zip(streams, vids, mix):
+        ok, oref = oracle_run(v.frames, v.flows if opts["method"] != "basic" else None, v.t_us,
+                              **ocfg)
+        np.testing.assert_array_equal(st.drain_keys(), ok, err_msg=str(opts))
+        np.testing.assert_array_equal(st.reference().view(np.uint32), oref.view(np.uint32))
+        st.close()
+
+
 ASAN_SCRIPT = textwrap.dedent("""
     import sys, numpy as np
     sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})

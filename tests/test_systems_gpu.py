@@ -113,6 +113,7 @@ def test_c4_batched_64_streams_full_size():
         cfgs.append(dict(W=W, H=H, method=method, c=c))
     streams = [sim.Stream(d["W"], d["H"], method=d["method"], c_pos=d["c"], c_neg=d["c"])
                for d in cfgs]
+    before = sim.batch_stats()
     for k in range(30):
         entries = []
         for st, d in zip(streams, cfgs):
@@ -120,6 +121,10 @@ def test_c4_batched_64_streams_full_size():
             flow = None if (d["method"] == sim.BASIC or k == 0) else fl[k - 1:k]
             entries.append((st, fr[k:k + 1], flow, v.t_us[k:k + 1]))
         sim.push_batch(entries)
+    after = sim.batch_stats()
+    launches = after["graph_launches"] - before["graph_launches"]
+    recorded = after["graphs_recorded"] - before["graphs_recorded"]
+    assert launches == 29 and recorded < launches, (launches, recorded)   # steps replay graphs
     batched = [st.drain_keys() for st in streams]
     for st in streams:
         st.close()
