@@ -261,6 +261,7 @@ def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
     elapsed = time.perf_counter() - t0
     per_step = np.diff(np.array([t0] + marks)) * 1e3
     st = s.stats()
+    chain_variant = s.chain_variant()
     selected = st["selected"]
     sim_ms, sim_launches = st["simulate_ms"], st["simulate_launches"]
     sel_ms = st["select_ms"]
@@ -311,6 +312,7 @@ def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
         "select_ms_per_step": round(sel_ms / steps, 4),
         "simulate_ms_per_step": round(sim_ms / steps, 4),
         "sort_ms_per_step": round(sort_ms / steps, 4),
+        "chain_variant": chain_variant,
         "plain_one_frame_pushes": plain_res,
         "roofline": roofline,
         "_video": video, "_spec": spec, "_wl": wl, "_shape": (T, H, W),
@@ -478,7 +480,7 @@ def main():
                    "seed": spec.seed, "mode": "window push (one launch per sequence)"},
     }
     for k in ("events_per_s", "events_per_step", "selected_fraction", "active_pixels_per_step",
-              "select_ms_per_step", "simulate_ms_per_step", "sort_ms_per_step",
+              "select_ms_per_step", "simulate_ms_per_step", "sort_ms_per_step", "chain_variant",
               "plain_one_frame_pushes", "roofline"):
         line[k] = m[k]
     line["cpu_baseline"] = cpu

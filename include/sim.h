@@ -217,6 +217,19 @@ typedef struct sim_frames {
  * returns SIM_OK or the first error.  One batched push runs at a time per process. */
 int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n);
 
+/* Chain-pass variant: how many interior samples' texel loads a lane keeps in flight (0: 2, 1: 5,
+ * 2: 10 for the frame methods; 1, 2 and 4 for difference frames).  Every variant computes the
+ * same events bit for bit; they differ in speed.  -1 (the default) lets the library's autotuner
+ * choose: on the first window of each (device architecture, width, height, method, thresholding
+ * mode, S) it times every variant on that window against scratch copies of the state the pass
+ * writes and keeps the fastest for the process (streams with estimated flow, and S = 1, use
+ * variant 2).  A batched push runs each thresholding mode's streams with the variant of its
+ * stream with the most pixels.  sim_get_chain_variant reports the variant the stream's last
+ * window used (-1 before its first window).
+ * Errors: SIM_E_INVAL (NULL, variant outside -1..2). */
+int sim_set_chain_variant(sim_stream* s, int32_t variant);
+int sim_get_chain_variant(sim_stream* s, int32_t* variant);
+
 /* Process-wide counts of the batched pushes since the library was loaded: graphs recorded,
  * graph launches, and stream windows finished by re-runs (sim_push_batch).  Any pointer may be
  * NULL.  Errors: none (returns SIM_OK). */

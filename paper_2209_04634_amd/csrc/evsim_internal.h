@@ -130,7 +130,11 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t stream);
 hipError_t launch_order(const OrderArgs& a, hipStream_t stream);
 // Blocks of the selection (and of the order copy) for npix pixels.
 inline int select_blocks(int64_t npix) { return (int)((npix + kSelectPx - 1) / kSelectPx); }
-hipError_t launch_chain(const ChainArgs& a, int max_slots, hipStream_t stream);
+// Chain-pass variants (interior samples in flight per lane: 2 / 5 / 10 for the frame methods,
+// 1 / 2 / 4 for difference frames); identical results.
+constexpr int kChainVariants = 3;
+constexpr int kDefaultChainVariant = 2;
+hipError_t launch_chain(const ChainArgs& a, int max_slots, int variant, hipStream_t stream);
 // Concatenates the used part of every sub-arena into `out`; writes the total to *n_total.
 hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
                          const unsigned long long* reserve, uint64_t* out,
@@ -199,7 +203,7 @@ hipError_t launch_batch_select(const BatchEntry* e, const int* start, int n, int
 hipError_t launch_batch_order(const BatchEntry* e, const int* start, int n, int blocks,
                               hipStream_t stream);
 hipError_t launch_batch_chain(const BatchEntry* e, const int* start, int n, int blocks, int mode,
-                              int max_stash, hipStream_t stream);
+                              int max_stash, int variant, hipStream_t stream);
 // out[e] = failed reservations of entry e (counters[0]).
 hipError_t launch_batch_fails(const BatchEntry* e, int n, unsigned long long* out,
                               hipStream_t stream);

@@ -233,15 +233,15 @@ __device__ __forceinline__ void stash_diff_samples(const uint8_t* Fm, const uint
     }
 }
 
-// Samples in flight per lane in the chain pass (frame methods / difference method).
-#ifndef EVSIM_FRAME_BATCH
-#define EVSIM_FRAME_BATCH 10
-#endif
-#ifndef EVSIM_DIFF_BATCH
-#define EVSIM_DIFF_BATCH 2
-#endif
-constexpr int kFrameBatch = EVSIM_FRAME_BATCH;
-constexpr int kDiffBatch = EVSIM_DIFF_BATCH;
+// Chain-pass variants: interior samples whose texel loads a lane keeps in flight at once (frame
+// methods / difference method).  More samples in flight hide more memory latency per wave but
+// take registers and so waves per SIMD; which is faster depends on the image, the method and the
+// selected fraction, so the runtime times the variants on the device (autotuner).  Every variant
+// performs the same arithmetic in the same order.
+template <int V> struct ChainVariant;
+template <> struct ChainVariant<0> { static constexpr int frame = 2, diff = 1; };
+template <> struct ChainVariant<1> { static constexpr int frame = 5, diff = 2; };
+template <> struct ChainVariant<2> { static constexpr int frame = 10, diff = 4; };
 
 struct PixelCtx {
     const uint8_t* F0;
@@ -646,8 +646,8 @@ __device__ __forceinline__ void order_scan_block(const OrderArgs& a) {
         uint32_t total = 0u;
         for (int c2 = 0; c2 < kClasses; ++c2) total += s_tot[c2];
         *a.n_total = total;
-        if (s_sel[0] > 0) atomicAdd(a.stats, (unsigned long long)s_sel[0]);
-        if (total > 0) atomicAdd(a.stats + 1, (unsigned long long)total);
+        if (a.stats && s_sel[0] > 0) atomicAdd(a.stats, (unsigned long long)s_sel[0]);
+        if (a.stats && total > 0) atomicAdd(a.stats + 1, (unsigned long long)total);
     }
 }
 
@@ -698,8 +698,10 @@ __global__ __launch_bounds__(256) void k_select(SelectArgs a) {
 // or the paper's memoryless thresholding of sample differences or of interpolated difference
 // frames (no reference level, which is then neither read nor written).
 // ------------------------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int V>
 __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
+    constexpr int kFrameBatch = ChainVariant<V>::frame;
+    constexpr int kDiffBatch = ChainVariant<V>::diff;
     extern __shared__ float smem[];
     __shared__ float tau[kMaxSubIntervals + 1];   // k / S for k = 0..S, shared by every sample
     float* lut = smem;
@@ -842,9 +844,9 @@ __device__ __forceinline__ void chain_block(ChainArgs a, unsigned bid) {
     }
 }
 
-template <int MODE>
+template <int MODE, int V>
 __global__ __launch_bounds__(kSimThreads) void k_chain(ChainArgs a) {
-    chain_block<MODE>(a, blockIdx.x);
+    chain_block<MODE, V>(a, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_copy_u8(const uint8_t* __restrict__ src,
@@ -1173,28 +1175,38 @@ hipError_t launch_order(const OrderArgs& a, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const ChainArgs& a, int max_slots, hipStream_t stream) {
+template <int MODE, int V>
+hipError_t launch_chain_v(const ChainArgs& a, int blocks, size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((k_chain<MODE, V>), dim3(blocks), dim3(kSimThreads), shmem, stream, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_chain_m(const ChainArgs& a, int blocks, size_t shmem, int variant,
+                          hipStream_t stream) {
+    switch (variant) {
+        case 0: return launch_chain_v<MODE, 0>(a, blocks, shmem, stream);
+        case 1: return launch_chain_v<MODE, 1>(a, blocks, shmem, stream);
+        case 2: return launch_chain_v<MODE, 2>(a, blocks, shmem, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_chain(const ChainArgs& a, int max_slots, int variant, hipStream_t stream) {
     const int stash_n = (a.S - 1 <= kMaxStash) ? (a.S - 1) : 0;
     const size_t shmem = (size_t)(256 + stash_n * kSimThreads) * sizeof(float);
     const int blocks = (max_slots + kSimThreads - 1) / kSimThreads;
     if (blocks == 0) return hipSuccess;
     switch (a.mode) {
         case kModeReference:
-            hipLaunchKernelGGL(k_chain<kModeReference>, dim3(blocks), dim3(kSimThreads), shmem,
-                               stream, a);
-            break;
+            return launch_chain_m<kModeReference>(a, blocks, shmem, variant, stream);
         case kModeMemoryless:
-            hipLaunchKernelGGL(k_chain<kModeMemoryless>, dim3(blocks), dim3(kSimThreads), shmem,
-                               stream, a);
-            break;
+            return launch_chain_m<kModeMemoryless>(a, blocks, shmem, variant, stream);
         case kModeDifference:
-            hipLaunchKernelGGL(k_chain<kModeDifference>, dim3(blocks), dim3(kSimThreads), shmem,
-                               stream, a);
-            break;
+            return launch_chain_m<kModeDifference>(a, blocks, shmem, variant, stream);
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_gather(const uint64_t* arena, uint64_t stripe_cap,
@@ -1352,12 +1364,12 @@ __global__ __launch_bounds__(256) void k_batch_order_copy(const BatchEntry* __re
     order_copy_block(entries[ei].ord, blockIdx.x - (unsigned)start[ei]);
 }
 
-template <int MODE>
+template <int MODE, int V>
 __global__ __launch_bounds__(kSimThreads) void k_batch_chain(const BatchEntry* __restrict__ entries,
                                                              const int* __restrict__ start,
                                                              int n) {
     const int ei = batch_entry(start, n, blockIdx.x);
-    chain_block<MODE>(entries[ei].chain, blockIdx.x - (unsigned)start[ei]);
+    chain_block<MODE, V>(entries[ei].chain, blockIdx.x - (unsigned)start[ei]);
 }
 
 __global__ void k_batch_fails(const BatchEntry* __restrict__ entries, int n,
@@ -1455,27 +1467,42 @@ hipError_t launch_batch_order(const BatchEntry* e, const int* start, int n, int 
     return hipGetLastError();
 }
 
+template <int MODE, int V>
+hipError_t launch_batch_chain_v(const BatchEntry* e, const int* start, int n, int blocks,
+                                size_t shmem, hipStream_t stream) {
+    hipLaunchKernelGGL((k_batch_chain<MODE, V>), dim3(blocks), dim3(kSimThreads), shmem, stream,
+                       e, start, n);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_batch_chain_m(const BatchEntry* e, const int* start, int n, int blocks,
+                                size_t shmem, int variant, hipStream_t stream) {
+    switch (variant) {
+        case 0: return launch_batch_chain_v<MODE, 0>(e, start, n, blocks, shmem, stream);
+        case 1: return launch_batch_chain_v<MODE, 1>(e, start, n, blocks, shmem, stream);
+        case 2: return launch_batch_chain_v<MODE, 2>(e, start, n, blocks, shmem, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_batch_chain(const BatchEntry* e, const int* start, int n, int blocks, int mode,
-                              int max_stash, hipStream_t stream) {
+                              int max_stash, int variant, hipStream_t stream) {
     if (n <= 0 || blocks <= 0) return hipSuccess;
     const size_t shmem = (size_t)(256 + max_stash * kSimThreads) * sizeof(float);
     switch (mode) {
         case kModeReference:
-            hipLaunchKernelGGL(k_batch_chain<kModeReference>, dim3(blocks), dim3(kSimThreads),
-                               shmem, stream, e, start, n);
-            break;
+            return launch_batch_chain_m<kModeReference>(e, start, n, blocks, shmem, variant,
+                                                        stream);
         case kModeMemoryless:
-            hipLaunchKernelGGL(k_batch_chain<kModeMemoryless>, dim3(blocks), dim3(kSimThreads),
-                               shmem, stream, e, start, n);
-            break;
+            return launch_batch_chain_m<kModeMemoryless>(e, start, n, blocks, shmem, variant,
+                                                         stream);
         case kModeDifference:
-            hipLaunchKernelGGL(k_batch_chain<kModeDifference>, dim3(blocks), dim3(kSimThreads),
-                               shmem, stream, e, start, n);
-            break;
+            return launch_batch_chain_m<kModeDifference>(e, start, n, blocks, shmem, variant,
+                                                         stream);
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_batch_fails(const BatchEntry* e, int n, unsigned long long* out,

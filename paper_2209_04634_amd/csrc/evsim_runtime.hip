@@ -17,8 +17,11 @@
 
 #include <algorithm>
 #include <array>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sim.h"
@@ -133,7 +136,11 @@ struct sim_stream {
         KeyLayout lay;
         ChainArgs a;
         int64_t t_last = 0;
+        int variant = kDefaultChainVariant;
     } job;
+
+    int forced_variant = -1;                     // sim_set_chain_variant; -1: autotuned
+    int last_variant = -1;                       // variant of the last window's chain pass
 
     // kernel timing (sim_set_kernel_timing)
     bool timing = false;
@@ -441,6 +448,130 @@ hipError_t launch_lk(sim_stream* s, const uint8_t* frames, int K, hipStream_t st
     return launch_lk_window(la, chain_slots(s), stream);
 }
 
+// ------------------------------------------------------------------------------------------
+// Chain-pass autotuner.  The variants differ only in how many interior samples' loads a lane
+// keeps in flight (registers against waves per SIMD); the fastest depends on the image size, the
+// method and mode, S and the selected fraction.  On the first window of each (device
+// architecture, W, H, method, mode, S), every variant runs on that window against scratch copies
+// of what the pass writes -- reference levels, resume points, event arena and counters -- so the
+// stream itself is untouched, timed with HIP events (a warm-up round, then the best of three
+// rounds, variants interleaved); the fastest is kept for the process.  All variants give
+// identical results.
+// ------------------------------------------------------------------------------------------
+struct TuneKey {
+    std::string arch;
+    int W, H, method, mode, S;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, W, H, method, mode, S) <
+               std::tie(o.arch, o.W, o.H, o.method, o.mode, o.S);
+    }
+};
+
+struct Tuner {
+    std::mutex mu;
+    std::map<TuneKey, int> best;
+    std::map<int, std::string> arch;   // per device
+};
+
+Tuner& tuner() {
+    static Tuner* t = new Tuner();   // lives until the process ends
+    return *t;
+}
+
+std::string device_arch(Tuner& t) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "?";
+    }
+    auto it = t.arch.find(dev);
+    if (it != t.arch.end()) return it->second;
+    hipDeviceProp_t p;
+    std::string name = "?";
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess)
+        name = p.gcnArchName;
+    else
+        (void)hipGetLastError();
+    t.arch[dev] = name;
+    return name;
+}
+
+// Times every variant of the chain pass `a` (max_slots slots) on `st`; returns the fastest, or
+// the default variant if anything fails.  Waits on `st`.
+int tune_chain(sim_stream* s, const ChainArgs& a, int max_slots, hipStream_t st) {
+    const size_t arena_n = (size_t)kArenaStripes * a.stripe_cap;
+    ChainArgs t = a;
+    float* lref = nullptr;
+    int* resume = nullptr;
+    uint64_t* arena = nullptr;
+    unsigned long long* reserve = nullptr;
+    unsigned long long* fails = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = (a.mode != kModeReference || dev_alloc(&lref, (size_t)s->npix) == hipSuccess) &&
+              dev_alloc(&resume, (size_t)max_slots) == hipSuccess &&
+              dev_alloc(&arena, arena_n) == hipSuccess &&
+              dev_alloc(&reserve, (size_t)kArenaStripes * kCounterStride) == hipSuccess &&
+              dev_alloc(&fails, 4) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+              hipEventCreate(&e1) == hipSuccess;
+    float ms[kChainVariants];
+    for (int v = 0; v < kChainVariants; ++v) ms[v] = 1e30f;
+    if (ok) {
+        if (lref) t.lref = lref;
+        t.resume = resume;
+        t.arena = arena;
+        t.reserve = reserve;
+        t.fails = fails;
+        for (int rep = 0; rep < 4 && ok; ++rep) {   // a warm-up round, then the best of three
+            for (int v = 0; v < kChainVariants && ok; ++v) {
+                // the state the real pass starts from: levels as they are, every chain at its
+                // first interval, empty arena counters
+                ok = (!lref || hipMemcpyAsync(lref, a.lref, (size_t)s->npix * sizeof(float),
+                                              hipMemcpyDeviceToDevice, st) == hipSuccess) &&
+                     launch_zero(resume, (size_t)max_slots * sizeof(int), st) == hipSuccess &&
+                     launch_zero(reserve, (size_t)kArenaStripes * kCounterStride *
+                                              sizeof(unsigned long long), st) == hipSuccess &&
+                     launch_zero(fails, 4 * sizeof(unsigned long long), st) == hipSuccess &&
+                     hipEventRecord(e0, st) == hipSuccess &&
+                     launch_chain(t, max_slots, v, st) == hipSuccess &&
+                     hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                float m = 0.0f;
+                if (ok && rep > 0 && hipEventElapsedTime(&m, e0, e1) == hipSuccess)
+                    ms[v] = std::min(ms[v], m);
+            }
+        }
+    }
+    if (!ok) (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dfree(lref);
+    dfree(resume);
+    dfree(arena);
+    dfree(reserve);
+    dfree(fails);
+    int best = kDefaultChainVariant;
+    if (ok)
+        for (int v = 0; v < kChainVariants; ++v)
+            if (ms[v] < ms[best]) best = v;
+    return best;
+}
+
+// The variant for the window `a` of stream s: forced, cached for its key, or tuned now (the
+// window's selection and order pass must be queued on `st` already).
+int chain_variant_for(sim_stream* s, const ChainArgs& a, int max_slots, hipStream_t st) {
+    if (s->forced_variant >= 0) return s->forced_variant;
+    if (s->S <= 1) return kDefaultChainVariant;   // no interior samples: variants coincide
+    if (s->cfg.flow_source == SIM_FLOW_LK) return kDefaultChainVariant;
+    Tuner& tu = tuner();
+    std::lock_guard<std::mutex> lock(tu.mu);
+    TuneKey k{device_arch(tu), s->cfg.width, s->cfg.height, s->cfg.method, a.mode, s->S};
+    auto it = tu.best.find(k);
+    if (it != tu.best.end()) return it->second;
+    const int v = tune_chain(s, a, max_slots, st);
+    tu.best[k] = v;
+    return v;
+}
+
 int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const int64_t* t_us,
                int K) {
     const bool estimate = s->cfg.flow_source == SIM_FLOW_LK && s->S > 1;
@@ -487,7 +618,9 @@ int win_launch(sim_stream* s, const uint8_t* frames, const float* flows, const i
     s->job.max_slots = max_slots;
     s->job.lay = lay;
     s->job.t_last = t_us[K - 1];
-    HIP_TRY(s, launch_chain(a, max_slots, s->stream));
+    s->job.variant = chain_variant_for(s, a, max_slots, s->stream);
+    s->last_variant = s->job.variant;
+    HIP_TRY(s, launch_chain(a, max_slots, s->job.variant, s->stream));
     if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s->stream));
@@ -526,7 +659,7 @@ int win_check(sim_stream* s) {
         a.arena = s->d_arena;
         a.stripe_cap = s->stripe_cap;
         if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[1], s->stream));
-        HIP_TRY(s, launch_chain(a, s->job.max_slots, s->stream));
+        HIP_TRY(s, launch_chain(a, s->job.max_slots, s->job.variant, s->stream));
         if (s->timing) HIP_TRY(s, hipEventRecord(s->ev[2], s->stream));
         HIP_TRY(s, hipMemcpyAsync(s->h_counters, s->d_counters, 2 * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, s->stream));
@@ -713,7 +846,7 @@ int run_window(sim_stream* s, const uint8_t* frames, const float* flows, const i
 struct BatchShape {
     int n = 0;
     size_t tab = 0;
-    std::array<int, 11> totals{};
+    std::array<int, 14> totals{};
     const void* blob = nullptr;
     const void* out = nullptr;
     bool operator==(const BatchShape& o) const {
@@ -844,6 +977,13 @@ int fused_window(std::vector<FusedItem>& items) {
     auto dstart = [&](int k) { return ds + (size_t)k * (n + 1); };
     enum { kSel = 0, kChain0 = 1, kGather = 4, kSort = 5, kOrder = 6 };
 
+#define BATCH_TRY(expr)                       \
+    do {                                      \
+        if ((expr) != hipSuccess) {           \
+            (void)hipGetLastError();          \
+            return SIM_E_HIP;                 \
+        }                                     \
+    } while (0)
     // every stream's staged inputs and earlier work are complete before the batch stream reads
     for (FusedItem& f : items)
         if (hipStreamSynchronize(f.s->stream) != hipSuccess) return SIM_E_HIP;
@@ -923,6 +1063,36 @@ int fused_window(std::vector<FusedItem>& items) {
         max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
         passes = std::max(passes, (f.nbits + 7) / 8);
     }
+    // chain-pass variant per thresholding mode: that of the entry with the most chain slots
+    // (tuned now if its key is new: its selection and order pass run alone first)
+    int variant[3] = {kDefaultChainVariant, kDefaultChainVariant, kDefaultChainVariant};
+    {
+        int lead[3] = {-1, -1, -1};
+        for (int e = 0; e < n; ++e) {
+            const int m = he[e].chain.mode;
+            if (lead[m] < 0 || chain_slots(items[lead[m]].s) < chain_slots(items[e].s))
+                lead[m] = e;
+        }
+        bool uploaded = false;
+        for (int m = 0; m < 3; ++m) {
+            if (lead[m] < 0) continue;
+            FusedItem& f = items[lead[m]];
+            BatchEntry& b = he[lead[m]];
+            if (!uploaded) {   // the per-interval tables the chain pass reads
+                BATCH_TRY(
+                    hipMemcpyAsync(c.d_blob, c.h_blob, tab, hipMemcpyHostToDevice, c.stream));
+                uploaded = true;
+            }
+            if (b.sparse) {
+                OrderArgs oa = b.ord;
+                oa.stats = nullptr;   // the chunk's own order pass counts the statistics
+                BATCH_TRY(launch_select(b.sel, c.stream));
+                BATCH_TRY(launch_order(oa, c.stream));
+            }
+            variant[m] = chain_variant_for(f.s, b.chain, chain_slots(f.s), c.stream);
+            f.s->last_variant = variant[m];
+        }
+    }
     const int sel_total = fill_starts(hstart(kSel), sel_blocks);
     const int order_total = fill_starts(hstart(kOrder), order_blocks);
     int chain_total[3];
@@ -931,13 +1101,6 @@ int fused_window(std::vector<FusedItem>& items) {
     const int sort_total = fill_starts(hstart(kSort), sort_blocks);
     hipStream_t st = c.stream;
     const size_t head = ent_bytes + starts_bytes;
-#define BATCH_TRY(expr)                       \
-    do {                                      \
-        if ((expr) != hipSuccess) {           \
-            (void)hipGetLastError();          \
-            return SIM_E_HIP;                 \
-        }                                     \
-    } while (0)
 
     // the chunk's whole device sequence (entries with fewer sort passes than `passes` take the
     // extra ones harmlessly: their keys are zero, their sentinels all ones, in those digits)
@@ -951,7 +1114,7 @@ int fused_window(std::vector<FusedItem>& items) {
                 r = launch_lk(f.s, f.frames, f.K, st);
         for (int m = 0; m < 3 && r == hipSuccess; ++m)
             r = launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m, max_stash[m],
-                                   st);
+                                   variant[m], st);
         if (r == hipSuccess) r = launch_batch_gather(de, dstart(kGather), n, gather_total, st);
         if (r == hipSuccess) r = launch_batch_sort(de, dstart(kSort), n, sort_total, passes, st);
         if (r == hipSuccess) r = launch_batch_status(de, n, c.d_out, st);
@@ -966,7 +1129,7 @@ int fused_window(std::vector<FusedItem>& items) {
         key.tab = tab;
         key.totals = {sel_total, order_total, chain_total[0], chain_total[1], chain_total[2],
                       gather_total, sort_total, passes, max_stash[0], max_stash[1],
-                      max_stash[2]};
+                      max_stash[2], variant[0], variant[1], variant[2]};
         key.blob = c.d_blob;
         key.out = c.d_out;
         if (!(c.graph_exec && c.graph_key == key)) {
@@ -1034,7 +1197,7 @@ int fused_window(std::vector<FusedItem>& items) {
             BATCH_TRY(launch_batch_clamp(de, n, st));
             for (int m = 0; m < 3; ++m)
                 BATCH_TRY(launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m,
-                                             max_stash[m], st));
+                                             max_stash[m], variant[m], st));
             BATCH_TRY(launch_batch_status(de, n, c.d_out, st));
             BATCH_TRY(hipMemcpyAsync(c.h_out, c.d_out, 3 * (size_t)n * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost, st));
@@ -1429,6 +1592,18 @@ int sim_push_batch(sim_stream** streams, sim_frames* items, int32_t n) {
     for (int i = 0; i < n; ++i)
         if (items[i].status && !first_err) first_err = items[i].status;
     return first_err;
+}
+
+int sim_set_chain_variant(sim_stream* s, int32_t variant) {
+    if (!s || variant < -1 || variant >= kChainVariants) return SIM_E_INVAL;
+    s->forced_variant = variant;
+    return SIM_OK;
+}
+
+int sim_get_chain_variant(sim_stream* s, int32_t* variant) {
+    if (!s || !variant) return SIM_E_INVAL;
+    *variant = s->last_variant;
+    return SIM_OK;
 }
 
 int sim_batch_stats(uint64_t* graphs_recorded, uint64_t* graph_launches, uint64_t* rerun_windows) {

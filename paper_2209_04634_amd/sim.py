@@ -118,6 +118,8 @@ def load() -> ctypes.CDLL:
         "sim_last_error": (ctypes.c_char_p, [P]),
         "sim_push_batch": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(SimFrames), I32]),
         "sim_batch_stats": (ctypes.c_int, [PU64, PU64, PU64]),
+        "sim_set_chain_variant": (ctypes.c_int, [P, I32]),
+        "sim_get_chain_variant": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
         "srv_footprint": (ctypes.c_int, [ctypes.POINTER(SimConfig), I32, PU64]),
         "srv_create": (ctypes.c_int, [U64, I32, I32, ctypes.POINTER(P)]),
         "srv_destroy": (ctypes.c_int, [P]),
@@ -481,6 +483,18 @@ class Stream:
 
     def sync(self) -> None:
         _check(self._lib.sim_sync(self._h), "sim_sync", self._h)
+
+    def set_chain_variant(self, variant: int = -1) -> None:
+        """sim_set_chain_variant: -1 = autotuned, 0..2 = a fixed chain-pass variant."""
+        _check(self._lib.sim_set_chain_variant(self._h, int(variant)), "sim_set_chain_variant",
+               self._h)
+
+    def chain_variant(self) -> int:
+        """sim_get_chain_variant: the variant the last window's chain pass used (-1: none)."""
+        v = ctypes.c_int32()
+        _check(self._lib.sim_get_chain_variant(self._h, ctypes.byref(v)),
+               "sim_get_chain_variant", self._h)
+        return v.value
 
     def reset(self) -> None:
         _check(self._lib.sim_reset(self._h), "sim_reset", self._h)

@@ -442,6 +442,10 @@ hipError_t emu_hipGetDevice(int* dev) {
     *dev = 0;
     return hipSuccess;
 }
+hipError_t emu_hipGetDeviceProperties(hipDeviceProp_t* p, int) {
+    snprintf(p->gcnArchName, sizeof(p->gcnArchName), "cpu-emulation");
+    return hipSuccess;
+}
 hipError_t emu_hipGetSymbolAddress(void** p, const void* symbol) {
     *p = const_cast<void*>(symbol);
     return hipSuccess;

@@ -172,6 +172,7 @@ inline void emu_launch(const char* name, void (*k)(P...), dim3 grid, dim3 block,
 #define hipGetLastError emu_hipGetLastError
 #define hipGetErrorString emu_hipGetErrorString
 #define hipGetDevice emu_hipGetDevice
+#define hipGetDeviceProperties emu_hipGetDeviceProperties
 #define hipStreamBeginCapture emu_hipStreamBeginCapture
 #define hipStreamEndCapture emu_hipStreamEndCapture
 #define hipGraphInstantiate emu_hipGraphInstantiate
@@ -202,6 +203,10 @@ hipError_t emu_hipEventDestroy(hipEvent_t e);
 hipError_t emu_hipGetLastError();
 const char* emu_hipGetErrorString(hipError_t e);
 hipError_t emu_hipGetDevice(int* dev);
+struct hipDeviceProp_t {
+    char gcnArchName[256];
+};
+hipError_t emu_hipGetDeviceProperties(hipDeviceProp_t* p, int dev);
 typedef struct emu_graph_t* hipGraph_t;
 typedef struct emu_graph_t* hipGraphExec_t;
 typedef struct emu_graph_node_t* hipGraphNode_t;

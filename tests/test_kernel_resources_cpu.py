@@ -15,12 +15,17 @@ CSRC = os.path.join(hipbuild.ROOT, "paper_2209_04634_amd", "csrc")
 KERNEL_SOURCES = ["evsim_kernels.hip", "evsim_lk.hip"]
 
 # waves per SIMD the hot kernels must keep (their current values; lower only on purpose).  The
-# chain kernels hold the texel loads of ten interior samples (two for difference frames) in flight
-# per lane, which costs registers: two waves per SIMD, measured faster than five with two samples.
+# chain kernels come in three variants (interior samples whose texel loads a lane keeps in
+# flight: 2 / 5 / 10, difference frames 1 / 2 / 4) that trade registers for waves per SIMD; the
+# runtime's autotuner picks among them.
 MIN_OCCUPANCY = {
-    "_ZN5evsim7k_chainILi0EEEvNS_9ChainArgsE": 2,          # reference-level chain
-    "_ZN5evsim7k_chainILi1EEEvNS_9ChainArgsE": 2,          # memoryless chain
-    "_ZN5evsim7k_chainILi2EEEvNS_9ChainArgsE": 4,          # difference-frame chain
+    "_ZN5evsim7k_chainILi0ELi0EEEvNS_9ChainArgsE": 5,      # reference-level chain, 2 in flight
+    "_ZN5evsim7k_chainILi0ELi1EEEvNS_9ChainArgsE": 4,      # 5 in flight
+    "_ZN5evsim7k_chainILi0ELi2EEEvNS_9ChainArgsE": 2,      # 10 in flight
+    "_ZN5evsim7k_chainILi1ELi0EEEvNS_9ChainArgsE": 5,      # memoryless chain
+    "_ZN5evsim7k_chainILi1ELi2EEEvNS_9ChainArgsE": 2,
+    "_ZN5evsim7k_chainILi2ELi0EEEvNS_9ChainArgsE": 6,      # difference-frame chain
+    "_ZN5evsim7k_chainILi2ELi2EEEvNS_9ChainArgsE": 3,
     # selection pass (a 1280x720 window launches 3.5 waves per SIMD: six per SIMD is ample)
     "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 6,
     "_ZN5evsim12k_radix_histEPKmPKyiPji": 8,
