@@ -69,7 +69,7 @@ def parse():
                     help="skip the extra legs (memoryless, difference, estimated flow, 64 batched "
                          "streams, 256-camera serving) that run in a child process after the "
                          "main measurement")
-    ap.add_argument("--legs-timeout", type=float, default=300.0)
+    ap.add_argument("--legs-timeout", type=float, default=420.0)
     ap.add_argument("--legs-child", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -157,19 +157,26 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
     return res
 
 
-def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES, pin=True):
-    """Serving loop: cameras of the serving configuration's resolutions, sparse method, frames
-    arriving as Poisson processes (rate U[30, 240] fps per camera) and copied from pinned host
-    memory on arrival; the loop steps the server whenever frames are queued.  Reports per-frame
-    latency (arrival to ordered events) and throughput."""
+def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES):
+    """Serving loop (continuous batching): cameras of the serving configuration's resolutions,
+    sparse method, frames arriving as Poisson processes (rate U[30, 240] fps per camera) and
+    handed to the server as they arrive (frames copied from pinned host memory, flows from a
+    device-resident pool), while the server's worker runs one batched step after another over
+    whatever is queued; events are drained into a device buffer every 20 ms.  Reports per-frame latency (arrival to ordered events), throughput and
+    the frames refused because a camera's staging ring was full."""
+    import ctypes
     import numpy as np
     rng = np.random.default_rng(7)
     pools = {}
+    P = 64
     for W, H in res_opts:
-        v = synth.blob_video(synth.mixed_stream(W, H, seed=W, n_frames=16))
-        fr, fl = torch.from_numpy(v.frames), torch.from_numpy(v.flows)
-        pools[(W, H)] = (fr.pin_memory(), fl.pin_memory()) if pin else (fr, fl)
-    srv = sim.Server(hbm_budget_bytes=64 << 30, max_cameras=args.cameras, queue_depth=8)
+        v = synth.blob_video(synth.serving_stream(W, H, seed=W, n_frames=P))
+        fr = torch.from_numpy(v.frames).pin_memory()
+        fl = torch.from_numpy(v.flows).to(dev)
+        pools[(W, H)] = (fr, fl, [fr[j].data_ptr() for j in range(P)],
+                         [fl[j].data_ptr() for j in range(P - 1)])
+    torch.cuda.synchronize()
+    srv = sim.Server(hbm_budget_bytes=160 << 30, max_cameras=args.cameras, queue_depth=8)
     cams = []
     for c in range(args.cameras):
         W, H = res_opts[int(rng.integers(3))]
@@ -177,41 +184,59 @@ def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES, pin=True):
             cid = srv.admit(width=W, height=H, method="sparse", c_pos=0.2, c_neg=0.2)
         except sim.SimError:
             continue
-        cams.append(dict(id=cid, W=W, H=H, rate=float(rng.uniform(30, 240)), k=0,
-                         next=0.0, t=0))
+        cams.append(dict(id=cid, W=W, H=H, rate=float(rng.uniform(30, 240)),
+                         k=int(rng.integers(P)), next=0.0, t=0))
+    lib, h = sim.load(), srv._h
+    drain = torch.empty(1 << 24, dtype=torch.int64, device=dev)
+
+    def submit(c, arrival):
+        """Frame k of the camera's pass over the pool (the flow of the interval ending there)."""
+        fr, fl, fp, lp = pools[(c["W"], c["H"])]
+        j = c["k"] % P
+        c["t"] += 1 + int(1e6 / c["rate"])
+        rc = lib.srv_submit(h, c["id"], ctypes.c_void_p(fp[j]),
+                            ctypes.c_void_p(lp[(j - 1) % (P - 1)]), c["t"], sim.MEM_HOST_FRAME,
+                            arrival)
+        c["k"] += 1                          # a refused frame (ring full) is dropped
+        return rc
+
+    for c in cams:       # warm-up, two frames per camera: buffers, tuning, recorded graphs
+        submit(c, 0)
+        submit(c, 0)
+    srv.sync()
+    for c in cams:
+        srv.drain_keys(c["id"], out=drain)
+    srv.clear_stats()
+    srv.start()
     start = time.perf_counter()
     for c in cams:
         c["next"] = start + float(rng.exponential(1.0 / c["rate"]))
-    frames = 0
+    offered = 0
+    last_drain = start
     while time.perf_counter() - start < args.serve:
         now = time.perf_counter()
-        queued = False
+        base_ns = srv.now_ns()
         for c in cams:
             while c["next"] <= now:
-                fr, fl = pools[(c["W"], c["H"])]
-                j = c["k"] % 16
-                flow = None if c["k"] == 0 else fl[(j - 1) % 15]
-                c["t"] += 1 + int(1e6 / c["rate"])
-                try:
-                    srv.submit(c["id"], fr[j], flow, c["t"],
-                               arrival_ns=int(srv.now_ns() - (now - c["next"]) * 1e9))
-                    c["k"] += 1
-                    queued = True
-                except sim.SimError:
-                    pass                                # queue full: the frame is dropped
+                submit(c, int(base_ns - (now - c["next"]) * 1e9))
+                offered += 1
                 c["next"] += float(rng.exponential(1.0 / c["rate"]))
-        if queued:
-            frames += srv.step()
+        if now - last_drain > 0.02:
             for c in cams:
-                srv.drain_keys(c["id"])
+                srv.drain_keys(c["id"], out=drain)
+            last_drain = now
+    srv.sync()
+    wall = time.perf_counter() - start
+    srv.stop()
     st = srv.stats()
     srv.close()
-    wall = time.perf_counter() - start
-    return {"cameras": len(cams), "seconds": round(wall, 2), "frames": frames,
-            "frames_per_s": round(frames / wall, 1), "events_per_s": round(st["events"] / wall, 1),
+    return {"cameras": len(cams), "seconds": round(wall, 2), "offered_frames": offered,
+            "frames": st["completed"], "frames_per_s": round(st["completed"] / wall, 1),
+            "events_per_s": round(st["events"] / wall, 1),
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
             "max_ms": round(st["max_ms"], 3), "rejected_frames": st["rejected_frames"],
-            "rejected_admissions": st["rejected_admissions"], "steps": st["steps"]}
+            "rejected_admissions": st["rejected_admissions"], "steps": st["steps"],
+            "frames_per_step": round(st["completed"] / max(1, st["steps"]), 1)}
 
 
 def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
@@ -360,7 +385,7 @@ def legs_child(args):
     args.batched = args.batched or 64
     leg("batched_vs_plain_streams", lambda: batched_leg(args, sim, synth, torch, dev))
     args.cameras = 256
-    args.serve = args.serve or 10.0
+    args.serve = args.serve or 60.0
     leg("serving", lambda: serve_leg(args, sim, synth, torch, dev))
 
 

@@ -81,6 +81,9 @@ enum { SIM_THRESH_REFERENCE = 0, SIM_THRESH_MEMORYLESS = 1 };
 enum { SIM_FLOW_SUPPLIED = 0, SIM_FLOW_LK = 1 };
 enum { SIM_LOG = 0, SIM_LINEAR = 1 };
 enum { SIM_MEM_HOST = 0, SIM_MEM_DEVICE = 1 };
+/* srv_submit only: the frame in host memory, the flow in device memory (cameras stream frames
+ * while flows are produced on the device). */
+enum { SIM_MEM_HOST_FRAME = 2 };
 
 typedef struct sim_config {
     int32_t width, height;      /* 1..4096 each (12-bit x and y fields of the packed key)          */
@@ -344,17 +347,22 @@ const char* sim_last_error(sim_stream* s);
  * Serving: many virtual cameras, continuous batching.
  *
  * A server owns cameras (one simulator stream each, with its device-resident state and a device
- * staging queue of `queue_depth` frames).  srv_admit creates a camera if a slot is free and its
- * estimated HBM footprint (srv_footprint) fits the remaining budget, else returns SIM_E_BUSY and
- * changes nothing; srv_release frees both.  srv_submit queues one frame (copied to the camera's
- * staging queue; SIM_E_BUSY when the queue is full, SIM_E_ORDER when t_us does not increase).
- * srv_step runs every queued frame of every camera as one batched push (sim_push_batch), so the
- * cameras' GPU work overlaps; frames submitted after a step started wait for the next one.  The
- * latency of a frame is the time from its arrival stamp (srv_now_ns clock; 0 = now) to the end
- * of the step that ordered its events.  Results per camera are exactly those of the camera's
- * frames pushed alone.  A server is not thread-safe.  srv_create reserves the server's own host
- * bookkeeping (about 8 MB of latency record, plus a little per camera slot), so it does not grow
- * while serving.
+ * staging ring of `queue_depth` frames (+ flows)).  srv_admit creates a camera if a slot is free
+ * and its estimated HBM footprint (srv_footprint) fits the remaining budget, else returns
+ * SIM_E_BUSY and changes nothing; srv_release frees both (frames still queued for it are dropped
+ * and counted as failed).  srv_submit queues one frame: its copy into the camera's ring is queued
+ * on the camera's stream and the call returns (SIM_E_BUSY when the ring is full, SIM_E_ORDER when
+ * t_us does not increase).  A step runs every queued frame of every camera as one batched push
+ * (sim_push_batch), so the cameras' GPU work overlaps.  srv_start runs steps on a worker thread
+ * of the server: each step admits every frame queued when it starts, frames that arrive while
+ * it runs are admitted by the next one, which starts as soon as it ends, and their copies
+ * overlap the running step on the device (continuous batching).  Without the worker, srv_step
+ * runs one step on the calling thread.  The latency of a frame is the time from its arrival stamp
+ * (srv_now_ns clock; 0 = now) to the end of the step that ordered its events.  Results per camera
+ * are exactly those of the camera's frames pushed alone.  Every srv_* call may come from any
+ * thread: calls are serialised inside the server, except that srv_submit (and srv_get_stats) do
+ * not wait for a running step.  srv_create reserves the server's own host bookkeeping (about 8 MB
+ * of latency record, plus a little per camera slot), so it does not grow while serving.
  * ------------------------------------------------------------------------------------------ */
 typedef struct sim_server sim_server;
 
@@ -381,20 +389,34 @@ int srv_destroy(sim_server* srv);
 int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam);
 int srv_release(sim_server* srv, int32_t cam);
 /* frame: uint8 [H][W]; flow: float32 [H][W][2] for the interval ending at this frame (required
- * for SIM_DENSE / SIM_SPARSE / SIM_DIFFERENCE except on a camera's first frame); both host or
- * both device.  The inputs are copied into the camera's staging slot before the call returns,
- * so the caller may reuse or free them at once; a device input must be complete (its writes
- * synchronised) at the call.  SIM_E_BUSY when the camera's queue is full (call srv_step),
- * SIM_E_ORDER when t_us does not increase. */
+ * for SIM_DENSE / SIM_SPARSE / SIM_DIFFERENCE except on a camera's first frame); both host
+ * (SIM_MEM_HOST), both device (SIM_MEM_DEVICE), or a host frame with a device flow
+ * (SIM_MEM_HOST_FRAME).  The inputs are read asynchronously, by a copy queued on the camera's stream: a
+ * device input must be complete (its writes synchronised) at the call, and host or device
+ * inputs must stay valid and unchanged until the frame completes (srv_sync, or the stats count
+ * it); pinned host memory lets the copy overlap device work.  SIM_E_BUSY when the camera's ring
+ * is full (a step frees it), SIM_E_ORDER when t_us does not increase. */
 int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* flow,
                int64_t t_us, int32_t mem_kind, int64_t arrival_ns);
-/* One continuous-batching step; *n_frames receives the frames completed.  Returns SIM_OK or the
- * first per-camera error (that camera's queued frames are dropped and counted as failed). */
+/* One continuous-batching step on the calling thread; *n_frames receives the frames completed.
+ * Returns SIM_OK or the first per-camera error (that camera's frames of the step are dropped
+ * and counted as failed); SIM_E_BUSY while the worker runs (it steps by itself). */
 int srv_step(sim_server* srv, uint64_t* n_frames);
+/* Starts the server's worker thread (steps back to back while frames are queued); a started
+ * server stays started until srv_stop or srv_destroy.  Errors: SIM_E_NOMEM (no thread). */
+int srv_start(sim_server* srv);
+/* Stops the worker after its current step (queued frames stay queued). */
+int srv_stop(sim_server* srv);
+/* Waits until every queued frame has completed (with the worker running: until it has run
+ * them; otherwise by running steps).  Returns SIM_OK or the first step error since the last
+ * srv_sync. */
+int srv_sync(sim_server* srv);
 /* Drains a camera's ordered events as packed keys (as sim_drain_keys). */
 int srv_drain(sim_server* srv, int32_t cam, uint64_t* dst, uint64_t max_events, int32_t mem_kind,
               uint64_t* n_written);
-/* The simulator stream of a camera (owned by the server). */
+/* Ordered events of a camera not yet drained (as sim_pending_events). */
+int srv_pending(sim_server* srv, int32_t cam, uint64_t* n);
+/* The simulator stream of a camera (owned by the server; not to be used while the worker runs). */
 int srv_stream(sim_server* srv, int32_t cam, sim_stream** out);
 int srv_get_stats(sim_server* srv, sim_server_stats* out);
 int srv_clear_stats(sim_server* srv);

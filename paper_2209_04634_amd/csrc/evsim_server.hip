@@ -1,18 +1,28 @@
 // Continuous-batching server over the simulator's C ABI (srv_* in include/sim.h).
 //
 // Many virtual cameras, each with its own device-resident simulator state (reference levels,
-// previous frame, event buffers) and a device staging queue for frames that arrived and wait for
+// previous frame, event buffers) and a device staging ring for frames that arrived and wait for
 // the GPU.  Cameras are admitted while their estimated HBM footprint fits the budget and a slot is
-// free; releasing a camera returns both.  srv_step() takes every queued frame of every camera and
+// free; releasing a camera returns both.  A step takes every queued frame of every camera and
 // runs them as one batched push (sim_push_batch), so different cameras' work overlaps on the
-// device while frames that arrive meanwhile wait for the next step.  Per frame, the latency from
-// its arrival stamp to the end of the step that ordered its events is recorded.
+// device.  srv_submit only queues the frame's copy into the camera's ring on the camera's stream
+// and returns: with the server's worker running (srv_start), steps follow one another while
+// frames keep arriving, each step admitting every frame queued when it starts, and the copies
+// of later frames overlap the running step's kernels.  Per frame, the latency from its arrival
+// stamp to the end of the step that ordered its events is recorded.
+//
+// Locking: `mu` guards the rings, the camera table and the statistics; `push_mu` is held for a
+// whole step (and by every call that touches a camera's simulator stream), so a step never sees
+// a camera released or drained under it, while srv_submit needs only `mu`.
 #include <math.h>
 #include <string.h>
 #include <time.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -31,9 +41,11 @@ struct Camera {
     int64_t npix = 0;
     bool interp = false;          // needs supplied flows
     bool started = false;         // has received its first frame (in a push)
-    int q = 0;                    // frames queued in staging
-    uint8_t* d_frames = nullptr;  // [qcap][H][W]
-    float* d_flows = nullptr;     // [qcap][H][W][2], slot j = flow of the interval ending at frame j
+    int head = 0;                 // oldest queued slot of the staging ring
+    int q = 0;                    // frames queued in the ring (from head, wrapping)
+    uint8_t* d_frames = nullptr;  // ring [qcap][H][W]
+    float* d_flows = nullptr;     // ring [qcap][H][W][2], slot j = flow of the interval ending at
+                                  // the frame of slot j
     std::vector<int64_t> t_us;
     std::vector<int64_t> arrival_ns;
     int64_t last_t = 0;
@@ -64,6 +76,13 @@ struct sim_server {
     uint64_t used = 0;
     int qcap = 0;
     std::vector<Camera> cams;
+    std::mutex mu;                 // rings, cameras, statistics
+    std::mutex push_mu;            // a step; calls on a camera's simulator stream
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool running = false, stopping = false;
+    uint64_t queued = 0;           // frames in the rings, not yet completed
+    int last_rc = SIM_OK;          // first error of a worker step since srv_sync
     // Everything below is reserved at creation, so that serving allocates no host memory.
     std::vector<float> lat_ms;     // ring of per-frame latencies
     size_t lat_next = 0;           // slot the next latency overwrites once the ring is full
@@ -71,6 +90,7 @@ struct sim_server {
     std::vector<sim_stream*> step_handles;
     std::vector<sim_frames> step_items;
     std::vector<int> step_cams;
+    std::vector<int> step_n;       // frames each camera contributes to the step
     sim_server_stats st;
 };
 
@@ -83,6 +103,102 @@ void record_latency(sim_server* srv, float ms) {
         srv->lat_ms[srv->lat_next] = ms;
         srv->lat_next = (srv->lat_next + 1) % kLatencyWindow;
     }
+}
+
+// One step: every camera's queued frames (those contiguous in its ring from its head) as one
+// batched push.  Holds push_mu throughout, mu while reading and updating the rings.  Returns
+// SIM_OK or the first per-camera error; *n_frames receives the frames completed.
+int run_step(sim_server* srv, uint64_t* n_frames) {
+    std::lock_guard<std::mutex> step(srv->push_mu);
+    std::vector<sim_stream*>& handles = srv->step_handles;   // capacity: one per camera slot
+    std::vector<sim_frames>& items = srv->step_items;
+    std::vector<int>& which = srv->step_cams;
+    std::vector<int>& taken = srv->step_n;
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        handles.clear();
+        items.clear();
+        which.clear();
+        taken.clear();
+        for (int i = 0; i < (int)srv->cams.size(); ++i) {
+            Camera& c = srv->cams[i];
+            if (!c.used || c.q == 0) continue;
+            const int n = std::min(c.q, srv->qcap - c.head);   // contiguous part of the ring
+            sim_frames it;
+            memset(&it, 0, sizeof(it));
+            it.n_frames = n;
+            it.mem_kind = SIM_MEM_DEVICE;
+            it.frames = c.d_frames + (size_t)c.head * c.npix;
+            // a camera's very first frame only initialises its state: its flow slot is unused
+            const int fl0 = c.started ? c.head : c.head + 1;
+            it.flows = c.interp ? c.d_flows + (size_t)fl0 * c.npix * 2 : nullptr;
+            it.t_us = c.t_us.data() + c.head;
+            handles.push_back(c.s);
+            items.push_back(it);
+            which.push_back(i);
+            taken.push_back(n);
+        }
+    }
+    if (n_frames) *n_frames = 0;
+    if (items.empty()) return SIM_OK;
+    const int rc = sim_push_batch(handles.data(), items.data(), (int32_t)items.size());
+    const int64_t done = now_ns();
+    uint64_t frames = 0;
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        for (size_t j = 0; j < items.size(); ++j) {
+            Camera& c = srv->cams[which[j]];
+            const int n = taken[j];
+            if (items[j].status == SIM_OK) {
+                for (int f = 0; f < n; ++f)
+                    record_latency(srv,
+                                   (float)((double)(done - c.arrival_ns[c.head + f]) * 1e-6));
+                frames += (uint64_t)n;
+                srv->st.events += items[j].n_new_events;
+                c.started = true;
+            } else {
+                srv->st.failed_frames += (uint64_t)n;
+            }
+            c.head = (c.head + n) % srv->qcap;
+            c.q -= n;
+            srv->queued -= (uint64_t)n;
+        }
+        srv->st.completed += frames;
+        srv->st.steps++;
+    }
+    srv->cv_done.notify_all();
+    if (n_frames) *n_frames = frames;
+    return rc;
+}
+
+// The worker of a running server: steps while frames are queued, sleeps otherwise.
+void worker_loop(sim_server* srv) {
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lock(srv->mu);
+            srv->cv_work.wait(lock, [&] { return srv->stopping || srv->queued > 0; });
+            if (srv->stopping) return;
+        }
+        const int rc = run_step(srv, nullptr);
+        if (rc) {
+            std::lock_guard<std::mutex> lock(srv->mu);
+            if (srv->last_rc == SIM_OK) srv->last_rc = rc;
+        }
+    }
+}
+
+void stop_worker(sim_server* srv) {
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        if (!srv->running) return;
+        srv->stopping = true;
+    }
+    srv->cv_work.notify_all();
+    srv->cv_done.notify_all();
+    srv->worker.join();
+    std::lock_guard<std::mutex> lock(srv->mu);
+    srv->running = false;
+    srv->stopping = false;
 }
 
 }  // namespace
@@ -126,6 +242,7 @@ int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_dep
         srv->step_handles.reserve(max_cameras);
         srv->step_items.reserve(max_cameras);
         srv->step_cams.reserve(max_cameras);
+        srv->step_n.reserve(max_cameras);
     } catch (...) {
         delete srv;
         return SIM_E_NOMEM;
@@ -138,6 +255,7 @@ int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_dep
 
 int srv_destroy(sim_server* srv) {
     if (!srv) return SIM_E_INVAL;
+    stop_worker(srv);
     for (Camera& c : srv->cams)
         if (c.used) release_camera(c);
     delete srv;
@@ -147,6 +265,8 @@ int srv_destroy(sim_server* srv) {
 int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
     if (!srv || !cfg || !cam) return SIM_E_INVAL;
     *cam = -1;
+    std::lock_guard<std::mutex> step(srv->push_mu);
+    std::lock_guard<std::mutex> lock(srv->mu);
     uint64_t fp = 0;
     int rc = srv_footprint(cfg, srv->qcap, &fp);
     if (rc) return rc;
@@ -206,8 +326,13 @@ int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
 }
 
 int srv_release(sim_server* srv, int32_t cam) {
-    if (!srv || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used)
-        return SIM_E_INVAL;
+    if (!srv) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> step(srv->push_mu);
+    std::lock_guard<std::mutex> lock(srv->mu);
+    if (cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used) return SIM_E_INVAL;
+    // frames still queued for the camera are dropped
+    srv->st.failed_frames += (uint64_t)srv->cams[cam].q;
+    srv->queued -= (uint64_t)srv->cams[cam].q;
     srv->used -= srv->cams[cam].footprint;
     release_camera(srv->cams[cam]);
     srv->st.cameras--;
@@ -217,101 +342,125 @@ int srv_release(sim_server* srv, int32_t cam) {
 
 int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* flow,
                int64_t t_us, int32_t mem_kind, int64_t arrival_ns) {
-    if (!srv || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used || !frame)
+    if (!srv || !frame) return SIM_E_INVAL;
+    if (mem_kind != SIM_MEM_HOST && mem_kind != SIM_MEM_DEVICE && mem_kind != SIM_MEM_HOST_FRAME)
         return SIM_E_INVAL;
-    if (mem_kind != SIM_MEM_HOST && mem_kind != SIM_MEM_DEVICE) return SIM_E_INVAL;
-    Camera& c = srv->cams[cam];
-    const bool first_ever = !c.started && c.q == 0;
-    if (c.interp && !first_ever && !flow) return SIM_E_INVAL;
-    if (c.any_t && t_us <= c.last_t) return SIM_E_ORDER;
-    if (c.q >= srv->qcap) {
-        srv->st.rejected_frames++;
-        return SIM_E_BUSY;
-    }
-    const hipMemcpyKind k = mem_kind == SIM_MEM_HOST ? hipMemcpyHostToDevice
-                                                     : hipMemcpyDeviceToDevice;
-    if (hipMemcpyAsync(c.d_frames + (size_t)c.q * c.npix, frame, (size_t)c.npix, k, c.stream) !=
-        hipSuccess)
-        return SIM_E_HIP;
-    if (c.interp && flow) {
-        if (hipMemcpyAsync(c.d_flows + (size_t)c.q * c.npix * 2, flow,
-                           (size_t)c.npix * 2 * sizeof(float), k, c.stream) != hipSuccess)
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        if (cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used) return SIM_E_INVAL;
+        Camera& c = srv->cams[cam];
+        const bool first_ever = !c.started && c.q == 0;
+        if (c.interp && !first_ever && !flow) return SIM_E_INVAL;
+        if (c.any_t && t_us <= c.last_t) return SIM_E_ORDER;
+        if (c.q >= srv->qcap) {
+            srv->st.rejected_frames++;
+            return SIM_E_BUSY;
+        }
+        const int slot = (c.head + c.q) % srv->qcap;
+        const hipMemcpyKind k = mem_kind == SIM_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                           : hipMemcpyHostToDevice;
+        const hipMemcpyKind kf = mem_kind == SIM_MEM_HOST ? hipMemcpyHostToDevice
+                                                          : hipMemcpyDeviceToDevice;
+        // queued on the camera's stream: the step that takes the slot waits for that stream
+        if (hipMemcpyAsync(c.d_frames + (size_t)slot * c.npix, frame, (size_t)c.npix, k,
+                           c.stream) != hipSuccess) {
+            (void)hipGetLastError();
             return SIM_E_HIP;
+        }
+        if (c.interp && flow) {
+            if (hipMemcpyAsync(c.d_flows + (size_t)slot * c.npix * 2, flow,
+                               (size_t)c.npix * 2 * sizeof(float), kf, c.stream) != hipSuccess) {
+                (void)hipGetLastError();
+                return SIM_E_HIP;
+            }
+        }
+        c.t_us[slot] = t_us;
+        c.arrival_ns[slot] = arrival_ns ? arrival_ns : now_ns();
+        c.q++;
+        c.last_t = t_us;
+        c.any_t = true;
+        srv->queued++;
+        srv->st.submitted++;
     }
-    if (hipStreamSynchronize(c.stream) != hipSuccess)
-        return SIM_E_HIP;   // the caller may reuse or free its buffer once we return
-    c.t_us[c.q] = t_us;
-    c.arrival_ns[c.q] = arrival_ns ? arrival_ns : now_ns();
-    c.q++;
-    c.last_t = t_us;
-    c.any_t = true;
-    srv->st.submitted++;
+    srv->cv_work.notify_one();
     return SIM_OK;
 }
 
 int srv_step(sim_server* srv, uint64_t* n_frames) {
     if (!srv) return SIM_E_INVAL;
     if (n_frames) *n_frames = 0;
-    std::vector<sim_stream*>& handles = srv->step_handles;   // capacity: one per camera slot
-    std::vector<sim_frames>& items = srv->step_items;
-    std::vector<int>& which = srv->step_cams;
-    handles.clear();
-    items.clear();
-    which.clear();
-    for (int i = 0; i < (int)srv->cams.size(); ++i) {
-        Camera& c = srv->cams[i];
-        if (!c.used || c.q == 0) continue;
-        sim_frames it;
-        memset(&it, 0, sizeof(it));
-        it.n_frames = c.q;
-        it.mem_kind = SIM_MEM_DEVICE;
-        it.frames = c.d_frames;
-        // a camera's very first frame only initialises its state: its flow slot is unused
-        it.flows = c.interp ? (c.started ? c.d_flows : c.d_flows + (size_t)c.npix * 2) : nullptr;
-        it.t_us = c.t_us.data();
-        handles.push_back(c.s);
-        items.push_back(it);
-        which.push_back(i);
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        if (srv->running) return SIM_E_BUSY;   // the worker steps
     }
-    if (items.empty()) return SIM_OK;
-    const int rc = sim_push_batch(handles.data(), items.data(), (int32_t)items.size());
-    const int64_t done = now_ns();
-    uint64_t frames = 0;
-    for (size_t j = 0; j < items.size(); ++j) {
-        Camera& c = srv->cams[which[j]];
-        if (items[j].status == SIM_OK) {
-            for (int f = 0; f < c.q; ++f)
-                record_latency(srv, (float)((double)(done - c.arrival_ns[f]) * 1e-6));
-            frames += (uint64_t)c.q;
-            srv->st.events += items[j].n_new_events;
-            c.started = true;
-        } else {
-            srv->st.failed_frames += (uint64_t)c.q;
+    return run_step(srv, n_frames);
+}
+
+int srv_start(sim_server* srv) {
+    if (!srv) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> lock(srv->mu);
+    if (srv->running) return SIM_OK;
+    try {
+        srv->worker = std::thread(worker_loop, srv);
+    } catch (...) {
+        return SIM_E_NOMEM;
+    }
+    srv->running = true;
+    return SIM_OK;
+}
+
+int srv_stop(sim_server* srv) {
+    if (!srv) return SIM_E_INVAL;
+    stop_worker(srv);
+    return SIM_OK;
+}
+
+int srv_sync(sim_server* srv) {
+    if (!srv) return SIM_E_INVAL;
+    std::unique_lock<std::mutex> lock(srv->mu);
+    // with the worker running, wait for it; if it is being stopped, run what is left here
+    if (srv->running)
+        srv->cv_done.wait(lock, [&] { return srv->queued == 0 || srv->stopping; });
+    int rc = srv->last_rc;
+    srv->last_rc = SIM_OK;
+    lock.unlock();
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> l(srv->mu);
+            if (srv->queued == 0) break;
         }
-        c.q = 0;
+        const int r = run_step(srv, nullptr);
+        if (r && rc == SIM_OK) rc = r;
     }
-    srv->st.completed += frames;
-    srv->st.steps++;
-    if (n_frames) *n_frames = frames;
     return rc;
 }
 
 int srv_drain(sim_server* srv, int32_t cam, uint64_t* dst, uint64_t max_events, int32_t mem_kind,
               uint64_t* n_written) {
-    if (!srv || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used)
-        return SIM_E_INVAL;
+    if (!srv) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> step(srv->push_mu);
+    if (cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used) return SIM_E_INVAL;
     return sim_drain_keys(srv->cams[cam].s, dst, max_events, mem_kind, n_written);
 }
 
+int srv_pending(sim_server* srv, int32_t cam, uint64_t* n) {
+    if (!srv || !n) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> step(srv->push_mu);
+    if (cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used) return SIM_E_INVAL;
+    return sim_pending_events(srv->cams[cam].s, n);
+}
+
 int srv_stream(sim_server* srv, int32_t cam, sim_stream** out) {
-    if (!srv || !out || cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used)
-        return SIM_E_INVAL;
+    if (!srv || !out) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> lock(srv->mu);
+    if (cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used) return SIM_E_INVAL;
     *out = srv->cams[cam].s;
     return SIM_OK;
 }
 
 int srv_get_stats(sim_server* srv, sim_server_stats* out) {
     if (!srv || !out) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> lock(srv->mu);
     *out = srv->st;
     const size_t n = srv->lat_ms.size();
     if (n) {
@@ -331,6 +480,7 @@ int srv_get_stats(sim_server* srv, sim_server_stats* out) {
 
 int srv_clear_stats(sim_server* srv) {
     if (!srv) return SIM_E_INVAL;
+    std::lock_guard<std::mutex> lock(srv->mu);
     const uint64_t cams = srv->st.cameras;
     memset(&srv->st, 0, sizeof(srv->st));
     srv->st.cameras = cams;

@@ -6,6 +6,7 @@ import fails with an error that says how to build it.
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 from typing import Optional, Sequence, Union
@@ -19,7 +20,7 @@ BASIC, DENSE, SPARSE, DIFFERENCE = 0, 1, 2, 3
 LOG, LINEAR = 0, 1
 REFERENCE, MEMORYLESS = 0, 1
 FLOW_SUPPLIED, FLOW_LK = 0, 1
-MEM_HOST, MEM_DEVICE = 0, 1
+MEM_HOST, MEM_DEVICE, MEM_HOST_FRAME = 0, 1, 2
 METHODS = {"basic": BASIC, "dense": DENSE, "sparse": SPARSE, "difference": DIFFERENCE}
 TRANSFORMS = {"log": LOG, "linear": LINEAR}
 THRESH_MODES = {"reference": REFERENCE, "memoryless": MEMORYLESS}
@@ -127,6 +128,10 @@ def load() -> ctypes.CDLL:
         "srv_release": (ctypes.c_int, [P, I32]),
         "srv_submit": (ctypes.c_int, [P, I32, P, P, I64, I32, I64]),
         "srv_step": (ctypes.c_int, [P, PU64]),
+        "srv_start": (ctypes.c_int, [P]),
+        "srv_stop": (ctypes.c_int, [P]),
+        "srv_sync": (ctypes.c_int, [P]),
+        "srv_pending": (ctypes.c_int, [P, I32, PU64]),
         "srv_drain": (ctypes.c_int, [P, I32, P, U64, I32, PU64]),
         "srv_stream": (ctypes.c_int, [P, I32, ctypes.POINTER(P)]),
         "srv_get_stats": (ctypes.c_int, [P, ctypes.POINTER(ServerStats)]),
@@ -564,6 +569,9 @@ class Server:
         self._h = h
         self.queue_depth = int(queue_depth)
         self._shape = {}
+        # the inputs of each camera's recent submissions: the library reads them asynchronously,
+        # and a ring slot is reused only after the step that read it
+        self._keep = {}
 
     @staticmethod
     def footprint(queue_depth: int = 8, **cfg) -> int:
@@ -580,31 +588,60 @@ class Server:
         cam = ctypes.c_int32()
         _check(self._lib.srv_admit(self._h, ctypes.byref(c), ctypes.byref(cam)), "srv_admit")
         self._shape[cam.value] = (c.height, c.width)
+        self._keep[cam.value] = collections.deque(maxlen=self.queue_depth + 1)
         return cam.value
 
     def release(self, cam: int) -> None:
         _check(self._lib.srv_release(self._h, int(cam)), "srv_release")
         self._shape.pop(int(cam), None)
+        self._keep.pop(int(cam), None)
 
     def submit(self, cam: int, frame, flow=None, t_us: int = 0, arrival_ns: int = 0) -> None:
         H, W = self._shape[int(cam)]
         fp, fk, fa = _buffer(frame, np.uint8, (H, W))
         lp, lk, la = _buffer(flow, np.float32, (H, W, 2))
+        kind = fk
         if lk is not None and lk != fk:
-            raise ValueError("frame and flow must both be host or both be device memory")
-        _check(self._lib.srv_submit(self._h, int(cam), fp, lp, int(t_us), fk, int(arrival_ns)),
+            if (fk, lk) != (MEM_HOST, MEM_DEVICE):
+                raise ValueError("a device frame needs a device flow")
+            kind = MEM_HOST_FRAME
+        _check(self._lib.srv_submit(self._h, int(cam), fp, lp, int(t_us), kind, int(arrival_ns)),
                "srv_submit")
+        self._keep[int(cam)].append((fa, la))
 
     def step(self) -> int:
         n = ctypes.c_uint64()
         _check(self._lib.srv_step(self._h, ctypes.byref(n)), "srv_step")
         return n.value
 
-    def drain_keys(self, cam: int, max_events: Optional[int] = None) -> np.ndarray:
-        s = ctypes.c_void_p()
-        _check(self._lib.srv_stream(self._h, int(cam), ctypes.byref(s)), "srv_stream")
+    def start(self) -> None:
+        """srv_start: steps run on the server's worker thread while frames are queued."""
+        _check(self._lib.srv_start(self._h), "srv_start")
+
+    def stop(self) -> None:
+        _check(self._lib.srv_stop(self._h), "srv_stop")
+
+    def sync(self) -> None:
+        """srv_sync: waits until every queued frame has completed."""
+        _check(self._lib.srv_sync(self._h), "srv_sync")
+
+    def pending(self, cam: int) -> int:
+        n = ctypes.c_uint64()
+        _check(self._lib.srv_pending(self._h, int(cam), ctypes.byref(n)), "srv_pending")
+        return n.value
+
+    def drain_keys(self, cam: int, max_events: Optional[int] = None, out=None):
+        """Drains a camera's ordered events: into a new numpy array, or into `out` (an int64
+        device tensor, returning the number written)."""
+        if out is not None:
+            p, kind, _ = _out_buffer(out, np.int64, None, also=(np.uint64,))
+            n = out.numel() if max_events is None else min(int(max_events), out.numel())
+            got = ctypes.c_uint64()
+            _check(self._lib.srv_drain(self._h, int(cam), p, n, kind, ctypes.byref(got)),
+                   "srv_drain")
+            return got.value
         pend = ctypes.c_uint64()
-        _check(self._lib.sim_pending_events(s, ctypes.byref(pend)), "sim_pending_events")
+        _check(self._lib.srv_pending(self._h, int(cam), ctypes.byref(pend)), "srv_pending")
         n = pend.value if max_events is None else int(max_events)
         arr = np.zeros(n, dtype=np.uint64)
         got = ctypes.c_uint64()

@@ -195,6 +195,14 @@ def mixed_stream(width: int, height: int, seed: int, n_frames: int = 30) -> Blob
                          motion="random", speed_max=12.0)
 
 
+def serving_stream(width: int, height: int, seed: int, n_frames: int = 64) -> BlobVideoSpec:
+    """A serving camera's pool: the sparse 1280x720 recipe (moving subset covering >= 10% of the
+    image at U[0,24] px/frame over a static background) with the blob count scaled by area."""
+    blobs = int(max(8, round(256 * width * height / 921600.0)))
+    return BlobVideoSpec(width, height, n_frames, 60.0, blobs, seed, motion="sparse",
+                         speed_max=24.0, moving_cover=0.10)
+
+
 def random_frames(rng: np.random.Generator, n: int, h: int, w: int,
                   flow_scale: float = 2.0) -> Tuple[np.ndarray, np.ndarray]:
     """Unstructured uint8 frames and fp32 flows for brute-force and edge-case testing."""

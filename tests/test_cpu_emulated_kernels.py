@@ -253,6 +253,43 @@ def test_emulated_server_results_match_cameras_alone(emu_sim):
     srv.close()
 
 
+def test_emulated_server_worker_continuous_batching(emu_sim):
+    """The same cameras with the server's worker running: frames are submitted from this thread
+    while the worker steps on its own (a full ring is retried after a short wait), then
+    srv_sync.  Every camera's events equal the oracle's for that camera alone, every frame is
+    completed, and manual steps are refused while the worker runs."""
+    import time
+    cams = _camera_videos(emu_sim)
+    srv = emu_sim.Server(hbm_budget_bytes=1 << 34, max_cameras=8, queue_depth=3)
+    ids = [srv.admit(width=c["W"], height=c["H"], method=c["method"], c_pos=0.15, c_neg=0.15,
+                     n_interp=4, event_capacity=16) for c in cams]
+    srv.start()
+    with pytest.raises(emu_sim.SimError) as e:
+        srv.step()
+    assert e.value.status == emu_sim.E_BUSY
+    rng = np.random.default_rng(1)
+    pos = [0] * len(cams)
+    while any(p < 9 for p in pos):
+        i = int(rng.integers(len(cams)))
+        if pos[i] >= 9:
+            continue
+        c, k = cams[i], pos[i]
+        flow = None if (c["method"] == "basic" or k == 0) else c["v"].flows[k - 1]
+        try:
+            srv.submit(ids[i], c["v"].frames[k], flow, int(c["v"].t_us[k]))
+            pos[i] += 1
+        except emu_sim.SimError as e:
+            assert e.status == emu_sim.E_BUSY       # ring full: the worker frees it
+            time.sleep(0.001)
+    srv.sync()
+    st = srv.stats()
+    assert st["completed"] == 9 * len(cams) and st["failed_frames"] == 0 and st["steps"] >= 1
+    for cid, c in zip(ids, cams):
+        np.testing.assert_array_equal(srv.drain_keys(cid), c["ok"])
+    srv.stop()
+    srv.close()
+
+
 def test_emulated_server_admission_by_footprint(emu_sim):
     fp = emu_sim.Server.footprint(queue_depth=2, width=64, height=48, method="sparse")
     srv = emu_sim.Server(hbm_budget_bytes=2 * fp + fp // 2, max_cameras=8, queue_depth=2)

@@ -147,19 +147,25 @@ def test_c4_batched_64_streams_full_size():
         np.testing.assert_array_equal(batched[i], ok, err_msg=str(d))
 
 
-def test_c5_serving_256_cameras():
+@pytest.mark.parametrize("worker", [False, True], ids=["manual-steps", "worker"])
+def test_c5_serving_256_cameras(worker):
     """The serving configuration's camera population: 256 sparse cameras (C = 0.2) with
-    resolutions drawn from 346x260, 640x480 and 1280x720, admitted by footprint, frames from
+    resolutions drawn from 346x260, 640x480 and 1280x720 (the sparse recipe with blob count
+    scaled by area), admitted by footprint, frames from
     device-resident pools at per-camera phases and rates U[30, 240] fps, submitted in random
-    interleaving with steps at random points.  Every camera equals the same frames pushed alone
-    on the GPU; sampled cameras equal the oracle; latency percentiles are reported."""
+    interleaving, with steps at random points or by the server's worker thread while frames keep
+    arriving (continuous batching; half the cameras then send host frames with device flows).
+    Every camera equals the same frames pushed alone on the GPU;
+    sampled cameras equal the oracle; latency percentiles are reported."""
+    import time
     import torch
     rng = np.random.default_rng(11)
     res = [(346, 260), (640, 480), (1280, 720)]
     pools = {}
     for W, H in res:
-        v = synth.blob_video(synth.mixed_stream(W, H, seed=3 * W, n_frames=16))
-        pools[(W, H)] = (v, torch.from_numpy(v.frames).cuda(), torch.from_numpy(v.flows).cuda())
+        v = synth.blob_video(synth.serving_stream(W, H, seed=3 * W, n_frames=16))
+        pools[(W, H)] = (v, torch.from_numpy(v.frames).cuda(), torch.from_numpy(v.flows).cuda(),
+                         torch.from_numpy(v.frames).pin_memory())
     torch.cuda.synchronize()
     srv = sim.Server(hbm_budget_bytes=200 << 30, max_cameras=256, queue_depth=4)
     cams = []
@@ -172,28 +178,36 @@ def test_c5_serving_256_cameras():
     n_frames = 6
     order = [c for c in range(256) for _ in range(n_frames)]
     rng.shuffle(order)
+    if worker:
+        srv.start()
     for c in order:
         cam = cams[c]
-        v, fr, fl = pools[(cam["W"], cam["H"])]
+        v, fr, fl, hfr = pools[(cam["W"], cam["H"])]
         j = cam["phase"] + cam["k"]
         flow = None if cam["k"] == 0 else fl[j - 1]
         t = 1000 + cam["k"] * cam["step"]
         while True:
             try:
-                srv.submit(cam["id"], fr[j], flow, t)
+                # with the worker, odd cameras send frames from pinned host memory
+                srv.submit(cam["id"], hfr[j] if worker and c % 2 else fr[j], flow, t)
                 break
             except sim.SimError as e:
                 assert e.status == sim.E_BUSY
-                srv.step()
+                if worker:
+                    time.sleep(0.0005)        # the worker frees the ring
+                else:
+                    srv.step()
         cam["k"] += 1
-        if rng.random() < 0.02:
+        if not worker and rng.random() < 0.02:
             srv.step()
-    srv.step()
+    srv.sync()
+    if worker:
+        srv.stop()
     st = srv.stats()
     assert st["cameras"] == 256 and st["completed"] == 256 * n_frames
     assert st["failed_frames"] == 0 and 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     for idx, cam in enumerate(cams):
-        v, fr, fl = pools[(cam["W"], cam["H"])]
+        v, fr, fl, _ = pools[(cam["W"], cam["H"])]
         a, b = cam["phase"], cam["phase"] + n_frames
         t = [1000 + k * cam["step"] for k in range(n_frames)]
         got = srv.drain_keys(cam["id"])
