@@ -207,6 +207,7 @@ def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES):
     for c in cams:
         srv.drain_keys(c["id"], out=drain)
     srv.clear_stats()
+    t0 = sim.batch_times()
     srv.start()
     start = time.perf_counter()
     for c in cams:
@@ -229,14 +230,22 @@ def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES):
     wall = time.perf_counter() - start
     srv.stop()
     st = srv.stats()
+    t1 = sim.batch_times()
     srv.close()
+    steps = max(1, st["steps"])
+    phases = {k: round((t1[k] - t0[k]) / steps, 3) for k in
+              ("inputs_ms", "plan_ms", "launch_ms", "wait_ms", "finish_ms", "device_ms")}
     return {"cameras": len(cams), "seconds": round(wall, 2), "offered_frames": offered,
             "frames": st["completed"], "frames_per_s": round(st["completed"] / wall, 1),
             "events_per_s": round(st["events"] / wall, 1),
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
             "max_ms": round(st["max_ms"], 3), "rejected_frames": st["rejected_frames"],
             "rejected_admissions": st["rejected_admissions"], "steps": st["steps"],
-            "frames_per_step": round(st["completed"] / max(1, st["steps"]), 1)}
+            "frames_per_step": round(st["completed"] / steps, 1),
+            "step_ms": round(st["busy_ms"] / steps, 3),
+            "worker_busy_frac": round(st["busy_ms"] / 1e3 / wall, 3),
+            "lock_wait_ms_per_step": round(st["lock_wait_ms"] / steps, 3),
+            "per_step_ms": phases}
 
 
 def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):

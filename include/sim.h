@@ -238,6 +238,19 @@ int sim_get_chain_variant(sim_stream* s, int32_t* variant);
  * NULL.  Errors: none (returns SIM_OK). */
 int sim_batch_stats(uint64_t* graphs_recorded, uint64_t* graph_launches, uint64_t* rerun_windows);
 
+/* Process-wide time spent by batched pushes since the library was loaded, per fused chunk (one
+ * chunk per window of up to 120 intervals of every stream of a sim_push_batch call): host time
+ * waiting for work already queued on the streams (their staged inputs), planning (per-stream
+ * tables, buffer checks, tuning), recording or replaying the chunk's graph, blocked until the
+ * chunk's counts are back, and finishing (re-runs, per-stream bookkeeping); and the device time
+ * of the chunks' sequences, from events recorded around them. */
+typedef struct sim_batch_timing {
+    uint64_t chunks;
+    double inputs_ms, plan_ms, launch_ms, wait_ms, finish_ms;
+    double device_ms;
+} sim_batch_timing;
+int sim_batch_times(sim_batch_timing* out);
+
 /* Number of events produced and not yet drained. */
 int sim_pending_events(sim_stream* s, uint64_t* n);
 
@@ -350,13 +363,13 @@ const char* sim_last_error(sim_stream* s);
  * staging ring of `queue_depth` frames (+ flows)).  srv_admit creates a camera if a slot is free
  * and its estimated HBM footprint (srv_footprint) fits the remaining budget, else returns
  * SIM_E_BUSY and changes nothing; srv_release frees both (frames still queued for it are dropped
- * and counted as failed).  srv_submit queues one frame: its copy into the camera's ring is queued
- * on the camera's stream and the call returns (SIM_E_BUSY when the ring is full, SIM_E_ORDER when
- * t_us does not increase).  A step runs every queued frame of every camera as one batched push
+ * and counted as failed).  srv_submit queues one frame into the camera's ring and returns
+ * (SIM_E_BUSY when the ring is full, SIM_E_ORDER when t_us does not increase).  Cameras whose
+ * configuration names no HIP stream share one stream of the server.  A step runs every queued frame of every camera as one batched push
  * (sim_push_batch), so the cameras' GPU work overlaps.  srv_start runs steps on a worker thread
  * of the server: each step admits every frame queued when it starts, frames that arrive while
- * it runs are admitted by the next one, which starts as soon as it ends, and their copies
- * overlap the running step on the device (continuous batching).  Without the worker, srv_step
+ * it runs are admitted by the next one, which starts as soon as it ends (continuous
+ * batching).  Without the worker, srv_step
  * runs one step on the calling thread.  The latency of a frame is the time from its arrival stamp
  * (srv_now_ns clock; 0 = now) to the end of the step that ordered its events.  Results per camera
  * are exactly those of the camera's frames pushed alone.  Every srv_* call may come from any
@@ -379,6 +392,9 @@ typedef struct sim_server_stats {
     uint64_t hbm_used, hbm_budget;/* footprint estimates of the admitted cameras, and the budget   */
     double p50_ms, p99_ms, max_ms;/* per-frame latency, arrival to ordered events, over the latest */
                                   /* 2^20 completed frames since srv_clear_stats                  */
+    double busy_ms;               /* wall time inside steps                                        */
+    double lock_wait_ms;          /* time steps waited for other calls on the cameras (drains,     */
+                                  /* admissions, releases) to finish                               */
 } sim_server_stats;
 
 /* Estimated device bytes of one camera with this configuration and staging queue depth. */
@@ -391,11 +407,13 @@ int srv_release(sim_server* srv, int32_t cam);
 /* frame: uint8 [H][W]; flow: float32 [H][W][2] for the interval ending at this frame (required
  * for SIM_DENSE / SIM_SPARSE / SIM_DIFFERENCE except on a camera's first frame); both host
  * (SIM_MEM_HOST), both device (SIM_MEM_DEVICE), or a host frame with a device flow
- * (SIM_MEM_HOST_FRAME).  The inputs are read asynchronously, by a copy queued on the camera's stream: a
- * device input must be complete (its writes synchronised) at the call, and host or device
- * inputs must stay valid and unchanged until the frame completes (srv_sync, or the stats count
- * it); pinned host memory lets the copy overlap device work.  SIM_E_BUSY when the camera's ring
- * is full (a step frees it), SIM_E_ORDER when t_us does not increase. */
+ * (SIM_MEM_HOST_FRAME).  Device inputs and pinned host inputs (hipHostMalloc) are read
+ * asynchronously by the step that takes the frame (one copy kernel per step pulls every queued
+ * input into the cameras' rings; the device reads pinned host memory directly); pageable host
+ * inputs are copied at the call.  A device input must be complete (its writes synchronised) at
+ * the call, and inputs must stay valid and unchanged until the frame completes (srv_sync, or the
+ * stats count it).  SIM_E_BUSY when the camera's ring is full (a step frees it), SIM_E_ORDER
+ * when t_us does not increase. */
 int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* flow,
                int64_t t_us, int32_t mem_kind, int64_t arrival_ns);
 /* One continuous-batching step on the calling thread; *n_frames receives the frames completed.

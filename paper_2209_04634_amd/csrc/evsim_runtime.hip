@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <new>
@@ -61,6 +62,7 @@ struct sim_stream {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool poisoned = false;
+    hipEvent_t ev_ready = nullptr;   // marks the stream's queued work for a batched push to wait on
 
     int64_t npix = 0;
     float* d_lut = nullptr;
@@ -177,6 +179,7 @@ int fail_mid_push(sim_stream* s, int rc, const char* what) {
 void free_stream(sim_stream* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->ev_ready) (void)hipEventDestroy(s->ev_ready);
     dfree(s->d_lut);
     dfree(s->d_lref);
     dfree(s->d_prev[0]);
@@ -860,6 +863,8 @@ struct BatchCtx {
     hipGraphExec_t graph_exec = nullptr;   // the recorded chunk of the last shape
     BatchShape graph_key;
     uint64_t graph_captures = 0, graph_launches = 0, redo_windows = 0;
+    sim_batch_timing times{};        // accumulated phase times of the chunks
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
     char* h_blob = nullptr;          // pinned: entries, block offsets, per-interval tables
     size_t h_cap = 0;
     char* d_blob = nullptr;
@@ -880,6 +885,8 @@ size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 bool batch_reserve(BatchCtx& c, size_t blob, size_t outs) {
     if (!c.stream && hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess)
         return false;
+    if (!c.ev_begin && hipEventCreate(&c.ev_begin) != hipSuccess) return false;
+    if (!c.ev_end && hipEventCreate(&c.ev_end) != hipSuccess) return false;
     if (blob > c.h_cap || blob > c.d_cap) {
         if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
         if (c.graph_exec) {   // its nodes point at the buffers being replaced
@@ -954,7 +961,14 @@ int fill_starts(int* start, const std::vector<int>& blocks) {
 // Entries whose chains ran out of arena space, or whose events outgrew the sort's grid, are
 // finished afterwards by the re-run path (grow the arena, resume the unfinished chains, gather and
 // sort again), which overwrites what the chunk's gather and sort wrote for them.
+double ms_between(std::chrono::steady_clock::time_point a,
+                  std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
 int fused_window(std::vector<FusedItem>& items) {
+    using clk = std::chrono::steady_clock;
+    const clk::time_point t_start = clk::now();
     BatchCtx& c = batch_ctx();
     const int n = (int)items.size();
     // blob: entries | 8 offset arrays of n + 1 ints | per-item delta (K floats) + tbase (K int64)
@@ -985,8 +999,32 @@ int fused_window(std::vector<FusedItem>& items) {
         }                                     \
     } while (0)
     // every stream's staged inputs and earlier work are complete before the batch stream reads
-    for (FusedItem& f : items)
-        if (hipStreamSynchronize(f.s->stream) != hipSuccess) return SIM_E_HIP;
+    // them: the batch stream waits on the device for an event marking each distinct stream's
+    // queued work (no host wait; entries that share a stream wait once)
+    {
+        std::vector<std::pair<hipStream_t, sim_stream*>> qs(n);
+        for (int e = 0; e < n; ++e) qs[e] = {items[e].s->stream, items[e].s};
+        std::sort(qs.begin(), qs.end(), [](const std::pair<hipStream_t, sim_stream*>& a,
+                                           const std::pair<hipStream_t, sim_stream*>& b) {
+            return (uintptr_t)a.first < (uintptr_t)b.first;
+        });
+        for (int e = 0; e < n; ++e) {
+            if (e && qs[e].first == qs[e - 1].first) continue;
+            sim_stream* s = qs[e].second;
+            if (!s->ev_ready &&
+                hipEventCreateWithFlags(&s->ev_ready, hipEventDisableTiming) != hipSuccess) {
+                s->ev_ready = nullptr;
+                (void)hipGetLastError();
+                return SIM_E_HIP;
+            }
+            if (hipEventRecord(s->ev_ready, qs[e].first) != hipSuccess ||
+                hipStreamWaitEvent(c.stream, s->ev_ready, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                return SIM_E_HIP;
+            }
+        }
+    }
+    const clk::time_point t_inputs = clk::now();
 
     std::vector<int> sel_blocks(n), order_blocks(n), chain_blocks[3], gather_blocks(n),
         sort_blocks(n), blocks(n);
@@ -1123,6 +1161,8 @@ int fused_window(std::vector<FusedItem>& items) {
                                hipMemcpyDeviceToHost, st);
         return r;
     };
+    const clk::time_point t_plan = clk::now();
+    BATCH_TRY(hipEventRecord(c.ev_begin, st));
     if (capturable) {
         BatchShape key;
         key.n = n;
@@ -1161,7 +1201,15 @@ int fused_window(std::vector<FusedItem>& items) {
     } else {
         BATCH_TRY(enqueue());
     }
+    BATCH_TRY(hipEventRecord(c.ev_end, st));
+    const clk::time_point t_launch = clk::now();
     BATCH_TRY(hipStreamSynchronize(st));
+    const clk::time_point t_wait = clk::now();
+    float dev_ms = 0.f;
+    if (hipEventElapsedTime(&dev_ms, c.ev_begin, c.ev_end) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_ms = 0.f;
+    }
 
     // entries that need the re-run path: chains out of arena space, or more events than the
     // sort's grid covered
@@ -1263,6 +1311,14 @@ int fused_window(std::vector<FusedItem>& items) {
         s->stats.events += f.n_valid;
         f.it->n_new_events += f.n_valid;
     }
+    sim_batch_timing& tm = c.times;
+    tm.chunks++;
+    tm.inputs_ms += ms_between(t_start, t_inputs);
+    tm.plan_ms += ms_between(t_inputs, t_plan);
+    tm.launch_ms += ms_between(t_plan, t_launch);
+    tm.wait_ms += ms_between(t_launch, t_wait);
+    tm.finish_ms += ms_between(t_wait, clk::now());
+    tm.device_ms += dev_ms;
     return SIM_OK;
 }
 
@@ -1612,6 +1668,14 @@ int sim_batch_stats(uint64_t* graphs_recorded, uint64_t* graph_launches, uint64_
     if (graphs_recorded) *graphs_recorded = c.graph_captures;
     if (graph_launches) *graph_launches = c.graph_launches;
     if (rerun_windows) *rerun_windows = c.redo_windows;
+    return SIM_OK;
+}
+
+int sim_batch_times(sim_batch_timing* out) {
+    if (!out) return SIM_E_INVAL;
+    BatchCtx& c = batch_ctx();
+    std::lock_guard<std::mutex> lock(c.mu);
+    *out = c.times;
     return SIM_OK;
 }
 

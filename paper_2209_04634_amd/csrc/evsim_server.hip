@@ -5,11 +5,15 @@
 // the GPU.  Cameras are admitted while their estimated HBM footprint fits the budget and a slot is
 // free; releasing a camera returns both.  A step takes every queued frame of every camera and
 // runs them as one batched push (sim_push_batch), so different cameras' work overlaps on the
-// device.  srv_submit only queues the frame's copy into the camera's ring on the camera's stream
-// and returns: with the server's worker running (srv_start), steps follow one another while
-// frames keep arriving, each step admitting every frame queued when it starts, and the copies
-// of later frames overlap the running step's kernels.  Per frame, the latency from its arrival
-// stamp to the end of the step that ordered its events is recorded.
+// device.  srv_submit only records where the frame (and flow) is and returns: inputs in device
+// memory or in pinned host memory are pulled into the cameras' rings by one copy kernel at the
+// start of the step that takes them (the device reads pinned host memory directly over the bus,
+// so thousands of small frames cost one launch rather than one DMA request each); pageable host
+// inputs are copied at submission.  Cameras without a stream of their own share the server's
+// stream, so a step waits on one stream rather than on one per camera.  With the server's worker
+// running (srv_start), steps follow one another while frames keep arriving, each step admitting
+// every frame queued when it starts.  Per frame, the latency from its arrival stamp to the end of
+// the step that ordered its events is recorded.
 //
 // Locking: `mu` guards the rings, the camera table and the statistics; `push_mu` is held for a
 // whole step (and by every call that touches a camera's simulator stream), so a step never sees
@@ -31,12 +35,68 @@
 
 namespace {
 
+// One input to pull into a ring slot at the start of a step.
+struct CopyDesc {
+    const unsigned char* src;   // device memory, or pinned host memory by its device address
+    unsigned char* dst;         // ring slot
+    uint64_t bytes;
+};
+
+constexpr uint64_t kCopyChunk = 64u << 10;   // bytes per workgroup of the copy kernel
+constexpr int kCopyThreads = 256;
+
+struct alignas(16) Vec16 {
+    uint64_t lo, hi;
+};
+
+// Copies every descriptor's bytes; workgroup b takes chunk b of the concatenation (cstart: the
+// descriptors' first chunks, n + 1 entries, the last the total).  Each lane keeps four 16-byte
+// loads in flight, which the bus reads of pinned host memory need.
+template <typename T>
+__device__ void copy_span(const unsigned char* __restrict__ s, unsigned char* __restrict__ t,
+                          uint64_t len) {
+    const uint64_t nv = len / sizeof(T);
+    const T* s4 = reinterpret_cast<const T*>(s);
+    T* t4 = reinterpret_cast<T*>(t);
+    for (uint64_t base = threadIdx.x; base < nv; base += 4 * kCopyThreads) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * kCopyThreads < nv) v[u] = s4[base + u * kCopyThreads];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (base + u * kCopyThreads < nv) t4[base + u * kCopyThreads] = v[u];
+    }
+    for (uint64_t i = nv * sizeof(T) + threadIdx.x; i < len; i += kCopyThreads) t[i] = s[i];
+}
+
+__global__ __launch_bounds__(kCopyThreads) void k_gather_copy(const CopyDesc* __restrict__ d,
+                                                              const uint64_t* __restrict__ cstart,
+                                                              int n) {
+    const uint64_t chunk = blockIdx.x;
+    int lo = 0, hi = n - 1;   // the last descriptor whose first chunk is at or before this one
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= chunk) lo = mid;
+        else hi = mid - 1;
+    }
+    const CopyDesc cd = d[lo];
+    const uint64_t off = (chunk - cstart[lo]) * kCopyChunk;
+    const uint64_t len = cd.bytes - off < kCopyChunk ? cd.bytes - off : kCopyChunk;
+    const unsigned char* s = cd.src + off;
+    unsigned char* t = cd.dst + off;
+    const uintptr_t a = (uintptr_t)s | (uintptr_t)t;
+    if ((a & 15) == 0) copy_span<Vec16>(s, t, len);
+    else if ((a & 7) == 0) copy_span<uint64_t>(s, t, len);
+    else if ((a & 3) == 0) copy_span<uint32_t>(s, t, len);
+    else copy_span<unsigned char>(s, t, len);
+}
+
 struct Camera {
     bool used = false;
     sim_stream* s = nullptr;
     sim_config cfg;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr;   // the server's shared stream unless the config names one
     uint64_t footprint = 0;
     int64_t npix = 0;
     bool interp = false;          // needs supplied flows
@@ -48,6 +108,8 @@ struct Camera {
                                   // the frame of slot j
     std::vector<int64_t> t_us;
     std::vector<int64_t> arrival_ns;
+    std::vector<const unsigned char*> src_frame;   // per slot: input to pull at the step, or
+    std::vector<const unsigned char*> src_flow;    // NULL when copied at submission
     int64_t last_t = 0;
     bool any_t = false;
 };
@@ -58,11 +120,21 @@ int64_t now_ns() {
     return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
 
+// The device address of pinned host memory, or NULL for pageable memory.
+const unsigned char* device_address_of_pinned(const void* p) {
+    hipPointerAttribute_t a;
+    memset(&a, 0, sizeof(a));
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return a.type == hipMemoryTypeHost ? (const unsigned char*)a.devicePointer : nullptr;
+}
+
 void release_camera(Camera& c) {
     if (c.s) sim_destroy(c.s);
     if (c.d_frames) (void)hipFree(c.d_frames);
     if (c.d_flows) (void)hipFree(c.d_flows);
-    if (c.own_stream && c.stream) (void)hipStreamDestroy(c.stream);
     c = Camera();
 }
 
@@ -91,6 +163,11 @@ struct sim_server {
     std::vector<sim_frames> step_items;
     std::vector<int> step_cams;
     std::vector<int> step_n;       // frames each camera contributes to the step
+    std::vector<std::pair<hipStream_t, CopyDesc>> step_copies;   // the step's ring fills
+    hipStream_t stream = nullptr;  // shared by the cameras without a stream of their own
+    CopyDesc* h_desc = nullptr;    // pinned: the step's descriptors, then their chunk starts
+    char* d_desc = nullptr;
+    size_t desc_cap = 0;           // descriptors the buffers hold
     sim_server_stats st;
 };
 
@@ -105,21 +182,88 @@ void record_latency(sim_server* srv, float ms) {
     }
 }
 
+// Queues the step's ring fills: per stream (in the usual case only the server's), one upload of
+// the descriptors and one copy kernel, ordered before the batched push, which waits for the
+// cameras' streams.  Holds push_mu (the descriptor buffers belong to the running step).
+int fill_rings(sim_server* srv, std::vector<std::pair<hipStream_t, CopyDesc>>& copies) {
+    if (copies.empty()) return SIM_OK;
+    const size_t n = copies.size();
+    if (n > srv->desc_cap) {
+        size_t cap = 1024;
+        while (cap < n) cap *= 2;
+        if (srv->h_desc) (void)hipHostFree(srv->h_desc);
+        if (srv->d_desc) (void)hipFree(srv->d_desc);
+        srv->h_desc = nullptr;
+        srv->d_desc = nullptr;
+        srv->desc_cap = 0;
+        const size_t bytes = cap * sizeof(CopyDesc) + (2 * cap + 2) * sizeof(uint64_t);
+        if (hipHostMalloc((void**)&srv->h_desc, bytes, 0) != hipSuccess ||
+            hipMalloc((void**)&srv->d_desc, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            if (srv->h_desc) (void)hipHostFree(srv->h_desc);
+            srv->h_desc = nullptr;
+            return SIM_E_NOMEM;
+        }
+        srv->desc_cap = cap;
+    }
+    std::stable_sort(copies.begin(), copies.end(),
+                     [](const std::pair<hipStream_t, CopyDesc>& a,
+                        const std::pair<hipStream_t, CopyDesc>& b) {
+                         return (uintptr_t)a.first < (uintptr_t)b.first;
+                     });
+    const size_t starts_off = srv->desc_cap * sizeof(CopyDesc);
+    uint64_t* h_starts = (uint64_t*)((char*)srv->h_desc + starts_off);
+    size_t si = 0;   // next free chunk-start slot
+    for (size_t a = 0; a < n;) {
+        size_t b = a;
+        while (b < n && copies[b].first == copies[a].first) ++b;
+        uint64_t chunks = 0;
+        for (size_t k = a; k < b; ++k) {
+            srv->h_desc[k] = copies[k].second;
+            h_starts[si + (k - a)] = chunks;
+            chunks += (copies[k].second.bytes + kCopyChunk - 1) / kCopyChunk;
+        }
+        h_starts[si + (b - a)] = chunks;
+        const hipStream_t st = copies[a].first;
+        const CopyDesc* d = (const CopyDesc*)(srv->d_desc + a * sizeof(CopyDesc));
+        const uint64_t* ds = (const uint64_t*)(srv->d_desc + starts_off + si * sizeof(uint64_t));
+        if (hipMemcpyAsync((void*)d, srv->h_desc + a, (b - a) * sizeof(CopyDesc),
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync((void*)ds, h_starts + si, (b - a + 1) * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIM_E_HIP;
+        }
+        if (chunks) {
+            hipLaunchKernelGGL(k_gather_copy, dim3((unsigned)chunks), dim3(kCopyThreads), 0, st,
+                               d, ds, (int)(b - a));
+            if (hipGetLastError() != hipSuccess) return SIM_E_HIP;
+        }
+        si += b - a + 1;
+        a = b;
+    }
+    return SIM_OK;
+}
+
 // One step: every camera's queued frames (those contiguous in its ring from its head) as one
 // batched push.  Holds push_mu throughout, mu while reading and updating the rings.  Returns
 // SIM_OK or the first per-camera error; *n_frames receives the frames completed.
 int run_step(sim_server* srv, uint64_t* n_frames) {
+    const int64_t asked = now_ns();
     std::lock_guard<std::mutex> step(srv->push_mu);
+    const int64_t began = now_ns();
     std::vector<sim_stream*>& handles = srv->step_handles;   // capacity: one per camera slot
     std::vector<sim_frames>& items = srv->step_items;
     std::vector<int>& which = srv->step_cams;
     std::vector<int>& taken = srv->step_n;
+    std::vector<std::pair<hipStream_t, CopyDesc>>& copies = srv->step_copies;
     {
         std::lock_guard<std::mutex> lock(srv->mu);
         handles.clear();
         items.clear();
         which.clear();
         taken.clear();
+        copies.clear();
         for (int i = 0; i < (int)srv->cams.size(); ++i) {
             Camera& c = srv->cams[i];
             if (!c.used || c.q == 0) continue;
@@ -133,6 +277,16 @@ int run_step(sim_server* srv, uint64_t* n_frames) {
             const int fl0 = c.started ? c.head : c.head + 1;
             it.flows = c.interp ? c.d_flows + (size_t)fl0 * c.npix * 2 : nullptr;
             it.t_us = c.t_us.data() + c.head;
+            for (int f = c.head; f < c.head + n; ++f) {
+                if (c.src_frame[f])
+                    copies.push_back({c.stream, {c.src_frame[f], c.d_frames + (size_t)f * c.npix,
+                                                 (uint64_t)c.npix}});
+                if (c.src_flow[f])
+                    copies.push_back(
+                        {c.stream, {c.src_flow[f], (unsigned char*)(c.d_flows + (size_t)f * c.npix * 2),
+                                    (uint64_t)c.npix * 2 * sizeof(float)}});
+                c.src_frame[f] = c.src_flow[f] = nullptr;
+            }
             handles.push_back(c.s);
             items.push_back(it);
             which.push_back(i);
@@ -141,7 +295,17 @@ int run_step(sim_server* srv, uint64_t* n_frames) {
     }
     if (n_frames) *n_frames = 0;
     if (items.empty()) return SIM_OK;
-    const int rc = sim_push_batch(handles.data(), items.data(), (int32_t)items.size());
+    int rc = fill_rings(srv, copies);
+    if (rc != SIM_OK) {
+        for (sim_frames& it : items) it.status = rc;
+    } else {
+        rc = sim_push_batch(handles.data(), items.data(), (int32_t)items.size());
+    }
+    if (rc != SIM_OK) {
+        // the fills may still be running: the descriptor buffers are reused by the next step
+        for (const auto& cp : copies) (void)hipStreamSynchronize(cp.first);
+        (void)hipGetLastError();
+    }
     const int64_t done = now_ns();
     uint64_t frames = 0;
     {
@@ -165,6 +329,8 @@ int run_step(sim_server* srv, uint64_t* n_frames) {
         }
         srv->st.completed += frames;
         srv->st.steps++;
+        srv->st.busy_ms += (double)(now_ns() - began) * 1e-6;
+        srv->st.lock_wait_ms += (double)(began - asked) * 1e-6;
     }
     srv->cv_done.notify_all();
     if (n_frames) *n_frames = frames;
@@ -243,6 +409,8 @@ int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_dep
         srv->step_items.reserve(max_cameras);
         srv->step_cams.reserve(max_cameras);
         srv->step_n.reserve(max_cameras);
+        srv->step_copies.reserve(std::min<size_t>((size_t)max_cameras * queue_depth * 2,
+                                                  size_t(1) << 16));
     } catch (...) {
         delete srv;
         return SIM_E_NOMEM;
@@ -258,6 +426,9 @@ int srv_destroy(sim_server* srv) {
     stop_worker(srv);
     for (Camera& c : srv->cams)
         if (c.used) release_camera(c);
+    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    if (srv->h_desc) (void)hipHostFree(srv->h_desc);
+    if (srv->d_desc) (void)hipFree(srv->d_desc);
     delete srv;
     return SIM_OK;
 }
@@ -288,11 +459,13 @@ int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
     if (cfg->hip_stream) {
         c.stream = (hipStream_t)cfg->hip_stream;
     } else {
-        if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) {
+        if (!srv->stream &&
+            hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
+            srv->stream = nullptr;
             (void)hipGetLastError();
             return SIM_E_NOMEM;
         }
-        c.own_stream = true;
+        c.stream = srv->stream;
         c.cfg.hip_stream = (void*)c.stream;
     }
     rc = sim_create(&c.cfg, &c.s);
@@ -310,6 +483,8 @@ int srv_admit(sim_server* srv, const sim_config* cfg, int32_t* cam) {
     try {
         c.t_us.resize(srv->qcap);
         c.arrival_ns.resize(srv->qcap);
+        c.src_frame.assign(srv->qcap, nullptr);
+        c.src_flow.assign(srv->qcap, nullptr);
     } catch (...) {
         c.used = true;
         release_camera(c);
@@ -345,6 +520,15 @@ int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* 
     if (!srv || !frame) return SIM_E_INVAL;
     if (mem_kind != SIM_MEM_HOST && mem_kind != SIM_MEM_DEVICE && mem_kind != SIM_MEM_HOST_FRAME)
         return SIM_E_INVAL;
+    // inputs the step's copy kernel can read: device memory, and pinned host memory (by its
+    // device address); pageable host memory is copied now
+    const unsigned char* pull_frame = mem_kind == SIM_MEM_DEVICE
+                                          ? (const unsigned char*)frame
+                                          : device_address_of_pinned(frame);
+    const unsigned char* pull_flow = nullptr;
+    if (flow)
+        pull_flow = mem_kind == SIM_MEM_HOST ? device_address_of_pinned(flow)
+                                             : (const unsigned char*)flow;
     {
         std::lock_guard<std::mutex> lock(srv->mu);
         if (cam < 0 || cam >= (int)srv->cams.size() || !srv->cams[cam].used) return SIM_E_INVAL;
@@ -357,23 +541,22 @@ int srv_submit(sim_server* srv, int32_t cam, const uint8_t* frame, const float* 
             return SIM_E_BUSY;
         }
         const int slot = (c.head + c.q) % srv->qcap;
-        const hipMemcpyKind k = mem_kind == SIM_MEM_DEVICE ? hipMemcpyDeviceToDevice
-                                                           : hipMemcpyHostToDevice;
-        const hipMemcpyKind kf = mem_kind == SIM_MEM_HOST ? hipMemcpyHostToDevice
-                                                          : hipMemcpyDeviceToDevice;
-        // queued on the camera's stream: the step that takes the slot waits for that stream
-        if (hipMemcpyAsync(c.d_frames + (size_t)slot * c.npix, frame, (size_t)c.npix, k,
+        // pageable inputs: queued on the camera's stream, which the step waits for
+        if (!pull_frame && hipMemcpyAsync(c.d_frames + (size_t)slot * c.npix, frame,
+                                          (size_t)c.npix, hipMemcpyHostToDevice,
+                                          c.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIM_E_HIP;
+        }
+        if (c.interp && flow && !pull_flow &&
+            hipMemcpyAsync(c.d_flows + (size_t)slot * c.npix * 2, flow,
+                           (size_t)c.npix * 2 * sizeof(float), hipMemcpyHostToDevice,
                            c.stream) != hipSuccess) {
             (void)hipGetLastError();
             return SIM_E_HIP;
         }
-        if (c.interp && flow) {
-            if (hipMemcpyAsync(c.d_flows + (size_t)slot * c.npix * 2, flow,
-                               (size_t)c.npix * 2 * sizeof(float), kf, c.stream) != hipSuccess) {
-                (void)hipGetLastError();
-                return SIM_E_HIP;
-            }
-        }
+        c.src_frame[slot] = pull_frame;
+        c.src_flow[slot] = c.interp ? pull_flow : nullptr;
         c.t_us[slot] = t_us;
         c.arrival_ns[slot] = arrival_ns ? arrival_ns : now_ns();
         c.q++;

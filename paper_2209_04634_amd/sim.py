@@ -72,7 +72,13 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "cameras", "admissions", "rejected_admissions", "submitted", "rejected_frames",
         "completed", "failed_frames", "steps", "events", "hbm_used", "hbm_budget")] + \
-        [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+        [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "max_ms", "busy_ms",
+                                         "lock_wait_ms")]
+
+
+class SimBatchTiming(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_uint64)] + [(n, ctypes.c_double) for n in (
+        "inputs_ms", "plan_ms", "launch_ms", "wait_ms", "finish_ms", "device_ms")]
 
 
 EVENT_DTYPE = np.dtype([("t", "<i8"), ("x", "<u2"), ("y", "<u2"), ("p", "i1"), ("pad", "u1", 3)])
@@ -119,6 +125,7 @@ def load() -> ctypes.CDLL:
         "sim_last_error": (ctypes.c_char_p, [P]),
         "sim_push_batch": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(SimFrames), I32]),
         "sim_batch_stats": (ctypes.c_int, [PU64, PU64, PU64]),
+        "sim_batch_times": (ctypes.c_int, [P]),
         "sim_set_chain_variant": (ctypes.c_int, [P, I32]),
         "sim_get_chain_variant": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
         "srv_footprint": (ctypes.c_int, [ctypes.POINTER(SimConfig), I32, PU64]),
@@ -230,6 +237,13 @@ def batch_stats() -> dict:
     _check(lib.sim_batch_stats(ctypes.byref(g), ctypes.byref(l), ctypes.byref(r)),
            "sim_batch_stats")
     return {"graphs_recorded": g.value, "graph_launches": l.value, "rerun_windows": r.value}
+
+
+def batch_times() -> dict:
+    """sim_batch_times: accumulated host phases and device time of the batched pushes' chunks."""
+    t = SimBatchTiming()
+    _check(load().sim_batch_times(ctypes.byref(t)), "sim_batch_times")
+    return {k: getattr(t, k) for k, _ in SimBatchTiming._fields_}
 
 
 def lk_flow(f0, f1, points=None, hip_stream=None, **params):

@@ -8,6 +8,8 @@
 #include "hip/hip_runtime.h"
 
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -338,11 +340,43 @@ hipError_t emu_hipFree(void* p) {
     free(p);
     return hipSuccess;
 }
+// Pinned host allocations (hipHostMalloc), which hipPointerGetAttributes reports as host memory
+// the device can read; other host memory is pageable unless emu_host_memory_pinned(1) says that
+// all of it is (so that tests can route host inputs through either path).
+static std::mutex g_pinned_mu;
+static std::map<uintptr_t, size_t> g_pinned;
+static bool g_all_pinned = false;
+extern "C" void emu_host_memory_pinned(int on) { g_all_pinned = on != 0; }
+
 hipError_t emu_hipHostMalloc(void** p, size_t n, unsigned) {
     *p = malloc(n ? n : 1);
-    return *p ? hipSuccess : hipErrorOutOfMemory;
+    if (!*p) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    g_pinned[(uintptr_t)*p] = n ? n : 1;
+    return hipSuccess;
+}
+hipError_t emu_hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) {
+    memset(a, 0, sizeof(*a));
+    bool pinned = g_all_pinned;
+    {
+        std::lock_guard<std::mutex> lock(g_pinned_mu);
+        auto it = g_pinned.upper_bound((uintptr_t)p);
+        if (it != g_pinned.begin()) {
+            --it;
+            pinned = pinned || (uintptr_t)p < it->first + it->second;
+        }
+    }
+    if (!pinned) return hipErrorInvalidValue;
+    a->type = hipMemoryTypeHost;
+    a->devicePointer = const_cast<void*>(p);
+    a->hostPointer = const_cast<void*>(p);
+    return hipSuccess;
 }
 hipError_t emu_hipHostFree(void* p) {
+    {
+        std::lock_guard<std::mutex> lock(g_pinned_mu);
+        g_pinned.erase((uintptr_t)p);
+    }
     free(p);
     return hipSuccess;
 }
@@ -419,6 +453,11 @@ hipError_t emu_hipStreamDestroy(hipStream_t s) {
 hipError_t emu_hipEventCreate(hipEvent_t* e) {
     *e = new emu_event_t();
     return hipSuccess;
+}
+hipError_t emu_hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return emu_hipEventCreate(e); }
+// work runs when it is queued, so a wait on an earlier record is already satisfied
+hipError_t emu_hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) {
+    return g_capture ? hipErrorInvalidValue : hipSuccess;
 }
 hipError_t emu_hipEventRecord(hipEvent_t e, hipStream_t) {
     e->t = std::chrono::steady_clock::now();

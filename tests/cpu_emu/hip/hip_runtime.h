@@ -54,7 +54,21 @@ enum hipMemcpyKind {
     hipMemcpyDeviceToDevice = 3,
     hipMemcpyDefault = 4
 };
+enum hipMemoryType {
+    hipMemoryTypeUnregistered = 0,
+    hipMemoryTypeHost = 1,
+    hipMemoryTypeDevice = 2,
+};
+typedef struct hipPointerAttribute_t {
+    enum hipMemoryType type;
+    int device;
+    void* devicePointer;
+    void* hostPointer;
+    int isManaged;
+    unsigned allocationFlags;
+} hipPointerAttribute_t;
 #define hipStreamNonBlocking 0x01
+#define hipEventDisableTiming 0x02
 
 // ---- thread geometry of the fiber currently running
 const emu_uint3& emu_thread_idx();
@@ -165,6 +179,9 @@ inline void emu_launch(const char* name, void (*k)(P...), dim3 grid, dim3 block,
 #define hipStreamSynchronize emu_hipStreamSynchronize
 #define hipStreamDestroy emu_hipStreamDestroy
 #define hipEventCreate emu_hipEventCreate
+#define hipPointerGetAttributes emu_hipPointerGetAttributes
+#define hipEventCreateWithFlags emu_hipEventCreateWithFlags
+#define hipStreamWaitEvent emu_hipStreamWaitEvent
 #define hipEventRecord emu_hipEventRecord
 #define hipEventSynchronize emu_hipEventSynchronize
 #define hipEventElapsedTime emu_hipEventElapsedTime
@@ -196,6 +213,9 @@ hipError_t emu_hipStreamCreateWithFlags(hipStream_t* s, unsigned flags);
 hipError_t emu_hipStreamSynchronize(hipStream_t s);
 hipError_t emu_hipStreamDestroy(hipStream_t s);
 hipError_t emu_hipEventCreate(hipEvent_t* e);
+hipError_t emu_hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p);
+hipError_t emu_hipEventCreateWithFlags(hipEvent_t* e, unsigned flags);
+hipError_t emu_hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 hipError_t emu_hipEventRecord(hipEvent_t e, hipStream_t s);
 hipError_t emu_hipEventSynchronize(hipEvent_t e);
 hipError_t emu_hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);

@@ -140,3 +140,33 @@ def test_noalloc_flow_validates_on_the_host():
         sim.E_TOO_BIG
     assert lib.sim_lk_flow_noalloc(f, f, 8, 8, pts, 0, fl, None, None, None) == sim.OK
     assert lib.sim_strerror(sim.E_TOO_BIG) != lib.sim_strerror(-100)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets (a C program
+    built against include/sim.h prints them)."""
+    import subprocess
+    pairs = [("sim_config", sim.SimConfig), ("sim_lk_params", sim.SimLkParams),
+             ("sim_event", sim.SimEvent), ("sim_stats", sim.SimStats),
+             ("sim_frames", sim.SimFrames), ("sim_server_stats", sim.ServerStats),
+             ("sim_batch_timing", sim.SimBatchTiming)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sim.h"', 'int main(void) {']
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    for ln in out.splitlines():
+        c, f, v = ln.split()
+        got[(c, f)] = int(v)
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)

@@ -253,11 +253,22 @@ def test_emulated_server_results_match_cameras_alone(emu_sim):
     srv.close()
 
 
-def test_emulated_server_worker_continuous_batching(emu_sim):
+@pytest.mark.parametrize("pinned", [False, True], ids=["copied-at-submit", "pulled-by-step"])
+def test_emulated_server_worker_continuous_batching(emu_sim, pinned):
     """The same cameras with the server's worker running: frames are submitted from this thread
     while the worker steps on its own (a full ring is retried after a short wait), then
-    srv_sync.  Every camera's events equal the oracle's for that camera alone, every frame is
-    completed, and manual steps are refused while the worker runs."""
+    srv_sync.  Host inputs are either pageable (copied into the ring at submission) or pinned
+    (pulled into the ring by the step's copy kernel).  Every camera's events equal the oracle's
+    for that camera alone, every frame is completed, and manual steps are refused while the
+    worker runs."""
+    emu_sim.load().emu_host_memory_pinned(1 if pinned else 0)
+    try:
+        _server_worker_run(emu_sim)
+    finally:
+        emu_sim.load().emu_host_memory_pinned(0)
+
+
+def _server_worker_run(emu_sim):
     import time
     cams = _camera_videos(emu_sim)
     srv = emu_sim.Server(hbm_budget_bytes=1 << 34, max_cameras=8, queue_depth=3)
@@ -340,19 +351,31 @@ ASAN_SCRIPT = textwrap.dedent("""
     f, fl = synth.random_frames(rng, 3, 5, 7)
     cases.append((f, fl, np.array([0, 10, 20]), dict(method=1, n_interp=40, event_capacity=1)))
     from test_cpu_emulated_kernels import _camera_videos
+    import time
     cams = _camera_videos(sim)[:2]     # two cameras of different shape and method suffice here
-    srv = sim.Server(hbm_budget_bytes=1 << 34, max_cameras=4, queue_depth=3)
-    ids = [srv.admit(width=c["W"], height=c["H"], method=c["method"], c_pos=0.15, c_neg=0.15,
-                     n_interp=4, event_capacity=8) for c in cams]
-    for k in range(9):
+    for pinned in (0, 1):              # host inputs copied at submission / pulled by the worker
+        sim.load().emu_host_memory_pinned(pinned)
+        srv = sim.Server(hbm_budget_bytes=1 << 34, max_cameras=4, queue_depth=3)
+        ids = [srv.admit(width=c["W"], height=c["H"], method=c["method"], c_pos=0.15,
+                         c_neg=0.15, n_interp=4, event_capacity=8) for c in cams]
+        if pinned:
+            srv.start()
+        for k in range(9):
+            for cid, c in zip(ids, cams):
+                fl = None if (c["method"] == "basic" or k == 0) else c["v"].flows[k - 1]
+                while True:
+                    try:
+                        srv.submit(cid, c["v"].frames[k], fl, int(c["v"].t_us[k]))
+                        break
+                    except sim.SimError:
+                        time.sleep(0.002)
+            if k % 3 == 2 and not pinned:
+                srv.step()
+        srv.sync()
         for cid, c in zip(ids, cams):
-            fl = None if (c["method"] == "basic" or k == 0) else c["v"].flows[k - 1]
-            srv.submit(cid, c["v"].frames[k], fl, int(c["v"].t_us[k]))
-        if k % 3 == 2:
-            srv.step()
-    for cid, c in zip(ids, cams):
-        assert np.array_equal(srv.drain_keys(cid), c["ok"])
-    srv.close()
+            assert np.array_equal(srv.drain_keys(cid), c["ok"])
+        srv.close()
+    sim.load().emu_host_memory_pinned(0)
     for frames, flows, t, cfg in cases:
         ocfg = dict((k, v) for k, v in cfg.items() if k != "event_capacity")
         ok, oref = oracle_run(frames, flows, t, **ocfg)
