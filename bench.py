@@ -93,6 +93,58 @@ def chain_bytes(npix: int, K: int, active: int, selected: int, events: int, meth
     return chains * per_chain + selected * per_sel + 8 * events
 
 
+def step_bytes(npix: int, K: int, selected: int, events: int, method: str,
+               memoryless: bool = False) -> int:
+    """Algorithmic HBM bytes of a whole step (every phase of the path, sort passes excluded),
+    per pixel-interval with the state in HBM between intervals: both frame endpoints (1 + 1 B;
+    the difference method reads 3), per interpolated pixel-interval (every one for the dense and
+    difference methods, the selected ones for sparse) the flow (8 B) and the reference level
+    read and written (8 B; none for memoryless and difference thresholding), and 8 B per event."""
+    ends = 3 if method == "difference" else 2
+    ref = 0 if (memoryless or method == "difference") else 8
+    if method == "basic":
+        return npix * K * (ends + ref) + 8 * events
+    interp = selected if method == "sparse" else npix * K
+    return npix * K * ends + interp * (8 + ref) + 8 * events
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 of the sources the simulation kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2209_04634_amd",
+                        "csrc")
+    for name in ("evsim_kernels.hip", "evsim_internal.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str, kernel: str = "k_chain"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of this
+    workload (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the counter reads for a
+    copy of known size), or None when there is none or the kernels changed since it was taken."""
+    import glob
+    import re
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*counters*.md"))):
+        with open(path) as f:
+            text = f.read()
+        for block in re.findall(r"```json\n(.*?)```", text, flags=re.S):
+            try:
+                d = json.loads(block)
+            except ValueError:
+                continue
+            if d.get("workload") != workload or d.get("kernel") != kernel:
+                continue
+            if d.get("source_sha256") != src:
+                return None
+            return (d["fetch_kib_per_dispatch"] * d["fetch_scale"] +
+                    d["write_kib_per_dispatch"] * d["write_scale"]) * 1024.0
+    return None
+
+
 BATCH_SHAPES = [(240, 180), (346, 260), (640, 480), (1920, 1080)]
 SERVE_SHAPES = [(346, 260), (640, 480), (1280, 720)]
 
@@ -155,6 +207,75 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
     g1 = sim.batch_stats()
     res["graphs"] = {k: g1[k] - g0[k] for k in g1}   # recorded, launched, re-run windows
     return res
+
+
+def host_cpu() -> dict:
+    """The host's logical CPUs (those this process may run on) and CPU model."""
+    import subprocess
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "model": model}
+
+
+def _oracle_worker(job):
+    """One process of the all-cores baseline: the oracle over the memory-mapped sequence, from
+    a common start time, repeated until `seconds` have passed; returns (px-intervals, events,
+    elapsed seconds)."""
+    folder, W, H, cfg, start_at, seconds, supplied = job
+    import numpy as np
+    from oracle.oracle import OracleSim
+    frames = np.load(os.path.join(folder, "frames.npy"), mmap_mode="r")
+    flows = np.load(os.path.join(folder, "flows.npy"), mmap_mode="r") if supplied else None
+    t_us = np.load(os.path.join(folder, "t_us.npy"))
+    K = len(t_us) - 1
+    while time.time() < start_at:
+        time.sleep(0.001)
+    a = time.perf_counter()
+    done = ev = 0
+    while time.perf_counter() - a < seconds:
+        o = OracleSim(W, H, **cfg)
+        o.push(np.asarray(frames[0]), None, int(t_us[0]))
+        for k in range(K):
+            e = o.push(np.asarray(frames[k + 1]), np.asarray(flows[k]) if supplied else None,
+                       int(t_us[k + 1]))
+            ev += len(e)
+            done += 1
+            if time.perf_counter() - a >= seconds:
+                break
+    return W * H * done, ev, time.perf_counter() - a
+
+
+def cpu_all_cores(video, W, H, cfg, supplied, seconds):
+    """The oracle on every logical CPU this process may use (at most 16): one process per CPU,
+    each simulating the same sequence from a shared memory-mapped copy, all starting together.
+    Returns the aggregate rate in Mpixel-frames/s and events/s, and the processes used."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    import numpy as np
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    base = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    folder = tempfile.mkdtemp(prefix="evsim_oracle_", dir=base)
+    try:
+        np.save(os.path.join(folder, "frames.npy"), video.frames)
+        if supplied:
+            np.save(os.path.join(folder, "flows.npy"), video.flows)
+        np.save(os.path.join(folder, "t_us.npy"), np.asarray(video.t_us))
+        start_at = time.time() + 8.0       # after every process has started and loaded
+        jobs = [(folder, W, H, cfg, start_at, seconds, supplied)] * procs
+        with mp.get_context("spawn").Pool(procs) as pool:
+            res = pool.map(_oracle_worker, jobs)
+    finally:
+        shutil.rmtree(folder, ignore_errors=True)
+    wall = max(r[2] for r in res)
+    return (sum(r[0] for r in res) / wall / 1e6, sum(r[1] for r in res) / wall, procs, wall)
 
 
 def serve_leg(args, sim, synth, torch, dev, res_opts=SERVE_SHAPES):
@@ -311,10 +432,20 @@ def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
                       memoryless=wl.get("thresh") == "memoryless")
     alg_per_launch = alg / launches_per_step
     achieved = alg_per_launch / (launch_ms * 1e-3) / 1e9
+    traffic = counter_traffic(wl_name)
+    # the whole step (every phase, sort passes excluded) against the same roof
+    sb = step_bytes(npix, K, sel_per_step, ev_per_step, wl["method"],
+                    memoryless=wl.get("thresh") == "memoryless")
+    step_gbs = sb / (elapsed / steps) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
                 "kernel": "k_chain", "launch_ms": round(launch_ms, 4),
-                "algorithmic_bytes_per_launch": int(alg_per_launch)}
+                "algorithmic_bytes_per_launch": int(alg_per_launch),
+                "traffic_gbs": None if traffic is None else
+                round(traffic / (launch_ms * 1e-3) / 1e9, 1),
+                "step_algorithmic_bytes": int(sb), "step_achieved": round(step_gbs, 1),
+                "step_frac": round(step_gbs / HBM_PEAK_GBS, 4)}
 
     # plain path: one push per frame, latency of each push until its events are ordered
     plain_res = None
@@ -482,11 +613,21 @@ def main():
             oev += len(e)
             done += 1
         ct = time.perf_counter() - a
-        cpu = {"value": round(npix * done / ct / 1e6, 3), "unit": "Mpixel-frames/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"first {done} of {K} intervals of the same {W}x{H} sequence, "
-                         f"single-threaded C oracle ({ct:.1f} s, {oev} events, "
-                         f"{oev / ct:.3g} events/s)"}
+        single = round(npix * done / ct / 1e6, 3)
+        ocfg = dict(method=sim.METHODS[wl["method"]], c_pos=wl["c"], c_neg=wl["c"],
+                    n_interp=wl["n_interp"],
+                    thresh_mode=sim.THRESH_MODES[wl.get("thresh", "reference")],
+                    flow_source=sim.FLOW_SOURCES[wl.get("flow", "supplied")])
+        rate, ev_rate, procs, wall = cpu_all_cores(video, W, H, ocfg, supplied,
+                                                   args.cpu_seconds)
+        cpu = {"value": round(rate, 3), "unit": "Mpixel-frames/s", "cores": procs,
+               "kind": "oracle",
+               "sample": f"the same {W}x{H} sequence ({K} intervals) simulated by {procs} "
+                         f"concurrent single-threaded C-oracle processes for {wall:.1f} s "
+                         f"({ev_rate:.3g} events/s in total); one process alone: {single} "
+                         f"Mpixel-frames/s over the first {done} intervals ({ct:.1f} s, "
+                         f"{oev} events)",
+               "single_core_value": single, "host": host_cpu()}
 
     batched = batched_leg(args, sim, synth, torch, dev) if args.batched else None
     served = serve_leg(args, sim, synth, torch, dev) if args.serve > 0 else None

@@ -38,6 +38,8 @@ PyrLayout pyr_layout(int W, int H, int levels) {
     return L;
 }
 
+extern __shared__ float smem[];   // dynamic LDS of the window kernel
+
 namespace {
 
 struct Level {
@@ -215,8 +217,117 @@ __global__ __launch_bounds__(256) void k_lk_points(const float* __restrict__ A,
     if (valid) valid[j] = ok ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_lk_window(LkWindowArgs a) {
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+// ------------------------------------------------------------------------------------------
+// One wave per point (the simulation's window pass).  The lanes share the window's positions
+// (position q = (dy + r) (2r + 1) + (dx + r), lane q mod 64): per level each lane samples the
+// first frame's intensity and gradients at its positions once and keeps them in registers for
+// every iteration, so an iteration samples only the second frame.  The sums run in the order of
+// the per-point loop above: the lanes write their positions' products to LDS and one lane per sum
+// adds them in position order, one rounding per addition, so the flow is bit-identical.
+// ------------------------------------------------------------------------------------------
+constexpr int kLkWave = 64;
+constexpr int kLkMaxPerLane = 16;   // (2 * 15 + 1)^2 = 961 <= 64 * 16 positions
+
+// v[0] + v[1] + ... + v[n - 1], left to right from 0.
+__device__ __forceinline__ float ordered_sum(const float* v, int n) {
+    float acc = 0.0f;
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = v[i + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u];
+    }
+    for (; i < n; ++i) acc += v[i];
+    return acc;
+}
+
+// lk_point with the wave's lanes sharing the window; `buf` holds 3 N + 4 floats of LDS.  Every
+// lane returns the same result.
+__device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L,
+                              const LkParams& P, int px, int py, float* fx, float* fy,
+                              float* buf) {
+    const int lane = threadIdx.x;
+    const int r = P.radius, side = 2 * r + 1, n = side * side;
+    const float N = (float)n;
+    float* p0 = buf;
+    float* p1 = buf + n;
+    float* p2 = buf + 2 * n;
+    float* res = buf + 3 * n;
+    float gx = 0.0f, gy = 0.0f;
+    for (int l = P.levels; l >= 0; --l) {
+        const Level I = level_of(A, L, l);
+        const Level J = level_of(B, L, l);
+        const float sc = ldexpf(1.0f, -l);
+        const float ux = (float)px * sc, uy = (float)py * sc;
+        float cix[kLkMaxPerLane], ciy[kLkMaxPerLane], ci0[kLkMaxPerLane];
+#pragma unroll
+        for (int j = 0; j < kLkMaxPerLane; ++j) {
+            const int q = lane + kLkWave * j;
+            cix[j] = ciy[j] = ci0[j] = 0.0f;
+            if (q < n) {
+                const int dy = q / side - r, dx = q - (q / side) * side - r;
+                const Tap t = tap_at(I, ux + (float)dx, uy + (float)dy);
+                cix[j] = bil_tap<1>(I, t);
+                ciy[j] = bil_tap<2>(I, t);
+                ci0[j] = bil_tap<0>(I, t);
+                p0[q] = cix[j] * cix[j];
+                p1[q] = cix[j] * ciy[j];
+                p2[q] = ciy[j] * ciy[j];
+            }
+        }
+        __syncthreads();
+        if (lane < 3) res[lane] = ordered_sum(lane == 0 ? p0 : (lane == 1 ? p1 : p2), n);
+        __syncthreads();
+        const float Gxx = res[0], Gxy = res[1], Gyy = res[2];
+        __syncthreads();   // the sums are read before the buffers are rewritten
+        const float trace = Gxx + Gyy;
+        const float det = Gxx * Gyy - Gxy * Gxy;
+        if (!(trace >= P.min_trace * N) || !(det >= P.min_ratio * trace * trace)) {
+            *fx = 0.0f;
+            *fy = 0.0f;
+            return false;
+        }
+        float vx = 0.0f, vy = 0.0f;
+        for (int k = 0; k < P.iters; ++k) {
+#pragma unroll
+            for (int j = 0; j < kLkMaxPerLane; ++j) {
+                const int q = lane + kLkWave * j;
+                if (q < n) {
+                    const int dy = q / side - r, dx = q - (q / side) * side - r;
+                    const float x = ux + (float)dx, y = uy + (float)dy;
+                    const Tap u = tap_at(J, x + (gx + vx), y + (gy + vy));
+                    const float d = ci0[j] - bil_tap<0>(J, u);
+                    p0[q] = d * cix[j];
+                    p1[q] = d * ciy[j];
+                }
+            }
+            __syncthreads();
+            if (lane < 2) res[lane] = ordered_sum(lane == 0 ? p0 : p1, n);
+            __syncthreads();
+            const float bx = res[0], by = res[1];
+            __syncthreads();
+            const float ex = (Gyy * bx - Gxy * by) / det;
+            const float ey = (Gxx * by - Gxy * bx) / det;
+            vx += ex;
+            vy += ey;
+            if (ex * ex + ey * ey < P.eps) break;
+        }
+        if (l > 0) {
+            gx = 2.0f * (gx + vx);
+            gy = 2.0f * (gy + vy);
+        } else {
+            *fx = gx + vx;
+            *fy = gy + vy;
+        }
+    }
+    return true;
+}
+
+// Block b (one wave): slot b of the active list (sparse) or pixel b.
+__global__ __launch_bounds__(kLkWave) void k_lk_window(LkWindowArgs a) {
+    const int slot = blockIdx.x;
     int p;
     if (a.act_px) {
         if (slot >= (int)*a.n_active) return;
@@ -229,11 +340,13 @@ __global__ __launch_bounds__(256) void k_lk_window(LkWindowArgs a) {
     for (int i = 0; i < a.K; ++i) {
         if (a.mask && !((a.mask[(int64_t)(i >> 5) * a.npix + p] >> (i & 31)) & 1u)) continue;
         float fx = 0.0f, fy = 0.0f;
-        lk_point(a.pyr + (uint64_t)i * a.lay.total, a.pyr + (uint64_t)(i + 1) * a.lay.total,
-                 a.lay, a.P, px, py, &fx, &fy);
-        float* out = a.flow + (int64_t)i * 2 * a.npix + 2 * (int64_t)p;
-        out[0] = fx;
-        out[1] = fy;
+        lk_point_wave(a.pyr + (uint64_t)i * a.lay.total, a.pyr + (uint64_t)(i + 1) * a.lay.total,
+                      a.lay, a.P, px, py, &fx, &fy, smem);
+        if (threadIdx.x == 0) {
+            float* out = a.flow + (int64_t)i * 2 * a.npix + 2 * (int64_t)p;
+            out[0] = fx;
+            out[1] = fy;
+        }
     }
 }
 
@@ -266,9 +379,12 @@ hipError_t launch_lk_points(const float* a, const float* b, const PyrLayout& lay
 }
 
 hipError_t launch_lk_window(const LkWindowArgs& a, int max_slots, hipStream_t stream) {
-    const int blocks = (max_slots + 255) / 256;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lk_window, dim3(blocks), dim3(256), 0, stream, a);
+    if (max_slots <= 0) return hipSuccess;
+    if (a.P.radius < 1 || (2 * a.P.radius + 1) * (2 * a.P.radius + 1) > kLkWave * kLkMaxPerLane)
+        return hipErrorInvalidValue;
+    const int side = 2 * a.P.radius + 1;
+    const size_t lds = (size_t)(3 * side * side + 4) * sizeof(float);
+    hipLaunchKernelGGL(k_lk_window, dim3(max_slots), dim3(kLkWave), lds, stream, a);
     return hipGetLastError();
 }
 

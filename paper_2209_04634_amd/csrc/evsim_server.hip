@@ -164,6 +164,7 @@ struct sim_server {
     std::vector<int> step_cams;
     std::vector<int> step_n;       // frames each camera contributes to the step
     std::vector<std::pair<hipStream_t, CopyDesc>> step_copies;   // the step's ring fills
+    std::vector<hipStream_t> fill_streams;   // streams of the last ring fills (reading h_desc)
     hipStream_t stream = nullptr;  // shared by the cameras without a stream of their own
     CopyDesc* h_desc = nullptr;    // pinned: the step's descriptors, then their chunk starts
     char* d_desc = nullptr;
@@ -187,6 +188,14 @@ void record_latency(sim_server* srv, float ms) {
 // cameras' streams.  Holds push_mu (the descriptor buffers belong to the running step).
 int fill_rings(sim_server* srv, std::vector<std::pair<hipStream_t, CopyDesc>>& copies) {
     if (copies.empty()) return SIM_OK;
+    // the previous step's uploads and copy kernels read these buffers; a step whose cameras all
+    // sent only their first frame runs no batched window, so nothing has waited for them yet
+    for (hipStream_t st : srv->fill_streams)
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            return SIM_E_HIP;
+        }
+    srv->fill_streams.clear();
     const size_t n = copies.size();
     if (n > srv->desc_cap) {
         size_t cap = 1024;
@@ -239,6 +248,7 @@ int fill_rings(sim_server* srv, std::vector<std::pair<hipStream_t, CopyDesc>>& c
                                d, ds, (int)(b - a));
             if (hipGetLastError() != hipSuccess) return SIM_E_HIP;
         }
+        srv->fill_streams.push_back(st);
         si += b - a + 1;
         a = b;
     }
@@ -409,6 +419,7 @@ int srv_create(uint64_t hbm_budget_bytes, int32_t max_cameras, int32_t queue_dep
         srv->step_items.reserve(max_cameras);
         srv->step_cams.reserve(max_cameras);
         srv->step_n.reserve(max_cameras);
+        srv->fill_streams.reserve(max_cameras);
         srv->step_copies.reserve(std::min<size_t>((size_t)max_cameras * queue_depth * 2,
                                                   size_t(1) << 16));
     } catch (...) {

@@ -18,12 +18,24 @@ def pytest_addoption(parser):
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "long: a CPU run of a minute or more (sanitizer builds, "
+                                       "exhaustive failure sweeps); runs with EMU_LONG=1")
     if config.getoption("--emulated-gpu"):
         sys.path.insert(0, os.path.join(ROOT, "tests", "cpu_emu"))
         import build as emu_build
         from paper_2209_04634_amd import sim
         sim.LIB_PATH = emu_build.build()
         sim._lib = None
+
+
+def pytest_collection_modifyitems(config, items):
+    # the default CPU suite stays a few minutes long; the long runs are opt-in
+    if os.environ.get("EMU_LONG") == "1":
+        return
+    skip = pytest.mark.skip(reason="long CPU run (a minute or more serially); set EMU_LONG=1")
+    for item in items:
+        if "long" in item.keywords:
+            item.add_marker(skip)
 
 
 def _needs_device(excinfo) -> bool:

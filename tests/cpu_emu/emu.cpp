@@ -7,9 +7,13 @@
 // which no fiber can make progress is reported as a deadlock; both abort the process.
 #include "hip/hip_runtime.h"
 
+#include <algorithm>
 #include <chrono>
+#include <deque>
 #include <map>
 #include <mutex>
+#include <random>
+#include <set>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -283,6 +287,10 @@ uint64_t emu_wave_exchange(int op, uint64_t value, int arg, int line) {
     return r;
 }
 
+// Execution options (emu_set_execution): shuffled block order when the seed is not zero.
+static uint64_t g_shuffle_seed = getenv("EMU_SHUFFLE") ? strtoull(getenv("EMU_SHUFFLE"), 0, 10) : 0;
+static uint64_t g_launches = 0;
+
 void emu_run_grid(dim3 grid, dim3 block, size_t shmem, const std::function<void()>& body,
                   const char* name) {
     if (shmem > sizeof(evsim::smem)) die("dynamic shared memory request too large");
@@ -292,21 +300,142 @@ void emu_run_grid(dim3 grid, dim3 block, size_t shmem, const std::function<void(
     if (block.y != 1 || block.z != 1 || block.x == 0 || block.x > 1024) die("unsupported block");
     g_gdim = grid;
     g_bdim = block;
-    for (unsigned bz = 0; bz < grid.z; ++bz)
-        for (unsigned by = 0; by < grid.y; ++by)
-            for (unsigned bx = 0; bx < grid.x; ++bx) {
-                g_block = emu_uint3{bx, by, bz};
-                run_block((int)block.x, body, name);
-            }
+    const uint64_t n = (uint64_t)grid.x * grid.y * grid.z;
+    if (g_shuffle_seed == 0) {
+        for (unsigned bz = 0; bz < grid.z; ++bz)
+            for (unsigned by = 0; by < grid.y; ++by)
+                for (unsigned bx = 0; bx < grid.x; ++bx) {
+                    g_block = emu_uint3{bx, by, bz};
+                    run_block((int)block.x, body, name);
+                }
+        return;
+    }
+    // blocks in a seeded random order (the device promises no order between blocks)
+    std::vector<uint64_t> order(n);
+    for (uint64_t i = 0; i < n; ++i) order[i] = i;
+    std::mt19937_64 rng(g_shuffle_seed + 0x9e3779b97f4a7c15ull * ++g_launches);
+    std::shuffle(order.begin(), order.end(), rng);
+    for (uint64_t i : order) {
+        g_block = emu_uint3{(unsigned)(i % grid.x), (unsigned)((i / grid.x) % grid.y),
+                            (unsigned)(i / ((uint64_t)grid.x * grid.y))};
+        run_block((int)block.x, body, name);
+    }
 }
 
 // ---- runtime API ------------------------------------------------------------------------------
+//
+// By default every call runs its work at once.  With deferred execution (emu_set_execution, or
+// EMU_DEFERRED=1 in the environment) kernels, memsets and copies that involve only device or
+// pinned memory are queued per stream and run only when a synchronisation needs them: a stream
+// or event synchronisation, a wait on an event, and the calls that HIP documents as synchronous
+// (hipFree and hipHostFree synchronise the device; a copy to or from pageable host memory
+// completes before it returns, after the work queued before it on its stream).  Code that reads a
+// result before synchronising, or frees or regrows a buffer that queued work still uses, then
+// reads stale data or trips the sanitizer, as it could on the device.
+struct emu_event_t;
+struct EmuOp {
+    int kind;                    // 0 work, 1 event record, 2 wait for an event record
+    std::function<void()> fn;
+    emu_event_t* ev;
+    uint64_t seq;                // the record's sequence number
+    struct emu_stream_t* where;  // wait: the stream holding that record
+};
 struct emu_stream_t {
-    int dummy;
+    std::deque<EmuOp> q;
 };
 struct emu_event_t {
     std::chrono::steady_clock::time_point t;
+    uint64_t recorded = 0, completed = 0;
+    emu_stream_t* where = nullptr;
 };
+
+static bool g_deferred = getenv("EMU_DEFERRED") && atoi(getenv("EMU_DEFERRED")) != 0;
+static std::recursive_mutex g_exec_mu;      // queues and execution (one host thread at a time)
+static emu_stream_t g_null_stream;
+static std::set<emu_stream_t*> g_streams = {&g_null_stream};
+
+static emu_stream_t* stream_of(hipStream_t s) { return s ? s : &g_null_stream; }
+
+static void drain_event(emu_event_t* e, uint64_t target, emu_stream_t* where);
+
+// Runs the head of a stream's queue (a wait first runs what it waits for).
+static void step_head(emu_stream_t* s) {
+    EmuOp op = std::move(s->q.front());
+    s->q.pop_front();
+    if (op.kind == 2) {
+        if (op.ev->completed < op.seq) drain_event(op.ev, op.seq, op.where);
+        return;
+    }
+    if (op.kind == 1) {
+        if (op.ev->completed < op.seq) op.ev->completed = op.seq;
+        op.ev->t = std::chrono::steady_clock::now();
+        return;
+    }
+    op.fn();
+}
+
+static void drain(emu_stream_t* s) {
+    while (!s->q.empty()) step_head(s);
+}
+
+static void drain_event(emu_event_t* e, uint64_t target, emu_stream_t* where) {
+    while (e->completed < target) {
+        if (!where || where->q.empty()) die("wait for an event record that is not queued");
+        step_head(where);
+    }
+}
+
+static void drain_all() {
+    for (bool any = true; any;) {
+        any = false;
+        for (emu_stream_t* s : g_streams)
+            if (!s->q.empty()) {
+                step_head(s);
+                any = true;
+            }
+    }
+}
+
+extern "C" void emu_set_execution(int deferred, unsigned long long shuffle_seed) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    drain_all();
+    g_deferred = deferred != 0;
+    g_shuffle_seed = shuffle_seed;
+}
+
+void emu_submit(hipStream_t s, std::function<void()> op) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    if (!g_deferred) {
+        op();
+        return;
+    }
+    stream_of(s)->q.push_back(EmuOp{0, std::move(op), nullptr, 0, nullptr});
+}
+
+// Pinned host allocations (hipHostMalloc), which hipPointerGetAttributes reports as host memory
+// the device can read; other host memory is pageable unless emu_host_memory_pinned(1) says that
+// all of it is (so that tests can route host inputs through either path).
+static std::mutex g_pinned_mu;
+static std::map<uintptr_t, size_t> g_pinned;
+static std::map<uintptr_t, size_t> g_device;   // hipMalloc allocations
+static bool g_all_pinned = false;
+extern "C" void emu_host_memory_pinned(int on) { g_all_pinned = on != 0; }
+
+static bool in_map(const std::map<uintptr_t, size_t>& m, const void* p) {
+    auto it = m.upper_bound((uintptr_t)p);
+    if (it == m.begin()) return false;
+    --it;
+    return (uintptr_t)p < it->first + it->second;
+}
+
+// Memory that HIP copies synchronously: host memory that is not pinned.  Anything that is not a
+// device or pinned allocation of this emulation counts as host memory, except __device__
+// variables, which tests reach only through the library.  (emu_host_memory_pinned changes only
+// what hipPointerGetAttributes reports, not how copies of host buffers behave.)
+static bool pageable(const void* p) {
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    return !in_map(g_device, p) && !in_map(g_pinned, p);
+}
 
 // Failure injection for tests of error handling: once armed with emu_fail_alloc_after(k), the
 // device allocation after k more successful ones fails (then the countdown is off again).
@@ -334,20 +463,22 @@ hipError_t emu_hipMalloc(void** p, size_t n) {
     memset(*p, 0xA5, n);   // device memory starts as garbage
     ++g_allocs;
     g_alloc_sizes.push_back(n);
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    g_device[(uintptr_t)*p] = n ? n : 1;
     return hipSuccess;
 }
 hipError_t emu_hipFree(void* p) {
+    {
+        std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+        drain_all();   // hipFree synchronises the device
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_pinned_mu);
+        g_device.erase((uintptr_t)p);
+    }
     free(p);
     return hipSuccess;
 }
-// Pinned host allocations (hipHostMalloc), which hipPointerGetAttributes reports as host memory
-// the device can read; other host memory is pageable unless emu_host_memory_pinned(1) says that
-// all of it is (so that tests can route host inputs through either path).
-static std::mutex g_pinned_mu;
-static std::map<uintptr_t, size_t> g_pinned;
-static bool g_all_pinned = false;
-extern "C" void emu_host_memory_pinned(int on) { g_all_pinned = on != 0; }
-
 hipError_t emu_hipHostMalloc(void** p, size_t n, unsigned) {
     *p = malloc(n ? n : 1);
     if (!*p) return hipErrorOutOfMemory;
@@ -357,14 +488,16 @@ hipError_t emu_hipHostMalloc(void** p, size_t n, unsigned) {
 }
 hipError_t emu_hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) {
     memset(a, 0, sizeof(*a));
-    bool pinned = g_all_pinned;
+    bool pinned = g_all_pinned, device = false;
     {
         std::lock_guard<std::mutex> lock(g_pinned_mu);
-        auto it = g_pinned.upper_bound((uintptr_t)p);
-        if (it != g_pinned.begin()) {
-            --it;
-            pinned = pinned || (uintptr_t)p < it->first + it->second;
-        }
+        pinned = pinned || in_map(g_pinned, p);
+        device = in_map(g_device, p);
+    }
+    if (device) {
+        a->type = hipMemoryTypeDevice;
+        a->devicePointer = const_cast<void*>(p);
+        return hipSuccess;
     }
     if (!pinned) return hipErrorInvalidValue;
     a->type = hipMemoryTypeHost;
@@ -374,6 +507,10 @@ hipError_t emu_hipPointerGetAttributes(hipPointerAttribute_t* a, const void* p) 
 }
 hipError_t emu_hipHostFree(void* p) {
     {
+        std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+        drain_all();   // hipHostFree synchronises the device
+    }
+    {
         std::lock_guard<std::mutex> lock(g_pinned_mu);
         g_pinned.erase((uintptr_t)p);
     }
@@ -381,6 +518,8 @@ hipError_t emu_hipHostFree(void* p) {
     return hipSuccess;
 }
 hipError_t emu_hipMemcpy(void* dst, const void* src, size_t n, hipMemcpyKind) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    drain(&g_null_stream);
     if (n) memmove(dst, src, n);
     return hipSuccess;
 }
@@ -407,9 +546,9 @@ hipError_t emu_hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode
     *e = new emu_graph_t(*g);   // an executable graph is a copy of the recorded ops
     return hipSuccess;
 }
-hipError_t emu_hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+hipError_t emu_hipGraphLaunch(hipGraphExec_t e, hipStream_t s) {
     if (g_capture) return hipErrorInvalidValue;
-    for (auto& op : e->ops) op();
+    for (auto& op : e->ops) emu_submit(s, op);
     return hipSuccess;
 }
 hipError_t emu_hipGraphDestroy(hipGraph_t g) {
@@ -421,32 +560,66 @@ hipError_t emu_hipGraphExecDestroy(hipGraphExec_t e) {
     return hipSuccess;
 }
 
-hipError_t emu_hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind k, hipStream_t) {
-    if (g_capture) {
-        emu_record([=]() { (void)emu_hipMemcpy(dst, src, n, k); });
+// A copy that HIP performs synchronously (pageable host memory on either side) runs now, after
+// the work queued before it on its stream; any other copy is queued.
+static hipError_t copy_on_stream(bool sync, hipStream_t s, std::function<void()> op) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    if (sync && g_deferred) {
+        drain(stream_of(s));
+        op();
         return hipSuccess;
     }
-    return emu_hipMemcpy(dst, src, n, k);
-}
-hipError_t emu_hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch,
-                                size_t width, size_t height, hipMemcpyKind, hipStream_t) {
-    if (width > dpitch || width > spitch) return hipErrorInvalidValue;
-    for (size_t r = 0; r < height; ++r)
-        memmove((char*)dst + r * dpitch, (const char*)src + r * spitch, width);
+    emu_submit(s, std::move(op));
     return hipSuccess;
 }
-hipError_t emu_hipMemsetAsync(void* p, int v, size_t n, hipStream_t) {
-    memset(p, v, n);
+hipError_t emu_hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t s) {
+    auto op = [=]() {
+        if (n) memmove(dst, src, n);
+    };
+    if (g_capture) {
+        emu_record(op);
+        return hipSuccess;
+    }
+    return copy_on_stream(n && (pageable(dst) || pageable(src)), s, op);
+}
+hipError_t emu_hipMemcpy2DAsync(void* dst, size_t dpitch, const void* src, size_t spitch,
+                                size_t width, size_t height, hipMemcpyKind, hipStream_t s) {
+    if (width > dpitch || width > spitch) return hipErrorInvalidValue;
+    auto op = [=]() {
+        for (size_t r = 0; r < height; ++r)
+            memmove((char*)dst + r * dpitch, (const char*)src + r * spitch, width);
+    };
+    if (g_capture) {
+        emu_record(op);
+        return hipSuccess;
+    }
+    return copy_on_stream(height && width && (pageable(dst) || pageable(src)), s, op);
+}
+hipError_t emu_hipMemsetAsync(void* p, int v, size_t n, hipStream_t s) {
+    auto op = [=]() { memset(p, v, n); };
+    if (g_capture) {
+        emu_record(op);
+        return hipSuccess;
+    }
+    emu_submit(s, op);
     return hipSuccess;
 }
 hipError_t emu_hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
     *s = new emu_stream_t();
+    g_streams.insert(*s);
     return hipSuccess;
 }
-hipError_t emu_hipStreamSynchronize(hipStream_t) {
-    return g_capture ? hipErrorInvalidValue : hipSuccess;   // not allowed while capturing
+hipError_t emu_hipStreamSynchronize(hipStream_t s) {
+    if (g_capture) return hipErrorInvalidValue;   // not allowed while capturing
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    drain(stream_of(s));
+    return hipSuccess;
 }
 hipError_t emu_hipStreamDestroy(hipStream_t s) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    drain(s);   // queued work completes before the stream's resources go
+    g_streams.erase(s);
     delete s;
     return hipSuccess;
 }
@@ -455,16 +628,33 @@ hipError_t emu_hipEventCreate(hipEvent_t* e) {
     return hipSuccess;
 }
 hipError_t emu_hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return emu_hipEventCreate(e); }
-// work runs when it is queued, so a wait on an earlier record is already satisfied
-hipError_t emu_hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) {
-    return g_capture ? hipErrorInvalidValue : hipSuccess;
-}
-hipError_t emu_hipEventRecord(hipEvent_t e, hipStream_t) {
-    e->t = std::chrono::steady_clock::now();
+hipError_t emu_hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+    if (g_capture) return hipErrorInvalidValue;
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    if (!g_deferred || e->recorded == 0) return hipSuccess;   // nothing to wait for
+    stream_of(s)->q.push_back(EmuOp{2, nullptr, e, e->recorded, e->where});
     return hipSuccess;
 }
-hipError_t emu_hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t emu_hipEventRecord(hipEvent_t e, hipStream_t s) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    const uint64_t seq = ++e->recorded;
+    e->where = stream_of(s);
+    if (!g_deferred) {
+        e->completed = seq;
+        e->t = std::chrono::steady_clock::now();
+        return hipSuccess;
+    }
+    e->where->q.push_back(EmuOp{1, nullptr, e, seq, nullptr});
+    return hipSuccess;
+}
+hipError_t emu_hipEventSynchronize(hipEvent_t e) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    drain_event(e, e->recorded, e->where);
+    return hipSuccess;
+}
 hipError_t emu_hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+    std::lock_guard<std::recursive_mutex> lock(g_exec_mu);
+    if (a->completed < a->recorded || b->completed < b->recorded) return hipErrorInvalidValue;
     *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();
     return hipSuccess;
 }

@@ -149,24 +149,27 @@ void emu_run_grid(dim3 grid, dim3 block, size_t shmem, const std::function<void(
 // when it runs, as on the device).
 bool emu_capturing();
 void emu_record(std::function<void()> op);
+// Queues work on a stream: run at once, or (deferred execution) when a synchronisation reaches it.
+void emu_submit(hipStream_t s, std::function<void()> op);
 
 template <class... P, class... A>
 inline void emu_launch(const char* name, void (*k)(P...), dim3 grid, dim3 block, size_t shmem,
-                       hipStream_t, A... args) {
+                       hipStream_t stream, A... args) {
     std::tuple<typename std::decay<P>::type...> params(args...);
+    auto op = [=]() {
+        auto p = params;
+        emu_run_grid(grid, block, shmem, [&]() { std::apply(k, p); }, name);
+    };
     if (emu_capturing()) {
-        emu_record([=]() {
-            auto p = params;
-            emu_run_grid(grid, block, shmem, [&]() { std::apply(k, p); }, name);
-        });
+        emu_record(op);
         return;
     }
-    emu_run_grid(grid, block, shmem, [&]() { std::apply(k, params); }, name);
+    emu_submit(stream, op);
 }
 #define hipLaunchKernelGGL(k, grid, block, shmem, stream, ...) \
     emu_launch(#k, k, grid, block, shmem, stream, __VA_ARGS__)
 
-// ---- runtime API (synchronous)
+// ---- runtime API (synchronous by default; see emu_set_execution for deferred execution)
 #define hipMalloc emu_hipMalloc
 #define hipFree emu_hipFree
 #define hipHostMalloc emu_hipHostMalloc

@@ -143,6 +143,7 @@ ASAN_SCRIPT = textwrap.dedent("""
 """)
 
 
+@pytest.mark.long
 def test_emulated_fused_batch_is_memory_safe_under_asan(tmp_path):
     lib = emu_build.build(asan=True)
     asan_rt = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True,

@@ -91,6 +91,7 @@ def test_every_allocation_failure_of_create(emu_sim):
     emu_sim.Stream(32, 16, method="sparse").close()
 
 
+@pytest.mark.long
 def test_every_allocation_failure_of_a_batch(emu_sim):
     """Per entry: completed (the oracle's events), untouched (failed while staging or
     reserving: nothing pending, a later push works) or poisoned (failed inside the fused
@@ -252,6 +253,7 @@ def run_heaviest_wave(s_mod, arm):
     raise AssertionError("no allocation of the push failed after the chain kernel")
 
 
+@pytest.mark.long
 def test_heaviest_wave_fails_cleanly(emu_sim):
     dt = run_heaviest_wave(emu_sim, lambda k: _arm(emu_sim, k))
     assert dt < 120, dt
@@ -292,6 +294,7 @@ ASAN_SCRIPT = textwrap.dedent("""
 """)
 
 
+@pytest.mark.long
 def test_heaviest_wave_is_memory_safe_under_asan(tmp_path):
     lib = emu_build.build(asan=True)
     asan_rt = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True,

@@ -385,6 +385,7 @@ ASAN_SCRIPT = textwrap.dedent("""
 """)
 
 
+@pytest.mark.long
 def test_emulated_kernels_are_memory_safe_under_asan(tmp_path):
     """Every device-memory access of the runtime and kernels, bounds-checked by AddressSanitizer
     (device buffers are host allocations in this build), on overflow re-runs, window splits and

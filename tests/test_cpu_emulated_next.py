@@ -246,6 +246,7 @@ ASAN_SCRIPT = textwrap.dedent("""
 """)
 
 
+@pytest.mark.long
 def test_emulated_next_paths_are_memory_safe_under_asan(tmp_path):
     """The difference method (window splits, overflow re-runs, the recompute path beyond the LDS
     stash), memoryless thresholding and the accumulation kernels under AddressSanitizer."""

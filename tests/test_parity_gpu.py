@@ -93,9 +93,12 @@ def test_basic_240x180():
 
 @pytest.mark.skip(reason="a window driver that gathered and sorted before checking for "
                   "event-buffer overflow faulted the GPU on this sequence (many buffer regrowths) "
-                  "twice; that driver is removed, but this case stays off the GPU until the cause "
-                  "is shown on the CPU and fixed; the same arithmetic at this size is covered by "
-                  "the per-frame and overflow tests below")
+                  "twice; that driver is removed and its cause was never shown, so this case stays "
+                  "off the GPU until the cause is shown on the CPU and fixed.  The current driver "
+                  "runs this exact case bit-exactly on the CPU emulation with deferred execution, "
+                  "shuffled blocks and AddressSanitizer (test_cpu_emulated_deferred.py); the "
+                  "same arithmetic at this size is covered on the GPU by the per-frame and "
+                  "overflow tests below")
 def test_dense_346x260_full_sequence():
     v = synth.blob_video(synth.dense_346x260())
     n = assert_parity(v.frames, v.flows, v.t_us, modes=("window", "device"), method=sim.DENSE,
