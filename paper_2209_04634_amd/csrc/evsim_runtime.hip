@@ -502,7 +502,6 @@ std::string device_arch(Tuner& t) {
 // Times every variant of the chain pass `a` (max_slots slots) on `st`; returns the fastest, or
 // the default variant if anything fails.  Waits on `st`.
 int tune_chain(sim_stream* s, const ChainArgs& a, int max_slots, hipStream_t st) {
-    const size_t arena_n = (size_t)kArenaStripes * a.stripe_cap;
     ChainArgs t = a;
     float* lref = nullptr;
     int* resume = nullptr;
@@ -512,20 +511,29 @@ int tune_chain(sim_stream* s, const ChainArgs& a, int max_slots, hipStream_t st)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool ok = (a.mode != kModeReference || dev_alloc(&lref, (size_t)s->npix) == hipSuccess) &&
               dev_alloc(&resume, (size_t)max_slots) == hipSuccess &&
-              dev_alloc(&arena, arena_n) == hipSuccess &&
               dev_alloc(&reserve, (size_t)kArenaStripes * kCounterStride) == hipSuccess &&
               dev_alloc(&fails, 4) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
               hipEventCreate(&e1) == hipSuccess;
     float ms[kChainVariants];
-    for (int v = 0; v < kChainVariants; ++v) ms[v] = 1e30f;
-    if (ok) {
+    // The scratch arena starts at the stream's capacity and grows fourfold (up to 2^28 keys)
+    // while a timed pass runs out of space: a pass whose waves stop early would be timed on
+    // part of the work.
+    uint64_t cap = std::max<uint64_t>(a.stripe_cap, 1);
+    for (int attempt = 0; ok; ++attempt) {
+        dfree(arena);
+        arena = nullptr;
+        ok = dev_alloc(&arena, (size_t)kArenaStripes * cap) == hipSuccess;
+        if (!ok) break;
         if (lref) t.lref = lref;
         t.resume = resume;
         t.arena = arena;
+        t.stripe_cap = cap;
         t.reserve = reserve;
         t.fails = fails;
-        for (int rep = 0; rep < 4 && ok; ++rep) {   // a warm-up round, then the best of three
-            for (int v = 0; v < kChainVariants && ok; ++v) {
+        for (int v = 0; v < kChainVariants; ++v) ms[v] = 1e30f;
+        bool overflow = false;
+        for (int rep = 0; rep < 4 && ok && !overflow; ++rep) {   // a warm-up, then best of three
+            for (int v = 0; v < kChainVariants && ok && !overflow; ++v) {
                 // the state the real pass starts from: levels as they are, every chain at its
                 // first interval, empty arena counters
                 ok = (!lref || hipMemcpyAsync(lref, a.lref, (size_t)s->npix * sizeof(float),
@@ -537,11 +545,23 @@ int tune_chain(sim_stream* s, const ChainArgs& a, int max_slots, hipStream_t st)
                      hipEventRecord(e0, st) == hipSuccess &&
                      launch_chain(t, max_slots, v, st) == hipSuccess &&
                      hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                unsigned long long failed = 0;
+                ok = ok &&
+                     hipMemcpyAsync(&failed, fails, sizeof(failed), hipMemcpyDeviceToHost, st) ==
+                         hipSuccess &&
+                     hipStreamSynchronize(st) == hipSuccess;
+                overflow = ok && failed != 0;
                 float m = 0.0f;
-                if (ok && rep > 0 && hipEventElapsedTime(&m, e0, e1) == hipSuccess)
+                if (ok && !overflow && rep > 0 && hipEventElapsedTime(&m, e0, e1) == hipSuccess)
                     ms[v] = std::min(ms[v], m);
             }
         }
+        if (!overflow || (uint64_t)kArenaStripes * cap * 4 > (1ull << 28)) {
+            if (overflow)   // timed on part of the work: fall back to the default
+                for (int v = 0; v < kChainVariants; ++v) ms[v] = 1e30f;
+            break;
+        }
+        cap *= 4;
     }
     if (!ok) (void)hipGetLastError();
     (void)hipStreamSynchronize(st);

@@ -3,6 +3,8 @@
 gives the oracle's events and levels bit for bit, and the autotuned stream picks one of them,
 keeps it for later windows of the same shape and gives the same result.  The product never loads
 these builds."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -47,3 +49,36 @@ def test_chain_variant_argument_is_validated(emu_sim):
             s.set_chain_variant(bad)
         assert e.value.status == emu_sim.E_INVAL
     s.close()
+
+
+def test_tuning_runs_are_not_cut_short_by_a_small_arena(emu_sim):
+    """A fresh shape tuned on a window whose events overflow the stream's arena: the tuner's timed
+    passes run on a scratch arena grown until no wave runs out of space (so each variant is timed
+    on the whole window).  Against the same push with the variant forced (no tuning), the device
+    allocation log of the tuned push holds a scratch arena of 4^k times the stream's capacity
+    (k >= 1); both results equal the oracle's."""
+    from collections import Counter
+    lib = emu_sim.load()
+    v = synth.blob_video(synth.BlobVideoSpec(43, 31, 6, 30.0, 8, seed=21, motion="random",
+                                             speed_max=6.0))
+    cfg = dict(method="dense", c_pos=0.02, c_neg=0.02, n_interp=9)
+    ok, oref = oracle_run(v.frames, v.flows, v.t_us, method=sim.DENSE, c_pos=0.02, c_neg=0.02,
+                          n_interp=9)
+    logs, chosen = {}, None
+    for forced in (-1, None):           # tuned, then the tuned choice forced (no tuning)
+        s = emu_sim.Stream(43, 31, event_capacity=1, **cfg)   # the smallest arena
+        cap0 = s.stats()["event_capacity"]
+        assert len(ok) > 2 * cap0       # every timed pass on the stream's arena would overflow
+        s.set_chain_variant(chosen if forced is None else forced)
+        lib.emu_reset_alloc_log()
+        s.push_frames(v.frames, v.flows, v.t_us)
+        sizes = (ctypes.c_size_t * 4096)()
+        n = lib.emu_alloc_log(sizes, 4096)
+        logs[forced] = Counter(sizes[i] for i in range(min(n, 4096)))
+        chosen = s.chain_variant()
+        np.testing.assert_array_equal(s.drain_keys(), ok)
+        np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32))
+        s.close()
+    extra = logs[-1] - logs[None]       # what the tuning allocated
+    grown = {8 * cap0 * 4 ** k for k in range(1, 12)}   # scratch arenas the tuner grew
+    assert grown & set(extra), sorted(extra)
