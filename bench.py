@@ -120,15 +120,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(workload: str, kernel: str = "k_chain"):
+def counter_traffic(workload: str, kernel: str = "k_chain", variant=None, folder=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of this
     workload (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the counter reads for a
-    copy of known size), or None when there is none or the kernels changed since it was taken."""
+    copy of known size), or None when there is none, the kernels changed since it was taken, or
+    it was taken on another chain variant than the one this run uses."""
     import glob
     import re
-    here = os.path.dirname(os.path.abspath(__file__))
+    folder = folder or os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
     src = kernel_source_hash()
-    for path in sorted(glob.glob(os.path.join(here, "profiles", "*counters*.md"))):
+    for path in sorted(glob.glob(os.path.join(folder, "*counters*.md"))):
         with open(path) as f:
             text = f.read()
         for block in re.findall(r"```json\n(.*?)```", text, flags=re.S):
@@ -139,6 +140,8 @@ def counter_traffic(workload: str, kernel: str = "k_chain"):
             if d.get("workload") != workload or d.get("kernel") != kernel:
                 continue
             if d.get("source_sha256") != src:
+                return None
+            if variant is not None and d.get("variant") not in (None, variant):
                 return None
             return (d["fetch_kib_per_dispatch"] * d["fetch_scale"] +
                     d["write_kib_per_dispatch"] * d["write_scale"]) * 1024.0
@@ -432,7 +435,7 @@ def measure(wl_name, steps, warmup, sim, synth, torch, dev, plain=True):
                       memoryless=wl.get("thresh") == "memoryless")
     alg_per_launch = alg / launches_per_step
     achieved = alg_per_launch / (launch_ms * 1e-3) / 1e9
-    traffic = counter_traffic(wl_name)
+    traffic = counter_traffic(wl_name, variant=chain_variant)
     # the whole step (every phase, sort passes excluded) against the same roof
     sb = step_bytes(npix, K, sel_per_step, ev_per_step, wl["method"],
                     memoryless=wl.get("thresh") == "memoryless")
