@@ -227,6 +227,8 @@ __global__ __launch_bounds__(256) void k_lk_points(const float* __restrict__ A,
 // ------------------------------------------------------------------------------------------
 constexpr int kLkWave = 64;
 constexpr int kLkMaxPerLane = 16;   // (2 * 15 + 1)^2 = 961 <= 64 * 16 positions
+// The window kernel is built for PL = 4, 8 and 16 positions per lane (radius <= 7, <= 11, <= 15),
+// so that a small window does not hold registers for the largest.
 
 // v[0] + v[1] + ... + v[n - 1], left to right from 0.
 __device__ __forceinline__ float ordered_sum(const float* v, int n) {
@@ -243,8 +245,9 @@ __device__ __forceinline__ float ordered_sum(const float* v, int n) {
     return acc;
 }
 
-// lk_point with the wave's lanes sharing the window; `buf` holds 3 N + 4 floats of LDS.  Every
-// lane returns the same result.
+// lk_point with the wave's lanes sharing the window (at most 64 PL positions); `buf` holds
+// 3 N + 4 floats of LDS.  Every lane returns the same result.
+template <int PL>
 __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L,
                               const LkParams& P, int px, int py, float* fx, float* fy,
                               float* buf) {
@@ -261,9 +264,9 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
         const Level J = level_of(B, L, l);
         const float sc = ldexpf(1.0f, -l);
         const float ux = (float)px * sc, uy = (float)py * sc;
-        float cix[kLkMaxPerLane], ciy[kLkMaxPerLane], ci0[kLkMaxPerLane];
+        float cix[PL], ciy[PL], ci0[PL];
 #pragma unroll
-        for (int j = 0; j < kLkMaxPerLane; ++j) {
+        for (int j = 0; j < PL; ++j) {
             const int q = lane + kLkWave * j;
             cix[j] = ciy[j] = ci0[j] = 0.0f;
             if (q < n) {
@@ -292,7 +295,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
         float vx = 0.0f, vy = 0.0f;
         for (int k = 0; k < P.iters; ++k) {
 #pragma unroll
-            for (int j = 0; j < kLkMaxPerLane; ++j) {
+            for (int j = 0; j < PL; ++j) {
                 const int q = lane + kLkWave * j;
                 if (q < n) {
                     const int dy = q / side - r, dx = q - (q / side) * side - r;
@@ -326,6 +329,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
 }
 
 // Block b (one wave): slot b of the active list (sparse) or pixel b.
+template <int PL>
 __global__ __launch_bounds__(kLkWave) void k_lk_window(LkWindowArgs a) {
     const int slot = blockIdx.x;
     int p;
@@ -340,8 +344,9 @@ __global__ __launch_bounds__(kLkWave) void k_lk_window(LkWindowArgs a) {
     for (int i = 0; i < a.K; ++i) {
         if (a.mask && !((a.mask[(int64_t)(i >> 5) * a.npix + p] >> (i & 31)) & 1u)) continue;
         float fx = 0.0f, fy = 0.0f;
-        lk_point_wave(a.pyr + (uint64_t)i * a.lay.total, a.pyr + (uint64_t)(i + 1) * a.lay.total,
-                      a.lay, a.P, px, py, &fx, &fy, smem);
+        lk_point_wave<PL>(a.pyr + (uint64_t)i * a.lay.total,
+                          a.pyr + (uint64_t)(i + 1) * a.lay.total, a.lay, a.P, px, py, &fx, &fy,
+                          smem);
         if (threadIdx.x == 0) {
             float* out = a.flow + (int64_t)i * 2 * a.npix + 2 * (int64_t)p;
             out[0] = fx;
@@ -382,9 +387,14 @@ hipError_t launch_lk_window(const LkWindowArgs& a, int max_slots, hipStream_t st
     if (max_slots <= 0) return hipSuccess;
     if (a.P.radius < 1 || (2 * a.P.radius + 1) * (2 * a.P.radius + 1) > kLkWave * kLkMaxPerLane)
         return hipErrorInvalidValue;
-    const int side = 2 * a.P.radius + 1;
-    const size_t lds = (size_t)(3 * side * side + 4) * sizeof(float);
-    hipLaunchKernelGGL(k_lk_window, dim3(max_slots), dim3(kLkWave), lds, stream, a);
+    const int side = 2 * a.P.radius + 1, n = side * side;
+    const size_t lds = (size_t)(3 * n + 4) * sizeof(float);
+    if (n <= kLkWave * 4)
+        hipLaunchKernelGGL(k_lk_window<4>, dim3(max_slots), dim3(kLkWave), lds, stream, a);
+    else if (n <= kLkWave * 8)
+        hipLaunchKernelGGL(k_lk_window<8>, dim3(max_slots), dim3(kLkWave), lds, stream, a);
+    else
+        hipLaunchKernelGGL(k_lk_window<16>, dim3(max_slots), dim3(kLkWave), lds, stream, a);
     return hipGetLastError();
 }
 

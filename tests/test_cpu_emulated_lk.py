@@ -80,6 +80,23 @@ def test_emulated_estimated_flow_simulation(emu_sim, method):
             np.testing.assert_array_equal(ref.view(np.uint32), oref.view(np.uint32))
 
 
+@pytest.mark.parametrize("radius", [8, 11, 12, 15])
+def test_emulated_estimated_flow_large_windows(emu_sim, radius):
+    """Window radii whose (2r + 1)^2 positions need 8 (r = 8 .. 11) and 16 (r = 12 .. 15)
+    positions per lane of the one-wave-per-point window pass, against the oracle."""
+    spec = synth.BlobVideoSpec(36, 30, 4, 30.0, 5, seed=40 + radius, motion="random",
+                               speed_max=4.0)
+    v = synth.blob_video(spec)
+    ok, oref = oracle_run(v.frames, None, v.t_us, method=sim.SPARSE, c_pos=0.1, c_neg=0.1,
+                          n_interp=3, flow_source=FLOW_LK, lk_levels=1, lk_radius=radius)
+    assert len(ok) > 20
+    keys, ref, _ = emu_run(emu_sim, v.frames, None, v.t_us, method=sim.SPARSE, c_pos=0.1,
+                           c_neg=0.1, n_interp=3, flow_source="lk",
+                           lk=dict(levels=1, radius=radius))
+    np.testing.assert_array_equal(keys, ok)
+    np.testing.assert_array_equal(ref.view(np.uint32), oref.view(np.uint32))
+
+
 def test_emulated_estimated_flow_in_a_batch_and_a_server(emu_sim):
     spec = synth.BlobVideoSpec(40, 32, 5, 30.0, 5, seed=6, motion="random", speed_max=4.0)
     v = synth.blob_video(spec)

@@ -32,6 +32,8 @@ MIN_OCCUPANCY = {
     # the scatter holds its 16 keys and their ranks in registers for the wave-private ranking
     "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 4,
     "_ZN5evsim8k_gatherEPKmmPKyPmPy": 8,
+    # Lucas-Kanade window pass, one wave per point, radius <= 7 (the default)
+    "_ZN5evsim12_GLOBAL__N_111k_lk_windowILi4EEEvNS_12LkWindowArgsE": 7,
 }
 
 

@@ -191,6 +191,25 @@ def test_estimated_flow_simulation(method, shape, frames):
         s.close()
 
 
+@pytest.mark.parametrize("radius", [11, 15])
+def test_estimated_flow_large_windows(radius):
+    """Lucas-Kanade windows of 23x23 and 31x31 positions (8 and 16 per lane of the window pass)
+    in a sparse simulation, bit for bit."""
+    from oracle.oracle import FLOW_LK
+    spec = synth.BlobVideoSpec(160, 120, 4, 30.0, 12, seed=radius, motion="random",
+                               speed_max=5.0)
+    v = synth.blob_video(spec)
+    ok, oref = oracle_keys(v.frames, None, v.t_us, method=sim.SPARSE, c_pos=0.15, c_neg=0.15,
+                           n_interp=10, flow_source=FLOW_LK, lk_levels=2, lk_radius=radius)
+    assert len(ok) > 100
+    s = sim.Stream(160, 120, method="sparse", c_pos=0.15, c_neg=0.15, n_interp=10,
+                   flow_source="lk", lk=dict(levels=2, radius=radius))
+    s.push_frames(v.frames, None, v.t_us)
+    np.testing.assert_array_equal(s.drain_keys(), ok)
+    np.testing.assert_array_equal(s.reference().view(np.uint32), oref.view(np.uint32))
+    s.close()
+
+
 def test_selection_statistics():
     """The device statistics of the sparse 1280x720 sequence: selected pixel-intervals equal the
     oracle's per-interval counts summed, active pixels those selected at least once."""
