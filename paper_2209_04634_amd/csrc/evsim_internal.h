@@ -67,7 +67,7 @@ struct SelectArgs {
     uint8_t* prev_out;          // receives the window's last frame
     uint32_t* mask;             // [kMaskWords][npix] selected-interval bits
     uint32_t* act_px;           // per block: its run of active pixels (kSelectPx slots)
-    uint32_t* counts;           // [block][kClasses] active pixels per length class
+    uint32_t* counts;           // [kClasses][block] active pixels per length class
     uint32_t* bsel;             // [block] selected pixel-intervals
     int npix, K;
     float m;
@@ -78,10 +78,10 @@ struct SelectArgs {
 // points cleared.  Two kernels: a one-block scan of the per-block counts, then the copy.
 struct OrderArgs {
     const uint32_t* act_px;     // the selection's runs
-    const uint32_t* counts;     // [block][kClasses]
+    const uint32_t* counts;     // [kClasses][block] (class-major: a class's counts are adjacent)
     const uint32_t* bsel;       // [block]
     int nblocks;
-    uint32_t* goff;             // [block][kClasses]: place of the block's class run in ord
+    uint32_t* goff;             // [kClasses][block]: place of the block's class run in ord
     unsigned int* n_total;      // length of ord
     unsigned long long* stats;  // += selected pixel-intervals, active pixels (one atomic each)
     uint32_t* ord;

@@ -574,7 +574,8 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
         uint32_t start = 0u;
         for (int c = kClasses - 1; c > tid; --c) start += class_field(bt, (uint32_t)c);
         s_cs[tid] = start;
-        a.counts[(size_t)bid * kClasses + tid] = class_field(bt, (uint32_t)tid);
+        const int nblocks = (a.npix + kSelectPx - 1) / kSelectPx;
+        a.counts[(size_t)tid * nblocks + bid] = class_field(bt, (uint32_t)tid);
     }
     if (tid == 0) a.bsel[bid] = s_nsel[0] + s_nsel[1] + s_nsel[2] + s_nsel[3];
     __syncthreads();
@@ -613,7 +614,7 @@ __device__ __forceinline__ void order_scan_block(const OrderArgs& a) {
         uint32_t v[16], w[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            v[u] = b + u < b1 ? a.counts[(size_t)(b + u) * kClasses + c] : 0u;
+            v[u] = b + u < b1 ? a.counts[(size_t)c * nb + b + u] : 0u;
             w[u] = (c == 0 && b + u < b1) ? a.bsel[b + u] : 0u;   // selected, counted once
         }
 #pragma unroll
@@ -635,10 +636,10 @@ __device__ __forceinline__ void order_scan_block(const OrderArgs& a) {
     for (int b = b0; b < b1; b += 16) {
         uint32_t v[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = b + u < b1 ? a.counts[(size_t)(b + u) * kClasses + c] : 0u;
+        for (int u = 0; u < 16; ++u) v[u] = b + u < b1 ? a.counts[(size_t)c * nb + b + u] : 0u;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            if (b + u < b1) a.goff[(size_t)(b + u) * kClasses + c] = pos;
+            if (b + u < b1) a.goff[(size_t)c * nb + b + u] = pos;
             pos += v[u];
         }
     }
@@ -659,11 +660,11 @@ __device__ __forceinline__ void order_copy_block(const OrderArgs& a, unsigned bi
         uint32_t pos = 0u;
         for (int c = kClasses - 1; c >= 0; --c) {
             s_start[c] = pos;
-            pos += a.counts[(size_t)bid * kClasses + c];
+            pos += a.counts[(size_t)c * a.nblocks + bid];
         }
         s_start[kClasses] = pos;
     }
-    if (tid < kClasses) s_goff[tid] = a.goff[(size_t)bid * kClasses + tid];
+    if (tid < kClasses) s_goff[tid] = a.goff[(size_t)tid * a.nblocks + bid];
     __syncthreads();
     const uint32_t n = s_start[kClasses];
     const uint32_t* run = a.act_px + (size_t)bid * kSelectPx;
