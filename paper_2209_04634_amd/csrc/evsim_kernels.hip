@@ -505,15 +505,15 @@ __device__ __forceinline__ void select_block(SelectArgs a, unsigned bid) {
             last = v;
         };
         if (VEC && cnt == 4) {
-            // eight frames' loads issued before any is used, so that they are in flight together
+            // sixteen frames' loads issued before any is used, so that they are in flight together
             int jj = 0;
-            for (; jj + 8 <= jend; jj += 8) {
-                uint32_t v[8];
+            for (; jj + 16 <= jend; jj += 16) {
+                uint32_t v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < 16; ++u)
                     v[u] = *(const uint32_t*)(Fw + (int64_t)(jj + u) * a.fstride);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) step(v[u], jj + u);
+                for (int u = 0; u < 16; ++u) step(v[u], jj + u);
             }
             for (; jj < jend; ++jj) step(*(const uint32_t*)(Fw + (int64_t)jj * a.fstride), jj);
         } else {
