@@ -15,7 +15,8 @@ kernel against the HBM roofline.  After the main measurement (and the CPU baseli
 process times the extra legs and the line carries them under "extra_legs" (or an "error" entry if
 the child fails or exceeds --legs-timeout; the main figures are unaffected): the memoryless,
 difference-frame and estimated-flow workloads, 64 mixed-resolution streams pushed as one batch
-per frame step against one push per stream, and a 10 s serving run with 256 cameras.
+per frame step against one push per stream (methods round-robin, then each method alone), and a
+60 s serving run with 256 cameras (Poisson arrivals, the server's worker stepping continuously).
 --no-legs skips them; --workload, --batched STREAMS and --serve SECONDS run single legs in
 process.
 """
@@ -152,11 +153,14 @@ BATCH_SHAPES = [(240, 180), (346, 260), (640, 480), (1920, 1080)]
 SERVE_SHAPES = [(346, 260), (640, 480), (1280, 720)]
 
 
-def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
-    """Streams of mixed resolution and method (the batched configuration's recipe, scaled to
-    `args.batched` streams): per frame step, one sim_push_batch of every stream's frame against
-    one push per stream.  Inputs resident in HBM; events drained into device buffers."""
-    methods = ["dense", "sparse", "basic"]
+def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30,
+                methods=("dense", "sparse", "basic")):
+    """Streams of mixed resolution (the batched configuration's recipe, scaled to `args.batched`
+    streams), methods round-robin over `methods`: per frame step, one sim_push_batch of every
+    stream's frame against one push per stream.  Inputs resident in HBM; events drained into
+    device buffers.  Also reports the timed batched run's per-frame-step host phases and device
+    time (sim_batch_times)."""
+    methods = list(methods)
     videos = {}
     for W, H in shapes:              # one device-resident video per resolution, shared
         v = synth.blob_video(synth.mixed_stream(W, H, seed=W + H, n_frames=n_frames))
@@ -165,7 +169,7 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
     streams, data = [], []
     for i in range(args.batched):
         W, H = shapes[i % len(shapes)]
-        method = methods[(i // len(shapes)) % 3]
+        method = methods[(i // len(shapes)) % len(methods)]
         c = [0.12, 0.15, 0.2, 0.25][(i // 12) % 4]
         fr, fl, t = videos[(W, H)]
         data.append((fr, None if method == "basic" else fl, t, W * H))
@@ -196,9 +200,16 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
     g0 = sim.batch_stats()
     for name, batched in (("batched", True), ("plain", False)):
         run(batched)                                   # warm-up: buffers reach their sizes
+        b0 = sim.batch_times()
         t0 = time.perf_counter()
         ev = run(batched)
         dt = time.perf_counter() - t0
+        if batched:
+            b1 = sim.batch_times()
+            steps = max(1, n_frames - 1)
+            res["batched_per_step_ms"] = {k: round((b1[k] - b0[k]) / steps, 3) for k in
+                                          ("inputs_ms", "plan_ms", "launch_ms", "wait_ms",
+                                           "finish_ms", "device_ms")}
         secs[name] = dt
         res[name] = {"mpix_frames_per_s": round(px_per_step * (n_frames - 1) / dt / 1e6, 1),
                      "ms_per_frame_step": round(1e3 * dt / (n_frames - 1), 3),
@@ -206,6 +217,7 @@ def batched_leg(args, sim, synth, torch, dev, shapes=BATCH_SHAPES, n_frames=30):
     for st in streams:
         st.close()
     res["streams"] = args.batched
+    res["methods"] = methods
     res["speedup"] = round(secs["plain"] / secs["batched"], 3)
     g1 = sim.batch_stats()
     res["graphs"] = {k: g1[k] - g0[k] for k in g1}   # recorded, launched, re-run windows
@@ -527,6 +539,9 @@ def legs_child(args):
         leg(name, lambda name=name: workload(name))
     args.batched = args.batched or 64
     leg("batched_vs_plain_streams", lambda: batched_leg(args, sim, synth, torch, dev))
+    for method in ("dense", "sparse", "basic"):
+        leg(f"batched_vs_plain_{method}",
+            lambda method=method: batched_leg(args, sim, synth, torch, dev, methods=(method,)))
     args.cameras = 256
     args.serve = args.serve or 60.0
     leg("serving", lambda: serve_leg(args, sim, synth, torch, dev))
