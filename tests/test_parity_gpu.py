@@ -106,6 +106,16 @@ def test_dense_346x260_full_sequence():
     assert n > 100000
 
 
+def test_dense_346x260_full_sequence_presized_buffer():
+    """The dense workload's whole 60-frame sequence (S = 11, C = 0.15) with the event buffer
+    sized for it up front, so that no window grows it: one window and frame-by-frame pushes.  The
+    regrowth path at this size stays covered by the overflow tests and the batched path."""
+    v = synth.blob_video(synth.dense_346x260())
+    n = assert_parity(v.frames, v.flows, v.t_us, modes=("window", "single"), method=sim.DENSE,
+                      c_pos=0.15, c_neg=0.15, n_interp=10, event_capacity=1 << 23)
+    assert n > 1000000
+
+
 def test_dense_346x260_per_frame_pushes():
     v = synth.blob_video(synth.dense_346x260(n_frames=8))
     assert_parity(v.frames, v.flows, v.t_us, modes=("single", "chunks"), method=sim.DENSE,
