@@ -151,12 +151,13 @@ def test_emulated_host_push_stages_one_window_at_a_time(emu_sim, method):
     assert not {300 * W * H, 299 * W * H, 299 * W * H * 2 * 4} & sizes, sorted(sizes)
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 70), (70, 1), (3, 129)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 70), (70, 1), (9, 2), (3, 129)])
 def test_emulated_degenerate_shapes(emu_sim, shape):
+    """One- and two-pixel-wide images: every bilinear footprint is clamped at a border."""
     H, W = shape
     rng = np.random.default_rng(H * 7 + W)
     frames, flows = synth.random_frames(rng, 3, H, W)
-    for method in (sim.BASIC, sim.DENSE, sim.SPARSE):
+    for method in (sim.BASIC, sim.DENSE, sim.SPARSE, sim.DIFFERENCE):
         check(emu_sim, frames, flows, np.array([0, 900, 2100]), method=method, n_interp=4)
 
 

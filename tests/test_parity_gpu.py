@@ -140,13 +140,13 @@ def test_subinterval_counts_ragged_image(S, method):
                   c_neg=0.25, n_interp=S - 1)
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (2, 129), (17, 256)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (40, 2), (2, 129), (17, 256)])
 def test_degenerate_shapes(shape):
     H, W = shape
     rng = np.random.default_rng(H * 1000 + W)
     frames, flows = synth.random_frames(rng, 3, H, W, flow_scale=2.0)
     t = np.array([5, 1005, 3000])
-    for method in (sim.BASIC, sim.DENSE, sim.SPARSE):
+    for method in (sim.BASIC, sim.DENSE, sim.SPARSE, sim.DIFFERENCE):
         assert_parity(frames, flows, t, method=method, n_interp=4)
 
 
