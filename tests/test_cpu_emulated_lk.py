@@ -8,7 +8,7 @@ import textwrap
 import numpy as np
 import pytest
 
-from oracle.oracle import OracleSim, lk_flow as oracle_lk_flow, FLOW_LK
+from oracle.oracle import lk_flow as oracle_lk_flow, FLOW_LK
 from paper_2209_04634_amd import sim, synth
 from test_cpu_emulated_kernels import (emu_build, emu_run, emu_sim, monkeypatch_module,  # noqa: F401
                                        oracle_run, HERE)

@@ -5,7 +5,6 @@ a swapped operand, a dropped term, an off-by-one tie or backlog rule.  Each muta
 from a modified copy of oracle/oracle.c into a temporary directory; the pin battery is then run
 against it and at least one pin must fail.
 """
-import os
 import subprocess
 
 import pytest
