@@ -13,6 +13,9 @@ constexpr int kMaxStash = 31;        // interior samples kept in LDS per pixel (
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // keys per sort block
+constexpr int kRadixBits = 9;        // sort digit width: 45-bit keys sort in five passes
+constexpr int kRadixDigits = 1 << kRadixBits;
+inline int sort_passes(int nbits) { return (nbits + kRadixBits - 1) / kRadixBits; }
 constexpr uint64_t kSentinel = ~0ull;
 constexpr int kMaskWords = 4;        // selected-interval bitmask words per pixel
 constexpr int kMaxWindow = 32 * kMaskWords;   // frame intervals per launch

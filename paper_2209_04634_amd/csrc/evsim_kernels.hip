@@ -956,15 +956,15 @@ __global__ __launch_bounds__(256) void k_moments(const uint32_t* __restrict__ co
 }
 
 // ------------------------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits, three kernels per pass.
+// Stable LSD radix sort, kRadixBits-bit digits, three kernels per pass.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void hist_block(const uint64_t* __restrict__ keys,
                                            const unsigned long long* n_dev, int shift,
                                            uint32_t* __restrict__ hist, int nblocks, unsigned bid) {
-    __shared__ uint32_t h[256];
+    __shared__ uint32_t h[kRadixDigits];
     const int tid = threadIdx.x;
     const uint64_t n = *n_dev;
-    h[tid] = 0;
+    for (int d = tid; d < kRadixDigits; d += kSortThreads) h[d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)bid * kSortTile;
     if (base < n) {
@@ -979,11 +979,11 @@ __device__ __forceinline__ void hist_block(const uint64_t* __restrict__ keys,
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
-            if (idx < n) atomicAdd(&h[(kv[j] >> shift) & 255u], 1u);
+            if (idx < n) atomicAdd(&h[(kv[j] >> shift) & (kRadixDigits - 1u)], 1u);
         }
     }
     __syncthreads();
-    hist[(size_t)tid * nblocks + bid] = h[tid];
+    for (int d = tid; d < kRadixDigits; d += kSortThreads) hist[(size_t)d * nblocks + bid] = h[d];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
@@ -1042,8 +1042,9 @@ __device__ __forceinline__ void scatter_block(
     const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv, unsigned bid) {
     static_assert(kSortThreads == 256 && kSortItems == 16, "four waves of 16 x 64 keys");
-    __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_wc[4][256];
+    static_assert(kRadixDigits == 2 * kSortThreads, "two digits per thread");
+    __shared__ uint32_t s_base[kRadixDigits];
+    __shared__ uint32_t s_wc[4][kRadixDigits];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t n = *n_dev;
@@ -1058,12 +1059,16 @@ __device__ __forceinline__ void scatter_block(
         kv[j] = in[idx < n ? idx : n - 1];
     }
     int tot;
-    const int dex = block_scan_256((int)totals[tid], s_wsum, &tot);
-    s_base[tid] = (uint32_t)dex + hist[(size_t)tid * nblocks + bid];
-    s_wc[0][tid] = 0u;
-    s_wc[1][tid] = 0u;
-    s_wc[2][tid] = 0u;
-    s_wc[3][tid] = 0u;
+    const int d0 = 2 * tid, d1 = 2 * tid + 1;   // this thread's digits
+    const uint32_t t0 = totals[d0];
+    const int dex = block_scan_256((int)(t0 + totals[d1]), s_wsum, &tot);
+    s_base[d0] = (uint32_t)dex + hist[(size_t)d0 * nblocks + bid];
+    s_base[d1] = (uint32_t)dex + t0 + hist[(size_t)d1 * nblocks + bid];
+#pragma unroll
+    for (int w2 = 0; w2 < 4; ++w2) {
+        s_wc[w2][d0] = 0u;
+        s_wc[w2][d1] = 0u;
+    }
     __syncthreads();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     uint32_t lrank[kSortItems];
@@ -1071,10 +1076,10 @@ __device__ __forceinline__ void scatter_block(
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         const bool valid = wbase + (uint64_t)j * 64 < n;
-        const uint32_t d = (uint32_t)(kv[j] >> shift) & 255u;
+        const uint32_t d = (uint32_t)(kv[j] >> shift) & (kRadixDigits - 1u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < kRadixBits; ++b) {
             const uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
@@ -1090,19 +1095,21 @@ __device__ __forceinline__ void scatter_block(
         if (leader) wc[d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit (thread tid): the counts of the waves before each wave, in place
-    {
-        const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid];
-        s_wc[0][tid] = 0u;
-        s_wc[1][tid] = c0;
-        s_wc[2][tid] = c0 + c1;
-        s_wc[3][tid] = c0 + c1 + c2;
+    // per digit (two per thread): the counts of the waves before each wave, in place
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int d = q ? d1 : d0;
+        const uint32_t c0 = s_wc[0][d], c1 = s_wc[1][d], c2 = s_wc[2][d];
+        s_wc[0][d] = 0u;
+        s_wc[1][d] = c0;
+        s_wc[2][d] = c0 + c1;
+        s_wc[3][d] = c0 + c1 + c2;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         if (wbase + (uint64_t)j * 64 < n) {
-            const uint32_t d = (uint32_t)(kv[j] >> shift) & 255u;
+            const uint32_t d = (uint32_t)(kv[j] >> shift) & (kRadixDigits - 1u);
             const uint64_t pos = (uint64_t)s_base[d] + wc[d] + lrank[j];
             if (!cv.enabled) {
                 out[pos] = kv[j];
@@ -1252,25 +1259,25 @@ hipError_t launch_copy_u8(const uint8_t* src, uint8_t* dst, int64_t n, hipStream
 
 size_t sort_hist_entries(uint64_t n_max) {
     const uint64_t nb = (n_max + kSortTile - 1) / kSortTile;
-    return (size_t)(nb ? nb : 1) * 256;
+    return (size_t)(nb ? nb : 1) * kRadixDigits;
 }
 
 hipError_t launch_sort(uint64_t* keys, uint64_t* alt, const unsigned long long* n,
                        uint64_t n_max, int nbits, uint32_t* hist, uint32_t* totals,
                        uint64_t* out, const ConvertArgs& cv, hipStream_t stream) {
     const int nblocks = (int)std::max<uint64_t>(1, (n_max + kSortTile - 1) / kSortTile);
-    const int passes = (nbits + 7) / 8;
+    const int passes = sort_passes(nbits);
     uint64_t* src = keys;
     uint64_t* dst = alt;
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = 8 * pass;
+        const int shift = kRadixBits * pass;
         const bool last = pass == passes - 1;
         ConvertArgs c = cv;
         if (!last) c.enabled = 0;
         hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, src, n,
                            shift, hist, nblocks);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, stream, hist,
-                           nblocks, totals);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits), dim3(kSortThreads), 0, stream,
+                           hist, nblocks, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, src,
                            last ? out : dst, n, shift, hist, totals, nblocks, c);
         uint64_t* t = src;
@@ -1423,15 +1430,15 @@ __global__ __launch_bounds__(kSortThreads) void k_batch_hist(const BatchEntry* _
     const int ei = batch_entry(start, n, blockIdx.x);
     const BatchEntry* e = entries + ei;
     const uint64_t* src = (pass & 1) ? e->sort_alt : e->gathered;
-    hist_block(src, e->counters + 2, 8 * pass, e->hist, e->sort_blocks,
+    hist_block(src, e->counters + 2, kRadixBits * pass, e->hist, e->sort_blocks,
                blockIdx.x - (unsigned)start[ei]);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_batch_rowscan(
     const BatchEntry* __restrict__ entries) {
-    const BatchEntry* e = entries + blockIdx.x / 256;
+    const BatchEntry* e = entries + blockIdx.x / kRadixDigits;
     if (e->sort_blocks == 0) return;
-    rowscan_block(e->hist, e->sort_blocks, e->totals, blockIdx.x % 256);
+    rowscan_block(e->hist, e->sort_blocks, e->totals, blockIdx.x % kRadixDigits);
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_batch_scatter(
@@ -1443,7 +1450,8 @@ __global__ __launch_bounds__(kSortThreads) void k_batch_scatter(
     uint64_t* dst = last ? e->out : ((pass & 1) ? e->gathered : e->sort_alt);
     ConvertArgs c = e->cv;
     if (!last) c.enabled = 0;
-    scatter_block(src, dst, e->counters + 2, 8 * pass, e->hist, e->totals, e->sort_blocks, c,
+    scatter_block(src, dst, e->counters + 2, kRadixBits * pass, e->hist, e->totals,
+                  e->sort_blocks, c,
                   blockIdx.x - (unsigned)start[ei]);
 }
 
@@ -1548,7 +1556,8 @@ hipError_t launch_batch_sort(const BatchEntry* e, const int* start, int n, int b
         const int last = pass == passes - 1;
         hipLaunchKernelGGL(k_batch_hist, dim3(blocks), dim3(kSortThreads), 0, stream, e, start, n,
                            pass);
-        hipLaunchKernelGGL(k_batch_rowscan, dim3(256 * n), dim3(kSortThreads), 0, stream, e);
+        hipLaunchKernelGGL(k_batch_rowscan, dim3(kRadixDigits * n), dim3(kSortThreads), 0,
+                           stream, e);
         hipLaunchKernelGGL(k_batch_scatter, dim3(blocks), dim3(kSortThreads), 0, stream, e, start,
                            n, pass, last);
     }

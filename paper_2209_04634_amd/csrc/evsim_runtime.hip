@@ -1119,7 +1119,7 @@ int fused_window(std::vector<FusedItem>& items) {
         const int m = b.chain.mode;
         chain_blocks[m][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
         max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
-        passes = std::max(passes, (f.nbits + 7) / 8);
+        passes = std::max(passes, sort_passes(f.nbits));
     }
     // chain-pass variant per thresholding mode: that of the entry with the most chain slots
     // (tuned now if its key is new: its selection and order pass run alone first)
@@ -1307,7 +1307,7 @@ int fused_window(std::vector<FusedItem>& items) {
             b.out = s->d_fifo + s->fifo_tail;
             b.sort_blocks = (int)std::max<uint64_t>(1, (n_total + kSortTile - 1) / kSortTile);
             blocks[e] = b.sort_blocks;
-            rpasses = std::max(rpasses, (f.nbits + 7) / 8);
+            rpasses = std::max(rpasses, sort_passes(f.nbits));
         }
         const int rt = fill_starts(hstart(kSort), blocks);
         BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
@@ -1533,7 +1533,7 @@ int sim_create(const sim_config* cfg, sim_stream** out) {
     ok = ok && dev_alloc(&s->d_arena, s->stripe_cap * kArenaStripes) == hipSuccess;
     ok = ok && dev_alloc(&s->d_reserve, (size_t)kArenaStripes * kCounterStride) == hipSuccess;
     ok = ok && dev_alloc(&s->d_stats, (size_t)kStatStripes * kCounterStride) == hipSuccess;
-    ok = ok && dev_alloc(&s->d_totals, 256) == hipSuccess;
+    ok = ok && dev_alloc(&s->d_totals, kRadixDigits) == hipSuccess;
     ok = ok && dev_alloc(&s->d_counters, 4) == hipSuccess;
     if (cfg->method == SIM_DIFFERENCE) {
         ok = ok && dev_alloc(&s->d_prev2[0], s->npix) == hipSuccess;
