@@ -958,13 +958,15 @@ __global__ __launch_bounds__(256) void k_moments(const uint32_t* __restrict__ co
 // ------------------------------------------------------------------------------------------
 // Stable LSD radix sort, kRadixBits-bit digits, three kernels per pass.
 // ------------------------------------------------------------------------------------------
+template <int BITS>
 __device__ __forceinline__ void hist_block(const uint64_t* __restrict__ keys,
                                            const unsigned long long* n_dev, int shift,
                                            uint32_t* __restrict__ hist, int nblocks, unsigned bid) {
-    __shared__ uint32_t h[kRadixDigits];
+    constexpr int D = 1 << BITS;
+    __shared__ uint32_t h[D];
     const int tid = threadIdx.x;
     const uint64_t n = *n_dev;
-    for (int d = tid; d < kRadixDigits; d += kSortThreads) h[d] = 0;
+    for (int d = tid; d < D; d += kSortThreads) h[d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)bid * kSortTile;
     if (base < n) {
@@ -979,19 +981,20 @@ __device__ __forceinline__ void hist_block(const uint64_t* __restrict__ keys,
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const uint64_t idx = base + (uint64_t)j * kSortThreads + tid;
-            if (idx < n) atomicAdd(&h[(kv[j] >> shift) & (kRadixDigits - 1u)], 1u);
+            if (idx < n) atomicAdd(&h[(kv[j] >> shift) & (D - 1u)], 1u);
         }
     }
     __syncthreads();
-    for (int d = tid; d < kRadixDigits; d += kSortThreads) hist[(size_t)d * nblocks + bid] = h[d];
+    for (int d = tid; d < D; d += kSortThreads) hist[(size_t)d * nblocks + bid] = h[d];
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                              const unsigned long long* n_dev,
                                                              int shift,
                                                              uint32_t* __restrict__ hist,
                                                              int nblocks) {
-    hist_block(keys, n_dev, shift, hist, nblocks, blockIdx.x);
+    hist_block<BITS>(keys, n_dev, shift, hist, nblocks, blockIdx.x);
 }
 
 // One block per digit: exclusive scan of that digit's per-block counts; row total to totals[d].
@@ -1037,14 +1040,17 @@ __device__ __forceinline__ uint64_t convert_key(uint64_t k, const ConvertArgs& c
 // rank among the wave's earlier keys, so no block barrier is needed until the quarters are
 // combined (the waves before w, per digit).  Stable: a key's place follows every key before it
 // in the tile with the same digit.
+template <int BITS>
 __device__ __forceinline__ void scatter_block(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
     const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv, unsigned bid) {
     static_assert(kSortThreads == 256 && kSortItems == 16, "four waves of 16 x 64 keys");
-    static_assert(kRadixDigits == 2 * kSortThreads, "two digits per thread");
-    __shared__ uint32_t s_base[kRadixDigits];
-    __shared__ uint32_t s_wc[4][kRadixDigits];
+    constexpr int D = 1 << BITS;
+    constexpr int PER = D / kSortThreads;   // digits per thread: 1 or 2
+    static_assert(PER == 1 || PER == 2, "8- or 9-bit digits");
+    __shared__ uint32_t s_base[D];
+    __shared__ uint32_t s_wc[4][D];
     __shared__ int s_wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint64_t n = *n_dev;
@@ -1059,15 +1065,22 @@ __device__ __forceinline__ void scatter_block(
         kv[j] = in[idx < n ? idx : n - 1];
     }
     int tot;
-    const int d0 = 2 * tid, d1 = 2 * tid + 1;   // this thread's digits
-    const uint32_t t0 = totals[d0];
-    const int dex = block_scan_256((int)(t0 + totals[d1]), s_wsum, &tot);
-    s_base[d0] = (uint32_t)dex + hist[(size_t)d0 * nblocks + bid];
-    s_base[d1] = (uint32_t)dex + t0 + hist[(size_t)d1 * nblocks + bid];
+    const int d0 = PER * tid;   // this thread's digits: d0 .. d0 + PER - 1
+    uint32_t tv[PER];
+    uint32_t tsum = 0u;
 #pragma unroll
-    for (int w2 = 0; w2 < 4; ++w2) {
-        s_wc[w2][d0] = 0u;
-        s_wc[w2][d1] = 0u;
+    for (int q = 0; q < PER; ++q) {
+        tv[q] = totals[d0 + q];
+        tsum += tv[q];
+    }
+    const int dex = block_scan_256((int)tsum, s_wsum, &tot);
+    uint32_t run = (uint32_t)dex;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        s_base[d0 + q] = run + hist[(size_t)(d0 + q) * nblocks + bid];
+        run += tv[q];
+#pragma unroll
+        for (int w2 = 0; w2 < 4; ++w2) s_wc[w2][d0 + q] = 0u;
     }
     __syncthreads();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
@@ -1076,10 +1089,10 @@ __device__ __forceinline__ void scatter_block(
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         const bool valid = wbase + (uint64_t)j * 64 < n;
-        const uint32_t d = (uint32_t)(kv[j] >> shift) & (kRadixDigits - 1u);
+        const uint32_t d = (uint32_t)(kv[j] >> shift) & (D - 1u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             const uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
@@ -1095,10 +1108,10 @@ __device__ __forceinline__ void scatter_block(
         if (leader) wc[d] = before + (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    // per digit (two per thread): the counts of the waves before each wave, in place
+    // per digit (PER per thread): the counts of the waves before each wave, in place
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int d = q ? d1 : d0;
+    for (int q = 0; q < PER; ++q) {
+        const int d = d0 + q;
         const uint32_t c0 = s_wc[0][d], c1 = s_wc[1][d], c2 = s_wc[2][d];
         s_wc[0][d] = 0u;
         s_wc[1][d] = c0;
@@ -1109,7 +1122,7 @@ __device__ __forceinline__ void scatter_block(
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         if (wbase + (uint64_t)j * 64 < n) {
-            const uint32_t d = (uint32_t)(kv[j] >> shift) & (kRadixDigits - 1u);
+            const uint32_t d = (uint32_t)(kv[j] >> shift) & (D - 1u);
             const uint64_t pos = (uint64_t)s_base[d] + wc[d] + lrank[j];
             if (!cv.enabled) {
                 out[pos] = kv[j];
@@ -1120,11 +1133,12 @@ __device__ __forceinline__ void scatter_block(
     }
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
     const unsigned long long* n_dev, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ totals, int nblocks, ConvertArgs cv) {
-    scatter_block(in, out, n_dev, shift, hist, totals, nblocks, cv, blockIdx.x);
+    scatter_block<BITS>(in, out, n_dev, shift, hist, totals, nblocks, cv, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1266,20 +1280,30 @@ hipError_t launch_sort(uint64_t* keys, uint64_t* alt, const unsigned long long* 
                        uint64_t n_max, int nbits, uint32_t* hist, uint32_t* totals,
                        uint64_t* out, const ConvertArgs& cv, hipStream_t stream) {
     const int nblocks = (int)std::max<uint64_t>(1, (n_max + kSortTile - 1) / kSortTile);
+    const int bits = sort_radix_bits(nbits);
     const int passes = sort_passes(nbits);
     uint64_t* src = keys;
     uint64_t* dst = alt;
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = kRadixBits * pass;
+        const int shift = bits * pass;
         const bool last = pass == passes - 1;
         ConvertArgs c = cv;
         if (!last) c.enabled = 0;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, src, n,
-                           shift, hist, nblocks);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadixDigits), dim3(kSortThreads), 0, stream,
-                           hist, nblocks, totals);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, src,
-                           last ? out : dst, n, shift, hist, totals, nblocks, c);
+        if (bits == 9) {
+            hipLaunchKernelGGL(k_radix_hist<9>, dim3(nblocks), dim3(kSortThreads), 0, stream, src,
+                               n, shift, hist, nblocks);
+            hipLaunchKernelGGL(k_radix_rowscan, dim3(512), dim3(kSortThreads), 0, stream, hist,
+                               nblocks, totals);
+            hipLaunchKernelGGL(k_radix_scatter<9>, dim3(nblocks), dim3(kSortThreads), 0, stream,
+                               src, last ? out : dst, n, shift, hist, totals, nblocks, c);
+        } else {
+            hipLaunchKernelGGL(k_radix_hist<8>, dim3(nblocks), dim3(kSortThreads), 0, stream, src,
+                               n, shift, hist, nblocks);
+            hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kSortThreads), 0, stream, hist,
+                               nblocks, totals);
+            hipLaunchKernelGGL(k_radix_scatter<8>, dim3(nblocks), dim3(kSortThreads), 0, stream,
+                               src, last ? out : dst, n, shift, hist, totals, nblocks, c);
+        }
         uint64_t* t = src;
         src = dst;
         dst = t;
@@ -1424,23 +1448,26 @@ __global__ void k_batch_counts(const BatchEntry* __restrict__ entries, int n,
 
 // One pass of every entry's sort: pass p reads the gathered keys (p even) or the ping-pong
 // buffer (p odd) and writes the other one, or the FIFO on the last pass.
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_batch_hist(const BatchEntry* __restrict__ entries,
                                                              const int* __restrict__ start, int n,
                                                              int pass) {
     const int ei = batch_entry(start, n, blockIdx.x);
     const BatchEntry* e = entries + ei;
     const uint64_t* src = (pass & 1) ? e->sort_alt : e->gathered;
-    hist_block(src, e->counters + 2, kRadixBits * pass, e->hist, e->sort_blocks,
-               blockIdx.x - (unsigned)start[ei]);
+    hist_block<BITS>(src, e->counters + 2, BITS * pass, e->hist, e->sort_blocks,
+                     blockIdx.x - (unsigned)start[ei]);
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_batch_rowscan(
     const BatchEntry* __restrict__ entries) {
-    const BatchEntry* e = entries + blockIdx.x / kRadixDigits;
+    const BatchEntry* e = entries + blockIdx.x / (1 << BITS);
     if (e->sort_blocks == 0) return;
-    rowscan_block(e->hist, e->sort_blocks, e->totals, blockIdx.x % kRadixDigits);
+    rowscan_block(e->hist, e->sort_blocks, e->totals, blockIdx.x % (1 << BITS));
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_batch_scatter(
     const BatchEntry* __restrict__ entries, const int* __restrict__ start, int n, int pass,
     int last) {
@@ -1450,8 +1477,8 @@ __global__ __launch_bounds__(kSortThreads) void k_batch_scatter(
     uint64_t* dst = last ? e->out : ((pass & 1) ? e->gathered : e->sort_alt);
     ConvertArgs c = e->cv;
     if (!last) c.enabled = 0;
-    scatter_block(src, dst, e->counters + 2, kRadixBits * pass, e->hist, e->totals,
-                  e->sort_blocks, c,
+    scatter_block<BITS>(src, dst, e->counters + 2, BITS * pass, e->hist, e->totals,
+                        e->sort_blocks, c,
                   blockIdx.x - (unsigned)start[ei]);
 }
 
@@ -1549,18 +1576,27 @@ hipError_t launch_batch_counts(const BatchEntry* e, int n, unsigned long long* o
     return hipGetLastError();
 }
 
-hipError_t launch_batch_sort(const BatchEntry* e, const int* start, int n, int blocks, int passes,
-                             hipStream_t stream) {
-    if (n <= 0 || blocks <= 0) return hipSuccess;
+template <int BITS>
+void launch_batch_sort_bits(const BatchEntry* e, const int* start, int n, int blocks, int passes,
+                            hipStream_t stream) {
     for (int pass = 0; pass < passes; ++pass) {
         const int last = pass == passes - 1;
-        hipLaunchKernelGGL(k_batch_hist, dim3(blocks), dim3(kSortThreads), 0, stream, e, start, n,
-                           pass);
-        hipLaunchKernelGGL(k_batch_rowscan, dim3(kRadixDigits * n), dim3(kSortThreads), 0,
+        hipLaunchKernelGGL(k_batch_hist<BITS>, dim3(blocks), dim3(kSortThreads), 0, stream, e,
+                           start, n, pass);
+        hipLaunchKernelGGL(k_batch_rowscan<BITS>, dim3((1 << BITS) * n), dim3(kSortThreads), 0,
                            stream, e);
-        hipLaunchKernelGGL(k_batch_scatter, dim3(blocks), dim3(kSortThreads), 0, stream, e, start,
-                           n, pass, last);
+        hipLaunchKernelGGL(k_batch_scatter<BITS>, dim3(blocks), dim3(kSortThreads), 0, stream, e,
+                           start, n, pass, last);
     }
+}
+
+hipError_t launch_batch_sort(const BatchEntry* e, const int* start, int n, int blocks, int passes,
+                             int radix_bits, hipStream_t stream) {
+    if (n <= 0 || blocks <= 0) return hipSuccess;
+    if (radix_bits == 9)
+        launch_batch_sort_bits<9>(e, start, n, blocks, passes, stream);
+    else
+        launch_batch_sort_bits<8>(e, start, n, blocks, passes, stream);
     return hipGetLastError();
 }
 

@@ -1051,7 +1051,7 @@ int fused_window(std::vector<FusedItem>& items) {
     std::vector<uint64_t> sort_cap(n);
     for (int m = 0; m < 3; ++m) chain_blocks[m].assign(n, 0);
     int max_stash[3] = {0, 0, 0};
-    int passes = 1;
+    int max_nbits = 1;
     bool capturable = true;
     for (int e = 0; e < n; ++e) {
         FusedItem& f = items[e];
@@ -1119,7 +1119,7 @@ int fused_window(std::vector<FusedItem>& items) {
         const int m = b.chain.mode;
         chain_blocks[m][e] = (chain_slots(s) + kSimThreads - 1) / kSimThreads;
         max_stash[m] = std::max(max_stash[m], (s->S - 1 <= kMaxStash) ? s->S - 1 : 0);
-        passes = std::max(passes, sort_passes(f.nbits));
+        max_nbits = std::max(max_nbits, f.nbits);
     }
     // chain-pass variant per thresholding mode: that of the entry with the most chain slots
     // (tuned now if its key is new: its selection and order pass run alone first)
@@ -1157,6 +1157,10 @@ int fused_window(std::vector<FusedItem>& items) {
     for (int m = 0; m < 3; ++m) chain_total[m] = fill_starts(hstart(kChain0 + m), chain_blocks[m]);
     const int gather_total = fill_starts(hstart(kGather), gather_blocks);
     const int sort_total = fill_starts(hstart(kSort), sort_blocks);
+    // every entry's sort takes the batch's digit width and pass count (an entry with fewer key
+    // bits takes the extra passes harmlessly)
+    const int radix_bits = sort_radix_bits(max_nbits);
+    const int passes = sort_passes(max_nbits);
     hipStream_t st = c.stream;
     const size_t head = ent_bytes + starts_bytes;
 
@@ -1174,7 +1178,8 @@ int fused_window(std::vector<FusedItem>& items) {
             r = launch_batch_chain(de, dstart(kChain0 + m), n, chain_total[m], m, max_stash[m],
                                    variant[m], st);
         if (r == hipSuccess) r = launch_batch_gather(de, dstart(kGather), n, gather_total, st);
-        if (r == hipSuccess) r = launch_batch_sort(de, dstart(kSort), n, sort_total, passes, st);
+        if (r == hipSuccess)
+            r = launch_batch_sort(de, dstart(kSort), n, sort_total, passes, radix_bits, st);
         if (r == hipSuccess) r = launch_batch_status(de, n, c.d_out, st);
         if (r == hipSuccess)
             r = hipMemcpyAsync(c.h_out, c.d_out, 3 * (size_t)n * sizeof(unsigned long long),
@@ -1187,9 +1192,10 @@ int fused_window(std::vector<FusedItem>& items) {
         BatchShape key;
         key.n = n;
         key.tab = tab;
-        key.totals = {sel_total, order_total, chain_total[0], chain_total[1], chain_total[2],
-                      gather_total, sort_total, passes, max_stash[0], max_stash[1],
-                      max_stash[2], variant[0], variant[1], variant[2]};
+        key.totals = {sel_total,    order_total,   chain_total[0],          chain_total[1],
+                      chain_total[2], gather_total, sort_total, passes * 16 + radix_bits,
+                      max_stash[0], max_stash[1],  max_stash[2],  variant[0],
+                      variant[1],   variant[2]};
         key.blob = c.d_blob;
         key.out = c.d_out;
         if (!(c.graph_exec && c.graph_key == key)) {
@@ -1291,7 +1297,7 @@ int fused_window(std::vector<FusedItem>& items) {
                                  hipMemcpyDeviceToHost, st));
         BATCH_TRY(hipStreamSynchronize(st));
         std::fill(blocks.begin(), blocks.end(), 0);
-        int rpasses = 1;
+        int rnbits = 1;
         for (int e : redo) {
             FusedItem& f = items[e];
             sim_stream* s = f.s;
@@ -1307,11 +1313,12 @@ int fused_window(std::vector<FusedItem>& items) {
             b.out = s->d_fifo + s->fifo_tail;
             b.sort_blocks = (int)std::max<uint64_t>(1, (n_total + kSortTile - 1) / kSortTile);
             blocks[e] = b.sort_blocks;
-            rpasses = std::max(rpasses, sort_passes(f.nbits));
+            rnbits = std::max(rnbits, f.nbits);
         }
         const int rt = fill_starts(hstart(kSort), blocks);
         BATCH_TRY(hipMemcpyAsync(c.d_blob, c.h_blob, head, hipMemcpyHostToDevice, st));
-        BATCH_TRY(launch_batch_sort(de, dstart(kSort), n, rt, rpasses, st));
+        BATCH_TRY(launch_batch_sort(de, dstart(kSort), n, rt, sort_passes(rnbits),
+                                    sort_radix_bits(rnbits), st));
         BATCH_TRY(hipStreamSynchronize(st));
         c.redo_windows += redo.size();
     }

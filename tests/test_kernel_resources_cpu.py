@@ -28,9 +28,12 @@ MIN_OCCUPANCY = {
     "_ZN5evsim7k_chainILi2ELi2EEEvNS_9ChainArgsE": 3,
     # selection pass (a 1280x720 window launches 3.5 waves per SIMD: six per SIMD is ample)
     "_ZN5evsim8k_selectILb1EEEvNS_10SelectArgsE": 6,
-    "_ZN5evsim12k_radix_histEPKmPKyiPji": 8,
+    # radix sort with 8- and 9-bit digits (the width that needs fewer passes is used)
+    "_ZN5evsim12k_radix_histILi8EEEvPKmPKyiPji": 8,
+    "_ZN5evsim12k_radix_histILi9EEEvPKmPKyiPji": 8,
     # the scatter holds its 16 keys and their ranks in registers for the wave-private ranking
-    "_ZN5evsim15k_radix_scatterEPKmPmPKyiPKjS6_iNS_11ConvertArgsE": 4,
+    "_ZN5evsim15k_radix_scatterILi8EEEvPKmPmPKyiPKjS7_iNS_11ConvertArgsE": 4,
+    "_ZN5evsim15k_radix_scatterILi9EEEvPKmPmPKyiPKjS7_iNS_11ConvertArgsE": 4,
     "_ZN5evsim8k_gatherEPKmmPKyPmPy": 8,
     # Lucas-Kanade window pass, one wave per point, radius <= 7 (the default)
     "_ZN5evsim12_GLOBAL__N_111k_lk_windowILi4EEEvNS_12LkWindowArgsE": 7,
