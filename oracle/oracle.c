@@ -42,7 +42,8 @@
  *   memoryless; interpolated difference frames are not rescaled (the paper's larger thresholds
  *   for this method, Table I, fit unscaled frames).  Accumulated frame: counts per pixel and
  *   polarity over a half-open time window.  Events/(pixel s): mean and population standard
- *   deviation over all pixels of the per-pixel count divided by the window length.
+ *   deviation over all pixels of the per-pixel count divided by the window length.  Lucas-Kanade
+ *   window sums: 64 strided partial sums combined pairwise, in one fixed order (window_sum).
  *
  * Parity is pinned (tests/test_oracle_*.py) by: the exhaustive table check against an exact
  * logarithm, zero-event invariants, the closed-form per-pixel count floor(|dL|/C) of the basic
@@ -278,25 +279,47 @@ static float bil_tap(const or_img* im, int kind, or_tap t) {
     return t.gy * top + t.fy * bot;
 }
 
+/* A window sum in a fixed order (the paper does not fix one; this order is exact to reproduce
+ * with 64 parallel partial sums): position q of the window, row-major, goes to partial q mod 64
+ * in order of q, each partial starting from 0; then partial l takes partial l + 32, l + 16, ...,
+ * l + 1 in turn (pairwise, 6 levels); the sum is partial 0.  One rounding per addition. */
+#define OR_WINDOW_MAX 961   /* (2 * 15 + 1)^2 */
+static float window_sum(const float* v, int n) {
+    float part[64];
+    for (int l = 0; l < 64; ++l) part[l] = 0.0f;
+    for (int q = 0; q < n; ++q) part[q % 64] += v[q];
+    for (int off = 32; off >= 1; off /= 2)
+        for (int l = 0; l < off; ++l) part[l] = part[l] + part[l + off];
+    return part[0];
+}
+
 /* Flow of integer pixel (px, py) from pyramid I to pyramid J; returns 1 if valid. */
 static int lk_point(const or_img* I, const or_img* J, const oracle_lk* P, int px, int py,
                     float* fx, float* fy) {
-    const int r = P->radius;
-    const float N = (float)((2 * r + 1) * (2 * r + 1));
+    const int r = P->radius, side = 2 * r + 1, n = side * side;
+    const float N = (float)n;
+    /* per window position q = (dy + r) side + (dx + r): the products whose window sums form the
+     * normal matrix and the right-hand side */
+    float pxx[OR_WINDOW_MAX], pxy[OR_WINDOW_MAX], pyy[OR_WINDOW_MAX];
+    float pbx[OR_WINDOW_MAX], pby[OR_WINDOW_MAX];
     float gx = 0.0f, gy = 0.0f;
     for (int l = P->levels; l >= 0; --l) {
         const float sc = ldexpf(1.0f, -l);
         const float ux = (float)px * sc, uy = (float)py * sc;
-        float Gxx = 0.0f, Gxy = 0.0f, Gyy = 0.0f;
+        memset(pxx, 0, sizeof pxx);
+        memset(pxy, 0, sizeof pxy);
+        memset(pyy, 0, sizeof pyy);
         for (int dy = -r; dy <= r; ++dy) {
             for (int dx = -r; dx <= r; ++dx) {
                 const or_tap t = tap_at(I[l].W, I[l].H, ux + (float)dx, uy + (float)dy);
                 const float ix = bil_tap(&I[l], 1, t), iy = bil_tap(&I[l], 2, t);
-                Gxx += ix * ix;
-                Gxy += ix * iy;
-                Gyy += iy * iy;
+                const int q = (dy + r) * side + (dx + r);
+                pxx[q] = ix * ix;
+                pxy[q] = ix * iy;
+                pyy[q] = iy * iy;
             }
         }
+        const float Gxx = window_sum(pxx, n), Gxy = window_sum(pxy, n), Gyy = window_sum(pyy, n);
         const float trace = Gxx + Gyy;
         const float det = Gxx * Gyy - Gxy * Gxy;
         if (!(trace >= P->min_trace * N) || !(det >= P->min_ratio * trace * trace)) {
@@ -306,7 +329,8 @@ static int lk_point(const or_img* I, const or_img* J, const oracle_lk* P, int px
         }
         float vx = 0.0f, vy = 0.0f;
         for (int k = 0; k < P->iters; ++k) {
-            float bx = 0.0f, by = 0.0f;
+            memset(pbx, 0, sizeof pbx);
+            memset(pby, 0, sizeof pby);
             for (int dy = -r; dy <= r; ++dy) {
                 for (int dx = -r; dx <= r; ++dx) {
                     const float x = ux + (float)dx, y = uy + (float)dy;
@@ -315,10 +339,12 @@ static int lk_point(const or_img* I, const or_img* J, const oracle_lk* P, int px
                     const float i0 = bil_tap(&I[l], 0, t);
                     const or_tap u = tap_at(J[l].W, J[l].H, x + (gx + vx), y + (gy + vy));
                     const float d = i0 - bil_tap(&J[l], 0, u);
-                    bx += d * ix;
-                    by += d * iy;
+                    const int q = (dy + r) * side + (dx + r);
+                    pbx[q] = d * ix;
+                    pby[q] = d * iy;
                 }
             }
+            const float bx = window_sum(pbx, n), by = window_sum(pby, n);
             const float ex = (Gyy * bx - Gxy * by) / det;
             const float ey = (Gxx * by - Gxy * bx) / det;
             vx += ex;

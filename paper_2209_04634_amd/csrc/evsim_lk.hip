@@ -12,7 +12,10 @@
 //   next level, flow = g + v at level 0.
 // Every value of the pyramid and of the gradients is exact in fp32 (dyadic with at most 24
 // significant bits for <= 4 levels of 8-bit input), and every other operation is one fp32
-// operation with one rounding in the order written (-ffp-contract=off).
+// operation with one rounding in the order written (-ffp-contract=off).  Each window sum is taken
+// in one fixed order: position q = (dy + r)(2r + 1) + (dx + r) goes to partial q mod 64, in order
+// of q from 0, and the 64 partials combine pairwise (partial l takes l + 32, then l + 16, ..., l + 1).
+// That is one wave's lanes each summing their own positions, then a six-step shuffle tree.
 #include "evsim_internal.h"
 
 #include <algorithm>
@@ -37,8 +40,6 @@ PyrLayout pyr_layout(int W, int H, int levels) {
     L.total = off;
     return L;
 }
-
-extern __shared__ float smem[];   // dynamic LDS of the window kernel
 
 namespace {
 
@@ -99,66 +100,6 @@ __device__ __forceinline__ float bil_tap(const Level& T, const Tap& t) {
     return t.gy * top + t.fy * bot;
 }
 
-// Flow of integer pixel (px, py) from pyramid A to pyramid B; returns true if valid.
-__device__ bool lk_point(const float* A, const float* B, const PyrLayout& L, const LkParams& P,
-                         int px, int py, float* fx, float* fy) {
-    const int r = P.radius;
-    const float N = (float)((2 * r + 1) * (2 * r + 1));
-    float gx = 0.0f, gy = 0.0f;
-    for (int l = P.levels; l >= 0; --l) {
-        const Level I = level_of(A, L, l);
-        const Level J = level_of(B, L, l);
-        const float sc = ldexpf(1.0f, -l);
-        const float ux = (float)px * sc, uy = (float)py * sc;
-        float Gxx = 0.0f, Gxy = 0.0f, Gyy = 0.0f;
-        for (int dy = -r; dy <= r; ++dy) {
-            for (int dx = -r; dx <= r; ++dx) {
-                const Tap t = tap_at(I, ux + (float)dx, uy + (float)dy);
-                const float ix = bil_tap<1>(I, t), iy = bil_tap<2>(I, t);
-                Gxx += ix * ix;
-                Gxy += ix * iy;
-                Gyy += iy * iy;
-            }
-        }
-        const float trace = Gxx + Gyy;
-        const float det = Gxx * Gyy - Gxy * Gxy;
-        if (!(trace >= P.min_trace * N) || !(det >= P.min_ratio * trace * trace)) {
-            *fx = 0.0f;
-            *fy = 0.0f;
-            return false;
-        }
-        float vx = 0.0f, vy = 0.0f;
-        for (int k = 0; k < P.iters; ++k) {
-            float bx = 0.0f, by = 0.0f;
-            for (int dy = -r; dy <= r; ++dy) {
-                for (int dx = -r; dx <= r; ++dx) {
-                    const float x = ux + (float)dx, y = uy + (float)dy;
-                    const Tap t = tap_at(I, x, y);
-                    const float ix = bil_tap<1>(I, t), iy = bil_tap<2>(I, t);
-                    const float i0 = bil_tap<0>(I, t);
-                    const Tap u = tap_at(J, x + (gx + vx), y + (gy + vy));
-                    const float d = i0 - bil_tap<0>(J, u);
-                    bx += d * ix;
-                    by += d * iy;
-                }
-            }
-            const float ex = (Gyy * bx - Gxy * by) / det;
-            const float ey = (Gxx * by - Gxy * bx) / det;
-            vx += ex;
-            vy += ey;
-            if (ex * ex + ey * ey < P.eps) break;
-        }
-        if (l > 0) {
-            gx = 2.0f * (gx + vx);
-            gy = 2.0f * (gy + vy);
-        } else {
-            *fx = gx + vx;
-            *fy = gy + vy;
-        }
-    }
-    return true;
-}
-
 // Level 0 of every frame: intensity as float.
 __global__ __launch_bounds__(256) void k_pyr_base(const uint8_t* __restrict__ first,
                                                   const uint8_t* __restrict__ rest,
@@ -198,66 +139,34 @@ __global__ __launch_bounds__(256) void k_pyr_down(PyrLayout L, int l, int n,
     }
 }
 
-__global__ __launch_bounds__(256) void k_lk_points(const float* __restrict__ A,
-                                                   const float* __restrict__ B, PyrLayout L,
-                                                   LkParams P, const uint32_t* __restrict__ pts,
-                                                   uint64_t n, float* __restrict__ flow,
-                                                   uint8_t* __restrict__ valid) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t p = pts[j];
-    const uint32_t W = (uint32_t)L.w[0];
-    // an index outside the image is invalid (flow 0) rather than read out of bounds
-    const bool inside = (uint64_t)p < (uint64_t)W * (uint64_t)L.h[0];
-    const int py = inside ? (int)(p / W) : 0, px = inside ? (int)(p - (uint32_t)py * W) : 0;
-    float fx = 0.0f, fy = 0.0f;
-    const bool ok = inside && lk_point(A, B, L, P, px, py, &fx, &fy);
-    flow[2 * j] = fx;
-    flow[2 * j + 1] = fy;
-    if (valid) valid[j] = ok ? 1 : 0;
-}
-
 // ------------------------------------------------------------------------------------------
-// One wave per point (the simulation's window pass).  The lanes share the window's positions
-// (position q = (dy + r) (2r + 1) + (dx + r), lane q mod 64): per level each lane samples the
-// first frame's intensity and gradients at its positions once and keeps them in registers for
-// every iteration, so an iteration samples only the second frame.  The sums run in the order of
-// the per-point loop above: the lanes write their positions' products to LDS and one lane per sum
-// adds them in position order, one rounding per addition, so the flow is bit-identical.
+// One wave per point.  The lanes share the window's positions (position q, lane q mod 64, PL
+// positions per lane): per level each lane samples the first frame's intensity and gradients at
+// its positions once and keeps them in registers for every iteration, so an iteration samples
+// only the second frame.  Each lane adds its positions' products in order of q, and the wave
+// combines the 64 partials pairwise (wave_window_sum): the order the file header fixes.
 // ------------------------------------------------------------------------------------------
 constexpr int kLkWave = 64;
 constexpr int kLkMaxPerLane = 16;   // (2 * 15 + 1)^2 = 961 <= 64 * 16 positions
-// The window kernel is built for PL = 4, 8 and 16 positions per lane (radius <= 7, <= 11, <= 15),
-// so that a small window does not hold registers for the largest.
+// The kernels are built for PL = 4, 8 and 16 positions per lane (radius <= 7, <= 11, <= 15), so
+// that a small window does not hold registers for the largest.
 
-// v[0] + v[1] + ... + v[n - 1], left to right from 0.
-__device__ __forceinline__ float ordered_sum(const float* v, int n) {
-    float acc = 0.0f;
-    int i = 0;
-    for (; i + 8 <= n; i += 8) {
-        float t[8];
+// Lane l's partial plus lane l + 32's, then l + 16's, ..., l + 1's; the total (lane 0's) to every
+// lane.  Lanes at or above 64 - off read their own value at that step and are not used after it.
+__device__ __forceinline__ float wave_window_sum(float part) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = v[i + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += t[u];
-    }
-    for (; i < n; ++i) acc += v[i];
-    return acc;
+    for (int off = 32; off >= 1; off >>= 1) part = part + __shfl_down(part, off, 64);
+    return __shfl(part, 0, 64);
 }
 
-// lk_point with the wave's lanes sharing the window (at most 64 PL positions); `buf` holds
-// 3 N + 4 floats of LDS.  Every lane returns the same result.
+// Flow of integer pixel (px, py) from pyramid A to pyramid B; every lane returns the same result
+// (true if valid).
 template <int PL>
 __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L,
-                              const LkParams& P, int px, int py, float* fx, float* fy,
-                              float* buf) {
-    const int lane = threadIdx.x;
+                              const LkParams& P, int px, int py, float* fx, float* fy) {
+    const int lane = threadIdx.x & 63;
     const int r = P.radius, side = 2 * r + 1, n = side * side;
     const float N = (float)n;
-    float* p0 = buf;
-    float* p1 = buf + n;
-    float* p2 = buf + 2 * n;
-    float* res = buf + 3 * n;
     float gx = 0.0f, gy = 0.0f;
     for (int l = P.levels; l >= 0; --l) {
         const Level I = level_of(A, L, l);
@@ -265,6 +174,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
         const float sc = ldexpf(1.0f, -l);
         const float ux = (float)px * sc, uy = (float)py * sc;
         float cix[PL], ciy[PL], ci0[PL];
+        float sxx = 0.0f, sxy = 0.0f, syy = 0.0f;
 #pragma unroll
         for (int j = 0; j < PL; ++j) {
             const int q = lane + kLkWave * j;
@@ -275,16 +185,13 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
                 cix[j] = bil_tap<1>(I, t);
                 ciy[j] = bil_tap<2>(I, t);
                 ci0[j] = bil_tap<0>(I, t);
-                p0[q] = cix[j] * cix[j];
-                p1[q] = cix[j] * ciy[j];
-                p2[q] = ciy[j] * ciy[j];
+                sxx += cix[j] * cix[j];
+                sxy += cix[j] * ciy[j];
+                syy += ciy[j] * ciy[j];
             }
         }
-        __syncthreads();
-        if (lane < 3) res[lane] = ordered_sum(lane == 0 ? p0 : (lane == 1 ? p1 : p2), n);
-        __syncthreads();
-        const float Gxx = res[0], Gxy = res[1], Gyy = res[2];
-        __syncthreads();   // the sums are read before the buffers are rewritten
+        const float Gxx = wave_window_sum(sxx), Gxy = wave_window_sum(sxy),
+                    Gyy = wave_window_sum(syy);
         const float trace = Gxx + Gyy;
         const float det = Gxx * Gyy - Gxy * Gxy;
         if (!(trace >= P.min_trace * N) || !(det >= P.min_ratio * trace * trace)) {
@@ -294,6 +201,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
         }
         float vx = 0.0f, vy = 0.0f;
         for (int k = 0; k < P.iters; ++k) {
+            float sbx = 0.0f, sby = 0.0f;
 #pragma unroll
             for (int j = 0; j < PL; ++j) {
                 const int q = lane + kLkWave * j;
@@ -302,15 +210,11 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
                     const float x = ux + (float)dx, y = uy + (float)dy;
                     const Tap u = tap_at(J, x + (gx + vx), y + (gy + vy));
                     const float d = ci0[j] - bil_tap<0>(J, u);
-                    p0[q] = d * cix[j];
-                    p1[q] = d * ciy[j];
+                    sbx += d * cix[j];
+                    sby += d * ciy[j];
                 }
             }
-            __syncthreads();
-            if (lane < 2) res[lane] = ordered_sum(lane == 0 ? p0 : p1, n);
-            __syncthreads();
-            const float bx = res[0], by = res[1];
-            __syncthreads();
+            const float bx = wave_window_sum(sbx), by = wave_window_sum(sby);
             const float ex = (Gyy * bx - Gxy * by) / det;
             const float ey = (Gxx * by - Gxy * bx) / det;
             vx += ex;
@@ -328,7 +232,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
     return true;
 }
 
-// Block b (one wave): slot b of the active list (sparse) or pixel b.
+// Block b (one wave): slot b of the active list (sparse) or pixel b, every selected interval.
 template <int PL>
 __global__ __launch_bounds__(kLkWave) void k_lk_window(LkWindowArgs a) {
     const int slot = blockIdx.x;
@@ -345,12 +249,34 @@ __global__ __launch_bounds__(kLkWave) void k_lk_window(LkWindowArgs a) {
         if (a.mask && !((a.mask[(int64_t)(i >> 5) * a.npix + p] >> (i & 31)) & 1u)) continue;
         float fx = 0.0f, fy = 0.0f;
         lk_point_wave<PL>(a.pyr + (uint64_t)i * a.lay.total,
-                          a.pyr + (uint64_t)(i + 1) * a.lay.total, a.lay, a.P, px, py, &fx, &fy,
-                          smem);
+                          a.pyr + (uint64_t)(i + 1) * a.lay.total, a.lay, a.P, px, py, &fx, &fy);
         if (threadIdx.x == 0) {
             float* out = a.flow + (int64_t)i * 2 * a.npix + 2 * (int64_t)p;
             out[0] = fx;
             out[1] = fy;
+        }
+    }
+}
+
+// Points j = block, block + grid, ...: one wave each.  An index outside the image is invalid
+// (flow 0) rather than read out of bounds.
+template <int PL>
+__global__ __launch_bounds__(kLkWave) void k_lk_points(const float* __restrict__ A,
+                                                       const float* __restrict__ B, PyrLayout L,
+                                                       LkParams P, const uint32_t* __restrict__ pts,
+                                                       uint64_t n, float* __restrict__ flow,
+                                                       uint8_t* __restrict__ valid) {
+    const uint32_t W = (uint32_t)L.w[0];
+    for (uint64_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const uint32_t p = pts[j];
+        const bool inside = (uint64_t)p < (uint64_t)W * (uint64_t)L.h[0];
+        const int py = inside ? (int)(p / W) : 0, px = inside ? (int)(p - (uint32_t)py * W) : 0;
+        float fx = 0.0f, fy = 0.0f;
+        const bool ok = inside && lk_point_wave<PL>(A, B, L, P, px, py, &fx, &fy);
+        if (threadIdx.x == 0) {
+            flow[2 * j] = fx;
+            flow[2 * j + 1] = fy;
+            if (valid) valid[j] = ok ? 1 : 0;
         }
     }
 }
@@ -377,9 +303,19 @@ hipError_t launch_lk_points(const float* a, const float* b, const PyrLayout& lay
                             const LkParams& P, const uint32_t* points, uint64_t n, float* flow,
                             uint8_t* valid, hipStream_t stream) {
     if (n == 0) return hipSuccess;
-    const uint64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_lk_points, dim3((unsigned)blocks), dim3(256), 0, stream, a, b, lay, P,
-                       points, n, flow, valid);
+    if (P.radius < 1 || (2 * P.radius + 1) * (2 * P.radius + 1) > kLkWave * kLkMaxPerLane)
+        return hipErrorInvalidValue;
+    const int n_win = (2 * P.radius + 1) * (2 * P.radius + 1);
+    const unsigned blocks = (unsigned)std::min<uint64_t>(n, 1u << 20);
+    if (n_win <= kLkWave * 4)
+        hipLaunchKernelGGL(k_lk_points<4>, dim3(blocks), dim3(kLkWave), 0, stream, a, b, lay, P,
+                           points, n, flow, valid);
+    else if (n_win <= kLkWave * 8)
+        hipLaunchKernelGGL(k_lk_points<8>, dim3(blocks), dim3(kLkWave), 0, stream, a, b, lay, P,
+                           points, n, flow, valid);
+    else
+        hipLaunchKernelGGL(k_lk_points<16>, dim3(blocks), dim3(kLkWave), 0, stream, a, b, lay, P,
+                           points, n, flow, valid);
     return hipGetLastError();
 }
 
@@ -388,13 +324,12 @@ hipError_t launch_lk_window(const LkWindowArgs& a, int max_slots, hipStream_t st
     if (a.P.radius < 1 || (2 * a.P.radius + 1) * (2 * a.P.radius + 1) > kLkWave * kLkMaxPerLane)
         return hipErrorInvalidValue;
     const int side = 2 * a.P.radius + 1, n = side * side;
-    const size_t lds = (size_t)(3 * n + 4) * sizeof(float);
     if (n <= kLkWave * 4)
-        hipLaunchKernelGGL(k_lk_window<4>, dim3(max_slots), dim3(kLkWave), lds, stream, a);
+        hipLaunchKernelGGL(k_lk_window<4>, dim3(max_slots), dim3(kLkWave), 0, stream, a);
     else if (n <= kLkWave * 8)
-        hipLaunchKernelGGL(k_lk_window<8>, dim3(max_slots), dim3(kLkWave), lds, stream, a);
+        hipLaunchKernelGGL(k_lk_window<8>, dim3(max_slots), dim3(kLkWave), 0, stream, a);
     else
-        hipLaunchKernelGGL(k_lk_window<16>, dim3(max_slots), dim3(kLkWave), lds, stream, a);
+        hipLaunchKernelGGL(k_lk_window<16>, dim3(max_slots), dim3(kLkWave), 0, stream, a);
     return hipGetLastError();
 }
 

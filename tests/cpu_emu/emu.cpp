@@ -273,6 +273,9 @@ uint64_t emu_wave_exchange(int op, uint64_t value, int arg, int line) {
     } else if (op == EMU_SHFL_UP) {
         const int src = lane - arg;
         r = (src >= 0 && w.present[src]) ? w.vals[src] : value;
+    } else if (op == EMU_SHFL_DOWN) {
+        const int src = lane + arg;
+        r = (src < 64 && w.present[src]) ? w.vals[src] : value;
     } else {
         for (int l = 0; l < 64; ++l)
             if (w.present[l] && w.vals[l]) r |= 1ull << l;

@@ -83,7 +83,7 @@ const dim3& emu_grid_dim();
 // ---- barriers and wave intrinsics (line numbers detect divergent use)
 void emu_syncthreads(int line);
 uint64_t emu_wave_exchange(int op, uint64_t value, int arg, int line);
-enum { EMU_SHFL = 0, EMU_SHFL_UP = 1, EMU_BALLOT = 2 };
+enum { EMU_SHFL = 0, EMU_SHFL_UP = 1, EMU_BALLOT = 2, EMU_SHFL_DOWN = 3 };
 
 #define __syncthreads() emu_syncthreads(__LINE__)
 
@@ -110,7 +110,13 @@ inline T emu_shfl_up(T v, unsigned delta, int width, int line) {
     (void)width;
     return emu_from_bits<T>(emu_wave_exchange(EMU_SHFL_UP, emu_to_bits(v), (int)delta, line));
 }
+template <class T>
+inline T emu_shfl_down(T v, unsigned delta, int width, int line) {
+    (void)width;
+    return emu_from_bits<T>(emu_wave_exchange(EMU_SHFL_DOWN, emu_to_bits(v), (int)delta, line));
+}
 #define __shfl(v, src, ...) emu_shfl((v), (src), 64, __LINE__)
+#define __shfl_down(v, d, ...) emu_shfl_down((v), (d), 64, __LINE__)
 #define __shfl_up(v, d, ...) emu_shfl_up((v), (d), 64, __LINE__)
 #define __ballot(p) ((unsigned long long)emu_wave_exchange(EMU_BALLOT, (p) ? 1 : 0, 0, __LINE__))
 #define __any(p) (__ballot(p) != 0ull ? 1 : 0)
