@@ -100,6 +100,93 @@ __device__ __forceinline__ float bil_tap(const Level& T, const Tap& t) {
     return t.gy * top + t.fy * bot;
 }
 
+// Wide reads of a tap's texels.  They read exactly the texels the one-texel forms above read (so
+// every sample is bit-identical) with fewer load instructions: a row's (x0, x1) pair in one 8-byte
+// read, the first frame's (x0 - 1 .. x0 + 2) run in one 16-byte read, where those texels are
+// adjacent inside the row (4-byte aligned, which multi-dword reads need); the clamped edge cases
+// read texel by texel.
+struct Pair {
+    float a, b;
+};
+struct Quad {
+    float a, b, c, d;
+};
+// Vector views of 2 and 4 adjacent texels at 4-byte alignment: one 8- or 16-byte read.
+typedef float TexelPair __attribute__((vector_size(8), aligned(4)));
+typedef float TexelQuad __attribute__((vector_size(16), aligned(4)));
+
+// (T(x0, y), T(x1, y)), x1 = min(x0 + 1, w - 1)
+__device__ __forceinline__ Pair row_pair(const Level& T, int x0, int x1, int y) {
+    const float* p = T.v + (int64_t)y * T.w + x0;
+    Pair r;
+    if (x1 > x0) {
+        const TexelPair v = *(const TexelPair*)p;
+        r.a = v[0];
+        r.b = v[1];
+    } else {
+        r.a = r.b = *p;
+    }
+    return r;
+}
+
+// (T(xm, y), T(x0, y), T(x1, y), T(x2, y)), xm = max(x0 - 1, 0), x2 = min(x1 + 1, w - 1)
+__device__ __forceinline__ Quad row_quad(const Level& T, int x0, int x1, int y) {
+    const float* row = T.v + (int64_t)y * T.w;
+    Quad r;
+    if (x0 >= 1 && x0 + 2 <= T.w - 1) {
+        const TexelQuad v = *(const TexelQuad*)(row + x0 - 1);
+        r.a = v[0];
+        r.b = v[1];
+        r.c = v[2];
+        r.d = v[3];
+    } else {
+        r.a = row[x0 >= 1 ? x0 - 1 : 0];
+        r.b = row[x0];
+        r.c = row[x1];
+        r.d = row[x1 + 1 <= T.w - 1 ? x1 + 1 : T.w - 1];
+    }
+    return r;
+}
+
+// bil_tap<0> of the second frame through row_pair
+__device__ __forceinline__ float bil0_wide(const Level& T, const Tap& t) {
+    const Pair r0 = row_pair(T, t.x0, t.x1, t.y0), r1 = row_pair(T, t.x0, t.x1, t.y1);
+    const float top = t.gx * r0.a + t.fx * r0.b;
+    const float bot = t.gx * r1.a + t.fx * r1.b;
+    return t.gy * top + t.fy * bot;
+}
+
+// bil_tap<0>, <1> and <2> of one tap from its 12 distinct texels: rows y0 and y1 at xm .. x2,
+// rows ym = max(y0 - 1, 0) and y2 = min(y1 + 1, h - 1) at x0 and x1.  A gradient texel at x1 takes
+// its left neighbour max(x1 - 1, 0): x0 when x1 = x0 + 1, else (right edge, x1 = x0) xm; likewise
+// for rows.
+__device__ __forceinline__ void bil_all_wide(const Level& T, const Tap& t, float* i0, float* ix,
+                                             float* iy) {
+    const Quad q0 = row_quad(T, t.x0, t.x1, t.y0), q1 = row_quad(T, t.x0, t.x1, t.y1);
+    const int ym = t.y0 >= 1 ? t.y0 - 1 : 0, y2 = t.y1 + 1 <= T.h - 1 ? t.y1 + 1 : T.h - 1;
+    const Pair pm = row_pair(T, t.x0, t.x1, ym), p2 = row_pair(T, t.x0, t.x1, y2);
+    const bool xs = t.x1 > t.x0, ys = t.y1 > t.y0;
+    const float gx00 = (q0.c - q0.a) * 0.5f, gx10 = (q0.d - (xs ? q0.b : q0.a)) * 0.5f;
+    const float gx01 = (q1.c - q1.a) * 0.5f, gx11 = (q1.d - (xs ? q1.b : q1.a)) * 0.5f;
+    const float gy00 = (q1.b - pm.a) * 0.5f, gy10 = (q1.c - pm.b) * 0.5f;
+    const float gy01 = (p2.a - (ys ? q0.b : pm.a)) * 0.5f, gy11 = (p2.b - (ys ? q0.c : pm.b)) * 0.5f;
+    {
+        const float top = t.gx * gx00 + t.fx * gx10;
+        const float bot = t.gx * gx01 + t.fx * gx11;
+        *ix = t.gy * top + t.fy * bot;
+    }
+    {
+        const float top = t.gx * gy00 + t.fx * gy10;
+        const float bot = t.gx * gy01 + t.fx * gy11;
+        *iy = t.gy * top + t.fy * bot;
+    }
+    {
+        const float top = t.gx * q0.b + t.fx * q0.c;
+        const float bot = t.gx * q1.b + t.fx * q1.c;
+        *i0 = t.gy * top + t.fy * bot;
+    }
+}
+
 // Level 0 of every frame: intensity as float.
 __global__ __launch_bounds__(256) void k_pyr_base(const uint8_t* __restrict__ first,
                                                   const uint8_t* __restrict__ rest,
@@ -182,9 +269,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
             if (q < n) {
                 const int dy = q / side - r, dx = q - (q / side) * side - r;
                 const Tap t = tap_at(I, ux + (float)dx, uy + (float)dy);
-                cix[j] = bil_tap<1>(I, t);
-                ciy[j] = bil_tap<2>(I, t);
-                ci0[j] = bil_tap<0>(I, t);
+                bil_all_wide(I, t, &ci0[j], &cix[j], &ciy[j]);
                 sxx += cix[j] * cix[j];
                 sxy += cix[j] * ciy[j];
                 syy += ciy[j] * ciy[j];
@@ -209,7 +294,7 @@ __device__ bool lk_point_wave(const float* A, const float* B, const PyrLayout& L
                     const int dy = q / side - r, dx = q - (q / side) * side - r;
                     const float x = ux + (float)dx, y = uy + (float)dy;
                     const Tap u = tap_at(J, x + (gx + vx), y + (gy + vy));
-                    const float d = ci0[j] - bil_tap<0>(J, u);
+                    const float d = ci0[j] - bil0_wide(J, u);
                     sbx += d * cix[j];
                     sby += d * ciy[j];
                 }
