@@ -161,6 +161,16 @@ def test_emulated_degenerate_shapes(emu_sim, shape):
         check(emu_sim, frames, flows, np.array([0, 900, 2100]), method=method, n_interp=4)
 
 
+@pytest.mark.parametrize("shape", [(300, 1), (40, 2), (2, 129)])
+def test_emulated_degenerate_shapes_gpu_cases(emu_sim, shape):
+    """The GPU suite's degenerate cases with the same seeds, flows and times."""
+    H, W = shape
+    rng = np.random.default_rng(H * 1000 + W)
+    frames, flows = synth.random_frames(rng, 3, H, W, flow_scale=2.0)
+    for method in (sim.BASIC, sim.DENSE, sim.SPARSE, sim.DIFFERENCE):
+        check(emu_sim, frames, flows, np.array([5, 1005, 3000]), method=method, n_interp=4)
+
+
 def test_emulated_batched_push_equals_streams_alone(emu_sim):
     """A batch mixing resolutions and methods gives each stream exactly its solo result, and
     pushing the batch twice continues every stream's state."""
