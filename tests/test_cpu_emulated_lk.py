@@ -165,6 +165,7 @@ ASAN_SCRIPT = textwrap.dedent("""
 """)
 
 
+@pytest.mark.long
 def test_emulated_lk_is_memory_safe_under_asan(tmp_path):
     """Pyramids down to 2x2 texels, windows larger than the image, indices out of range and
     overflow re-runs of estimated-flow windows under AddressSanitizer."""
